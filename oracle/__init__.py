@@ -1,0 +1,164 @@
+"""CPU oracle for the local semiring sparse product (test infrastructure).
+
+This package is the plain reference the GPU library is checked against.  Only
+``tests/``, the smoke check and the benchmark's CPU-baseline leg may import
+it.  It wraps ``oracle.cpp`` (row/column Gustavson with an ordered-map
+accumulator, paper Sec. 4.1) through ``ctypes``; it shares no code with the
+GPU library.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "oracle.cpp")
+LIB = os.path.join(HERE, "liboracle.so")
+
+# Semiring codes (an interface convention, restated here rather than shared).
+SEMIRINGS = {
+    "plus_times_f64": 0,
+    "plus_times_f32": 1,
+    "min_plus_i32": 2,
+    "min_plus_f32": 3,
+    "or_and_bool": 4,
+    "max_times_f64": 5,
+    "max_times_f32": 6,
+}
+# Input value dtype and oracle output dtype per semiring.
+IN_DTYPE = {0: np.float64, 1: np.float32, 2: np.int32, 3: np.float32, 4: np.uint8, 5: np.float64,
+            6: np.float32}
+OUT_DTYPE = {0: np.float64, 1: np.float64, 2: np.int32, 3: np.float32, 4: np.uint8, 5: np.float64,
+             6: np.float32}
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile ``oracle.cpp`` into ``liboracle.so`` with g++."""
+    if force or not os.path.exists(LIB):
+        tmp = LIB + ".tmp"
+        cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+               "-fPIC", "-shared", SRC, "-o", tmp]
+        subprocess.check_call(cmd)
+        os.replace(tmp, LIB)
+    return LIB
+
+
+def load(path: str):
+    """Open a compiled oracle library and declare its entry points."""
+    L = ctypes.CDLL(path)
+    vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+    L.orc_spgemm.restype = vp
+    L.orc_spgemm.argtypes = [i32, i32, i64, vp, vp, vp, vp, vp, vp, vp, i32]
+    L.orc_nnz.restype = i64
+    L.orc_nnz.argtypes = [vp]
+    L.orc_elem_bytes.restype = i32
+    L.orc_elem_bytes.argtypes = [vp]
+    L.orc_copy.restype = None
+    L.orc_copy.argtypes = [vp, vp, vp, vp]
+    L.orc_free.restype = None
+    L.orc_free.argtypes = [vp]
+    L.orc_flops.restype = None
+    L.orc_flops.argtypes = [i32, i64, vp, vp, vp, vp, vp, vp]
+    L.orc_prune_f32.restype = i64
+    L.orc_prune_f32.argtypes = [i64, vp, vp, vp, ctypes.c_float, vp, vp, vp]
+    return L
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+            build()
+        _lib = load(LIB)
+    return _lib
+
+
+def _p(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _code(semiring) -> int:
+    return SEMIRINGS[semiring] if isinstance(semiring, str) else int(semiring)
+
+
+def _arrays(M, code: int, name: str):
+    ptr = np.ascontiguousarray(M.ptr, dtype=np.int64)
+    idx = np.ascontiguousarray(M.idx, dtype=np.int32)
+    val = None
+    if M.val is not None:
+        val = np.ascontiguousarray(M.val, dtype=IN_DTYPE[code])
+    elif code != 4:
+        raise ValueError(f"{name}: values are required for semiring {code}")
+    return ptr, idx, val
+
+
+def spgemm(A, B, semiring, select: Optional[Sequence[int]] = None,
+           nthreads: int = 0, _lib=None) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """C = A (x).(+) B for the slices ``select`` (rows for CSR, columns for
+    CSC; all when None).  A and B are ``spgen.SparseMatrix`` of one layout.
+    Returns (ptr, idx, val) of the selected slices, packed in order."""
+    code = _code(semiring)
+    if A.layout != B.layout:
+        raise ValueError("A and B must share a layout")
+    if A.ncols != B.nrows:
+        raise ValueError("inner dimensions differ")
+    layout = 0 if A.layout == "csr" else 1
+    nslices = A.nrows if layout == 0 else B.ncols
+    Ap, Ai, Av = _arrays(A, code, "A")
+    Bp, Bi, Bv = _arrays(B, code, "B")
+    sel = None
+    if select is not None:
+        sel = np.ascontiguousarray(select, dtype=np.int64)
+        nsel = sel.size
+    else:
+        nsel = nslices
+    L = _lib or lib()
+    h = L.orc_spgemm(code, layout, nsel, _p(sel), _p(Ap), _p(Ai), _p(Av), _p(Bp), _p(Bi), _p(Bv),
+                     int(nthreads))
+    if not h:
+        raise ValueError(f"unknown semiring {semiring}")
+    try:
+        nnz = L.orc_nnz(h)
+        ptr = np.empty(nsel + 1, np.int64)
+        idx = np.empty(nnz, np.int32)
+        val = np.empty(nnz, OUT_DTYPE[code])
+        L.orc_copy(h, _p(ptr), _p(idx), _p(val))
+    finally:
+        L.orc_free(h)
+    return ptr, idx, val
+
+
+def flops(A, B, select: Optional[Sequence[int]] = None) -> np.ndarray:
+    """Number of (x) operations per output slice."""
+    layout = 0 if A.layout == "csr" else 1
+    nslices = A.nrows if layout == 0 else B.ncols
+    sel = None if select is None else np.ascontiguousarray(select, dtype=np.int64)
+    nsel = nslices if sel is None else sel.size
+    out = np.empty(nsel, np.int64)
+    Ap = np.ascontiguousarray(A.ptr, np.int64)
+    Ai = np.ascontiguousarray(A.idx, np.int32)
+    Bp = np.ascontiguousarray(B.ptr, np.int64)
+    Bi = np.ascontiguousarray(B.idx, np.int32)
+    lib().orc_flops(layout, nsel, _p(sel), _p(Ap), _p(Ai), _p(Bp), _p(Bi), _p(out))
+    return out
+
+
+def prune_f32(ptr: np.ndarray, idx: np.ndarray, val: np.ndarray, thresh: float):
+    """Keep entries with value >= thresh.  Returns (ptr, idx, val)."""
+    ptr = np.ascontiguousarray(ptr, np.int64)
+    idx = np.ascontiguousarray(idx, np.int32)
+    val = np.ascontiguousarray(val, np.float32)
+    nmajor = ptr.size - 1
+    L = lib()
+    nnz = L.orc_prune_f32(nmajor, _p(ptr), _p(idx), _p(val), float(thresh), None, None, None)
+    nptr = np.empty(nmajor + 1, np.int64)
+    nidx = np.empty(nnz, np.int32)
+    nval = np.empty(nnz, np.float32)
+    L.orc_prune_f32(nmajor, _p(ptr), _p(idx), _p(val), float(thresh), _p(nptr), _p(nidx), _p(nval))
+    return nptr, nidx, nval
