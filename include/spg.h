@@ -1,0 +1,180 @@
+/* spg.h -- local semiring sparse-times-sparse product C = A (x).(+) B on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The operation (paper Sec. 3.1): C = AB with A in S^{m x n}, B in S^{n x k}
+ * over a semiring S (Sec. 1: user-defined semirings over several value types;
+ * Sec. 2: compressed column / row storage with compact local indices):
+ *
+ *     C(i,j) = (+)_{k : A(i,k) and B(k,j) stored}  A(i,k) (x) B(k,j)
+ *
+ * The pattern of C is structural: an entry is stored whenever at least one
+ * product contributes to it, even if its value equals the additive identity.
+ * Output slices (rows for CSR, columns for CSC) are sorted ascending.
+ *
+ * Like the paper's node-level product (Sec. 4.1: flop estimation, a symbolic
+ * phase that sizes C, then a numeric phase), a product is two calls:
+ * spg_symbolic() computes the offsets of C and its entry count, the caller
+ * allocates C, and spg_numeric() fills it.
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ * - Device pointers are HIP device addresses (e.g. torch tensor data
+ *   pointers); host pointers are ordinary memory.  Every device buffer is
+ *   owned by the caller; the library never allocates or frees device memory.
+ *   Temporary device memory comes from the caller's workspace.  The only
+ *   library-owned objects are the small host-side plans.
+ * - All device work is enqueued on the stream given at plan creation (a
+ *   hipStream_t passed as void*; NULL is the default stream).  A call that
+ *   returns a value on the host synchronises that stream before returning.
+ * - Errors are reported as spg_status codes; nothing aborts or throws across
+ *   this interface.  Asynchronous device faults surface as SPG_E_DEVICE at
+ *   the next synchronising call.
+ * - Plans are not thread-safe; use one plan per thread and stream.
+ */
+#ifndef SPG_H_
+#define SPG_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum spg_status {
+  SPG_OK = 0,
+  SPG_E_INVALID = 1,   /* bad argument: NULL pointer, malformed matrix */
+  SPG_E_SHAPE = 2,     /* inner dimensions differ, or a dimension < 0 */
+  SPG_E_LAYOUT = 3,    /* unknown layout, or A and B in different layouts */
+  SPG_E_SEMIRING = 4,  /* unknown semiring code, or values missing */
+  SPG_E_NOMEM = 5,     /* workspace too small, or a request over budget */
+  SPG_E_OVERFLOW = 6,  /* a count or index exceeds its integer type */
+  SPG_E_DEVICE = 7,    /* a HIP runtime call or kernel failed */
+  SPG_E_STATE = 8      /* calls out of order (create -> symbolic -> numeric) */
+} spg_status;
+
+/* Semiring codes: ((+), (x), value type).  The (+)-identity is never stored.
+ *  SPG_PLUS_TIMES_F64  (+, x) float64
+ *  SPG_PLUS_TIMES_F32  (+, x) float32 with float32 accumulation
+ *  SPG_MIN_PLUS_I32    (min, +) int32; + is saturating (int64 sum clamped to
+ *                      the int32 range), so INT32_MAX acts as +infinity
+ *  SPG_MIN_PLUS_F32    (min, +) float32
+ *  SPG_OR_AND_BOOL     (OR, AND) uint8 values in {0,1}; values may be NULL,
+ *                      meaning every stored entry is true (pattern only)
+ *  SPG_MAX_TIMES_F64   (max, x) float64
+ *  SPG_MAX_TIMES_F32   (max, x) float32
+ * min and max on floating point use the total order in which -0 < +0, so
+ * those results do not depend on summation order.  (+, x) results do, in the
+ * last bits: the accumulation order on the device is unspecified. */
+typedef enum spg_semiring {
+  SPG_PLUS_TIMES_F64 = 0,
+  SPG_PLUS_TIMES_F32 = 1,
+  SPG_MIN_PLUS_I32 = 2,
+  SPG_MIN_PLUS_F32 = 3,
+  SPG_OR_AND_BOOL = 4,
+  SPG_MAX_TIMES_F64 = 5,
+  SPG_MAX_TIMES_F32 = 6
+} spg_semiring;
+
+typedef enum spg_layout { SPG_CSR = 0, SPG_CSC = 1 } spg_layout;
+
+/* A compressed sparse matrix held in device memory.
+ *  CSR: ptr has nrows+1 entries, idx holds column ids of each row.
+ *  CSC: ptr has ncols+1 entries, idx holds row ids of each column.
+ * ptr[0] == 0, ptr is non-decreasing and ptr[last] == nnz.  Within a slice
+ * the ids are strictly ascending (sorted, no duplicates).  val holds nnz
+ * values of the semiring's value type (double, float, int32_t or uint8_t),
+ * or NULL for SPG_OR_AND_BOOL (all true).  The library only reads them. */
+typedef struct spg_matrix {
+  int32_t nrows;
+  int32_t ncols;
+  int64_t nnz;
+  spg_layout layout;
+  const int64_t* ptr;
+  const int32_t* idx;
+  const void* val;
+} spg_matrix;
+
+/* Tuning knobs; a zero field takes its default.  Bins follow the paper's
+ * per-slice choice of accumulator by expected output size (Sec. 4.1, hybrid
+ * hash/heap by compression ratio). */
+typedef struct spg_options {
+  int32_t validate;        /* 1: check both operands on the device first;
+                              a malformed operand gives SPG_E_INVALID */
+  int32_t hash_max_flops;  /* symbolic: rows with more products than this use
+                              the dense bitmap accumulator (default 8192) */
+  int32_t hash_max_nnz;    /* numeric: rows with more output entries than this
+                              use the dense panel accumulator (default 4096) */
+  int32_t short_seg;       /* B-row segments up to this length are walked by
+                              one lane; longer ones are split across the
+                              waves of a workgroup (default 32) */
+  int32_t dense_threads;   /* workgroup size of the dense kernels (default 1024) */
+  int32_t sym_panel_log2;  /* log2 of the dense symbolic bitmap width in
+                              columns (default 20, i.e. 128 KiB) */
+  int32_t lds_budget;      /* bytes of LDS a dense numeric workgroup may use for
+                              its panel (default 131072) */
+  int32_t reserved[9];
+} spg_options;
+
+typedef struct spg_plan spg_plan;
+
+/* Creates a plan for C = A (x).(+) B.  Host-only: checks the descriptors
+ * (non-NULL arrays, matching inner dimension, one shared layout, semiring
+ * code, values present unless SPG_OR_AND_BOOL) and records the stream; it
+ * launches nothing.  A and B must stay valid until the plan is destroyed.
+ * CSC operands give a CSC result, computed through (AB)^T = B^T A^T on the
+ * same arrays.  opt may be NULL.  *out receives the plan. */
+spg_status spg_plan_create(const spg_matrix* A, const spg_matrix* B, spg_semiring sr,
+                           const spg_options* opt, void* stream, spg_plan** out);
+
+/* Bytes of device workspace the plan needs (256-byte aligned base).  The same
+ * workspace must be passed, untouched, to spg_symbolic and spg_numeric. */
+spg_status spg_workspace_size(const spg_plan* plan, size_t* bytes);
+
+/* Symbolic phase (paper Sec. 4.1 phases 1-2): per-slice flop count and
+ * binning, optional validation, the pattern size of every output slice, and
+ * the exclusive scan into c_ptr.
+ *   ws     device workspace of spg_workspace_size() bytes
+ *   c_ptr  device, int64[nslices+1] (nslices = rows of C for CSR, columns of
+ *          C for CSC), written
+ *   c_nnz  host, receives nnz(C)
+ * Synchronises the stream. */
+spg_status spg_symbolic(spg_plan* plan, void* ws, int64_t* c_ptr, int64_t* c_nnz);
+
+/* Numeric phase (paper Sec. 4.1 phase 3): fills C's ids (sorted within each
+ * slice) and values.  Call after spg_symbolic with the same workspace and
+ * c_ptr.
+ *   c_idx  device, int32[nnz(C)]
+ *   c_val  device, nnz(C) values of the output type (double, float, int32_t,
+ *          uint8_t per semiring); may be NULL only for SPG_OR_AND_BOOL with
+ *          pattern-only operands.
+ * Asynchronous: returns once the work is enqueued. */
+spg_status spg_numeric(spg_plan* plan, void* ws, int32_t* c_idx, void* c_val);
+
+/* Statistics of the last symbolic phase (host): total products (flops, the
+ * paper's count of nonzero multiplications) and number of output slices. */
+spg_status spg_plan_stats(const spg_plan* plan, int64_t* flops, int64_t* nslices);
+
+spg_status spg_plan_destroy(spg_plan* plan);
+
+const char* spg_status_str(spg_status s);
+
+/* Pruning of a float32 matrix (the Markov-clustering step after expansion):
+ * keep entries with value >= thresh, drop the rest, order unchanged.  Two
+ * phases like the product.
+ *   C          float32 matrix in device memory (either layout)
+ *   ws         device workspace of at least spg_prune_workspace_size() bytes
+ *   new_ptr    device int64[nslices+1], written by the count phase
+ *   new_nnz    host, receives the kept count (synchronises the stream)
+ *   new_idx/new_val  device outputs of new_nnz entries */
+spg_status spg_prune_workspace_size(const spg_matrix* C, size_t* bytes);
+spg_status spg_prune_count_f32(const spg_matrix* C, float thresh, void* ws, void* stream,
+                               int64_t* new_ptr, int64_t* new_nnz);
+spg_status spg_prune_apply_f32(const spg_matrix* C, float thresh, void* ws, void* stream,
+                               const int64_t* new_ptr, int32_t* new_idx, float* new_val);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPG_H_ */

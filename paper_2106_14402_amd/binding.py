@@ -1,0 +1,213 @@
+"""ctypes binding of libspg (include/spg.h), argument marshalling only.
+
+Every function keeps its C name.  Device buffers are torch tensors on a ROCm
+device; their data pointers cross the boundary as plain addresses, and the
+stream is the raw hipStream_t of a torch stream.  Nothing here computes any
+part of the product: when the library is missing, loading raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libspg.so")
+
+SPG_CSR, SPG_CSC = 0, 1
+SEMIRINGS = {
+    "plus_times_f64": 0,
+    "plus_times_f32": 1,
+    "min_plus_i32": 2,
+    "min_plus_f32": 3,
+    "or_and_bool": 4,
+    "max_times_f64": 5,
+    "max_times_f32": 6,
+}
+STATUS = {
+    0: "SPG_OK", 1: "SPG_E_INVALID", 2: "SPG_E_SHAPE", 3: "SPG_E_LAYOUT", 4: "SPG_E_SEMIRING",
+    5: "SPG_E_NOMEM", 6: "SPG_E_OVERFLOW", 7: "SPG_E_DEVICE", 8: "SPG_E_STATE",
+}
+
+
+class SpgError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {STATUS.get(status, status)} ({spg_status_str(status)})")
+
+
+class spg_matrix(ctypes.Structure):
+    _fields_ = [
+        ("nrows", ctypes.c_int32),
+        ("ncols", ctypes.c_int32),
+        ("nnz", ctypes.c_int64),
+        ("layout", ctypes.c_int),
+        ("ptr", ctypes.c_void_p),
+        ("idx", ctypes.c_void_p),
+        ("val", ctypes.c_void_p),
+    ]
+
+
+class spg_options(ctypes.Structure):
+    _fields_ = [
+        ("validate", ctypes.c_int32),
+        ("hash_max_flops", ctypes.c_int32),
+        ("hash_max_nnz", ctypes.c_int32),
+        ("short_seg", ctypes.c_int32),
+        ("dense_threads", ctypes.c_int32),
+        ("sym_panel_log2", ctypes.c_int32),
+        ("lds_budget", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 9),
+    ]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Open libspg.so and declare its entry points."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with paper_2106_14402_amd.build.build()")
+    L = ctypes.CDLL(path)
+    vp, i64, st = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+    pm = ctypes.POINTER(spg_matrix)
+    po = ctypes.POINTER(spg_options)
+    L.spg_status_str.restype = ctypes.c_char_p
+    L.spg_status_str.argtypes = [st]
+    L.spg_plan_create.restype = st
+    L.spg_plan_create.argtypes = [pm, pm, ctypes.c_int, po, vp, ctypes.POINTER(vp)]
+    L.spg_workspace_size.restype = st
+    L.spg_workspace_size.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+    L.spg_symbolic.restype = st
+    L.spg_symbolic.argtypes = [vp, vp, vp, ctypes.POINTER(i64)]
+    L.spg_numeric.restype = st
+    L.spg_numeric.argtypes = [vp, vp, vp, vp]
+    L.spg_plan_stats.restype = st
+    L.spg_plan_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    L.spg_plan_destroy.restype = st
+    L.spg_plan_destroy.argtypes = [vp]
+    L.spg_prune_workspace_size.restype = st
+    L.spg_prune_workspace_size.argtypes = [pm, ctypes.POINTER(ctypes.c_size_t)]
+    L.spg_prune_count_f32.restype = st
+    L.spg_prune_count_f32.argtypes = [pm, ctypes.c_float, vp, vp, vp, ctypes.POINTER(i64)]
+    L.spg_prune_apply_f32.restype = st
+    L.spg_prune_apply_f32.argtypes = [pm, ctypes.c_float, vp, vp, vp, vp, vp]
+    _declare_batch(L)
+    _lib = L
+    return L
+
+
+def _declare_batch(L):
+    """Declare the batched entry points when the library has them."""
+    if not hasattr(L, "spg_batch_plan_create"):
+        return
+    vp, i64, st = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+    pm = ctypes.POINTER(spg_matrix)
+    po = ctypes.POINTER(spg_options)
+    L.spg_batch_plan_create.restype = st
+    L.spg_batch_plan_create.argtypes = [ctypes.c_int, pm, pm, ctypes.POINTER(ctypes.c_int), po, vp,
+                                        ctypes.POINTER(vp)]
+    L.spg_batch_workspace_size.restype = st
+    L.spg_batch_workspace_size.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+    L.spg_batch_symbolic.restype = st
+    L.spg_batch_symbolic.argtypes = [vp, vp, vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    L.spg_batch_numeric.restype = st
+    L.spg_batch_numeric.argtypes = [vp, vp, vp, vp, ctypes.POINTER(i64)]
+    L.spg_batch_plan_destroy.restype = st
+    L.spg_batch_plan_destroy.argtypes = [vp]
+
+
+def _check(status: int, where: str):
+    if status != 0:
+        raise SpgError(status, where)
+
+
+def _addr(t) -> Optional[int]:
+    if t is None:
+        return None
+    p = t.data_ptr()
+    return p if p else None
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return getattr(stream, "cuda_stream", stream) or None
+
+
+def make_matrix(nrows: int, ncols: int, layout: int, ptr, idx, val) -> spg_matrix:
+    """Descriptor of device arrays (torch tensors); val may be None."""
+    nnz = int(idx.numel()) if idx is not None else 0
+    return spg_matrix(int(nrows), int(ncols), nnz, int(layout), _addr(ptr), _addr(idx), _addr(val))
+
+
+def make_options(**kw) -> spg_options:
+    o = spg_options()
+    for k, v in kw.items():
+        setattr(o, k, int(v))
+    return o
+
+
+# ---- the C entry points, one Python function each --------------------------
+def spg_status_str(status: int) -> str:
+    return load().spg_status_str(int(status)).decode()
+
+
+def spg_plan_create(A: spg_matrix, B: spg_matrix, semiring, options: Optional[spg_options] = None,
+                    stream=None) -> ctypes.c_void_p:
+    code = SEMIRINGS[semiring] if isinstance(semiring, str) else int(semiring)
+    plan = ctypes.c_void_p()
+    _check(load().spg_plan_create(ctypes.byref(A), ctypes.byref(B), code,
+                                  ctypes.byref(options) if options is not None else None,
+                                  _stream(stream), ctypes.byref(plan)), "spg_plan_create")
+    return plan
+
+
+def spg_workspace_size(plan) -> int:
+    n = ctypes.c_size_t()
+    _check(load().spg_workspace_size(plan, ctypes.byref(n)), "spg_workspace_size")
+    return int(n.value)
+
+
+def spg_symbolic(plan, ws, c_ptr) -> int:
+    nnz = ctypes.c_int64()
+    _check(load().spg_symbolic(plan, _addr(ws), _addr(c_ptr), ctypes.byref(nnz)), "spg_symbolic")
+    return int(nnz.value)
+
+
+def spg_numeric(plan, ws, c_idx, c_val) -> None:
+    _check(load().spg_numeric(plan, _addr(ws), _addr(c_idx), _addr(c_val)), "spg_numeric")
+
+
+def spg_plan_stats(plan):
+    f, n = ctypes.c_int64(), ctypes.c_int64()
+    _check(load().spg_plan_stats(plan, ctypes.byref(f), ctypes.byref(n)), "spg_plan_stats")
+    return int(f.value), int(n.value)
+
+
+def spg_plan_destroy(plan) -> None:
+    if plan:
+        load().spg_plan_destroy(plan)
+
+
+def spg_prune_workspace_size(C: spg_matrix) -> int:
+    n = ctypes.c_size_t()
+    _check(load().spg_prune_workspace_size(ctypes.byref(C), ctypes.byref(n)), "spg_prune_workspace_size")
+    return int(n.value)
+
+
+def spg_prune_count_f32(C: spg_matrix, thresh: float, ws, new_ptr, stream=None) -> int:
+    nnz = ctypes.c_int64()
+    _check(load().spg_prune_count_f32(ctypes.byref(C), float(thresh), _addr(ws), _stream(stream),
+                                      _addr(new_ptr), ctypes.byref(nnz)), "spg_prune_count_f32")
+    return int(nnz.value)
+
+
+def spg_prune_apply_f32(C: spg_matrix, thresh: float, ws, new_ptr, new_idx, new_val, stream=None) -> None:
+    _check(load().spg_prune_apply_f32(ctypes.byref(C), float(thresh), _addr(ws), _stream(stream),
+                                      _addr(new_ptr), _addr(new_idx), _addr(new_val)),
+           "spg_prune_apply_f32")

@@ -1,0 +1,375 @@
+// Host side of the C ABI in include/spg.h: descriptor checks, plan state,
+// workspace layout, and the launch sequence of the symbolic and numeric
+// phases (paper Sec. 4.1: flop estimate, symbolic, numeric).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+
+#include "../../include/spg.h"
+#include "spg_launch.h"
+
+using namespace spg;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+enum PlanState { kCreated = 0, kSymbolicDone = 1 };
+
+}  // namespace
+
+struct spg_plan {
+  Operands op;       // oriented CSR problem
+  int sr;            // kernel semiring code (0..6, 7 = pattern-only boolean)
+  int user_sr;
+  bool csc;
+  hipStream_t stream;
+  spg_options opt;
+  BinParams bp;
+  int sym_wlog2, sym_P, num_wlog2, num_P;
+  // workspace layout (byte offsets)
+  size_t off_ctr, off_flops, off_rows_sym, off_rows_num, off_scan, off_psym, off_pnum, ws_bytes;
+  int64_t a_nnz, b_nnz;  // entries of the oriented operands
+  int state;
+  int64_t flops_total;
+  int64_t c_nnz;
+  int64_t* c_ptr;
+  unsigned long long sym_counts[kNumBins];
+  unsigned long long num_counts[kNumBins];
+};
+
+namespace {
+
+// Counter block inside the workspace (uint64 words).
+constexpr int kCtrSym = 0;                 // [64] symbolic bin counts
+constexpr int kCtrNum = kNumBins;          // [64] numeric bin counts
+constexpr int kCtrCursor = 2 * kNumBins;   // [64] scatter cursors
+constexpr int kCtrMisc = 3 * kNumBins;     // [0] total flops, [1] validation error bits
+constexpr int kCtrWords = 4 * kNumBins;
+
+spg_status from_hip(hipError_t e) { return e == hipSuccess ? SPG_OK : SPG_E_DEVICE; }
+
+#define SPG_TRY_HIP(expr)                      \
+  do {                                         \
+    hipError_t e_ = (expr);                    \
+    if (e_ != hipSuccess) return SPG_E_DEVICE; \
+  } while (0)
+
+bool valid_semiring(int sr) { return sr >= 0 && sr <= 6; }
+
+spg_status check_matrix(const spg_matrix* M) {
+  if (!M) return SPG_E_INVALID;
+  if (M->nrows < 0 || M->ncols < 0 || M->nnz < 0) return SPG_E_SHAPE;
+  if (M->layout != SPG_CSR && M->layout != SPG_CSC) return SPG_E_LAYOUT;
+  if (!M->ptr) return SPG_E_INVALID;
+  if (M->nnz > 0 && !M->idx) return SPG_E_INVALID;
+  return SPG_OK;
+}
+
+int ilog2_ceil(int64_t x) { return ceil_log2_u64(static_cast<uint64_t>(x < 1 ? 1 : x)); }
+
+void resolve_options(const spg_options* in, spg_options* o) {
+  std::memset(o, 0, sizeof(*o));
+  if (in) *o = *in;
+  if (o->hash_max_flops <= 0) o->hash_max_flops = 8192;
+  if (o->hash_max_nnz <= 0) o->hash_max_nnz = 4096;
+  if (o->short_seg <= 0) o->short_seg = 32;
+  if (o->dense_threads <= 0) o->dense_threads = 1024;
+  if (o->sym_panel_log2 <= 0) o->sym_panel_log2 = 20;
+  if (o->lds_budget <= 0) o->lds_budget = 131072;
+}
+
+spg_status check_options(const spg_options& o, int sr) {
+  if (o.hash_max_flops > 16384 || o.hash_max_flops < 32) return SPG_E_INVALID;
+  if (o.hash_max_nnz < 32) return SPG_E_INVALID;
+  if (o.dense_threads % kWave != 0 || o.dense_threads > 1024) return SPG_E_INVALID;
+  if (o.sym_panel_log2 < 7 || o.sym_panel_log2 > 20) return SPG_E_INVALID;
+  // hash tables must fit in LDS
+  const int csym = hash_class(o.hash_max_flops);
+  if (hash_sym_lds(hash_table_size(csym), hash_threads(csym)) > static_cast<size_t>(max_lds_bytes()))
+    return SPG_E_INVALID;
+  const int cnum = hash_class(o.hash_max_nnz);
+  if (hash_num_lds(sr, hash_table_size(cnum), hash_threads(cnum)) > static_cast<size_t>(max_lds_bytes()))
+    return SPG_E_INVALID;
+  return SPG_OK;
+}
+
+// Offsets of bins in the row lists: bins 1..63 in ascending order.
+BinOffsets offsets_of(const unsigned long long* counts) {
+  BinOffsets o;
+  int64_t run = 0;
+  o.v[0] = 0;
+  for (int b = 1; b < kNumBins; ++b) {
+    o.v[b] = run;
+    run += static_cast<int64_t>(counts[b]);
+  }
+  return o;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* spg_status_str(spg_status s) {
+  switch (s) {
+    case SPG_OK: return "ok";
+    case SPG_E_INVALID: return "invalid argument or malformed matrix";
+    case SPG_E_SHAPE: return "shape mismatch";
+    case SPG_E_LAYOUT: return "bad or mixed layout";
+    case SPG_E_SEMIRING: return "unknown semiring or missing values";
+    case SPG_E_NOMEM: return "workspace too small or over budget";
+    case SPG_E_OVERFLOW: return "integer overflow";
+    case SPG_E_DEVICE: return "HIP device error";
+    case SPG_E_STATE: return "call out of order";
+  }
+  return "unknown status";
+}
+
+spg_status spg_plan_create(const spg_matrix* A, const spg_matrix* B, spg_semiring sr_in,
+                           const spg_options* opt_in, void* stream, spg_plan** out) {
+  if (!out) return SPG_E_INVALID;
+  *out = nullptr;
+  spg_status st;
+  if ((st = check_matrix(A)) != SPG_OK) return st;
+  if ((st = check_matrix(B)) != SPG_OK) return st;
+  const int sr = static_cast<int>(sr_in);
+  if (!valid_semiring(sr)) return SPG_E_SEMIRING;
+  if (A->layout != B->layout) return SPG_E_LAYOUT;
+  if (A->ncols != B->nrows) return SPG_E_SHAPE;
+  const bool bool_sr = sr == SPG_OR_AND_BOOL;
+  if (!bool_sr && ((A->nnz > 0 && !A->val) || (B->nnz > 0 && !B->val))) return SPG_E_SEMIRING;
+
+  auto* p = new (std::nothrow) spg_plan();
+  if (!p) return SPG_E_NOMEM;
+  p->user_sr = sr;
+  p->csc = A->layout == SPG_CSC;
+  p->stream = static_cast<hipStream_t>(stream);
+  // Orientation.  CSR: C = A B row by row.  CSC: the arrays of a CSC matrix
+  // are the CSR arrays of its transpose, and C^T = B^T A^T, so the CSR kernel
+  // runs on (B^T, A^T).  Every listed multiplication is commutative, so the
+  // operand swap needs no change to (x).
+  const spg_matrix* L = p->csc ? B : A;
+  const spg_matrix* R = p->csc ? A : B;
+  p->op.a_ptr = L->ptr;
+  p->op.a_idx = L->idx;
+  p->op.a_val = L->val;
+  p->op.b_ptr = R->ptr;
+  p->op.b_idx = R->idx;
+  p->op.b_val = R->val;
+  p->a_nnz = L->nnz;
+  p->b_nnz = R->nnz;
+  p->op.m = p->csc ? B->ncols : A->nrows;
+  p->op.n = A->ncols;
+  p->op.k = p->csc ? A->nrows : B->ncols;
+  p->sr = (bool_sr && !A->val && !B->val) ? 7 : sr;
+
+  resolve_options(opt_in, &p->opt);
+  if ((st = check_options(p->opt, p->sr)) != SPG_OK) {
+    delete p;
+    return st;
+  }
+  p->bp.hash_max_flops = p->opt.hash_max_flops;
+  p->bp.hash_max_nnz = p->opt.hash_max_nnz;
+
+  // Dense panels.  Symbolic: a bitmap of 2^sym_panel_log2 columns.  Numeric:
+  // presence bits plus one accumulator value per column, as wide as the LDS
+  // budget allows (bits only for the pattern-only product).
+  const int kbits = std::max(7, ilog2_ceil(p->op.k));
+  p->sym_wlog2 = std::min(p->opt.sym_panel_log2, kbits);
+  const size_t sb = storage_bytes(p->sr);
+  int wl = p->opt.sym_panel_log2;
+  if (sb > 0) {
+    wl = 7;
+    while (wl < 24 && (static_cast<size_t>(1) << (wl + 1)) * sb <= static_cast<size_t>(p->opt.lds_budget))
+      ++wl;
+  }
+  p->num_wlog2 = std::min(wl, kbits);
+  const int nt = p->opt.dense_threads;
+  while (p->num_wlog2 > 7 && dense_num_lds(p->sr, p->num_wlog2, nt) > static_cast<size_t>(max_lds_bytes()))
+    --p->num_wlog2;
+  while (p->sym_wlog2 > 7 && dense_sym_lds(p->sym_wlog2, nt) > static_cast<size_t>(max_lds_bytes()))
+    --p->sym_wlog2;
+  const int64_t kk = std::max<int64_t>(1, p->op.k);
+  p->sym_P = static_cast<int>((kk + (int64_t(1) << p->sym_wlog2) - 1) >> p->sym_wlog2);
+  p->num_P = static_cast<int>((kk + (int64_t(1) << p->num_wlog2) - 1) >> p->num_wlog2);
+
+  // Workspace layout.
+  const int64_t m = p->op.m;
+  const int64_t nB = p->op.n;
+  size_t off = 0;
+  p->off_ctr = off;
+  off = align_up(off + kCtrWords * sizeof(uint64_t));
+  p->off_flops = off;
+  off = align_up(off + static_cast<size_t>(m) * sizeof(int64_t));
+  p->off_rows_sym = off;
+  off = align_up(off + static_cast<size_t>(m) * sizeof(int32_t));
+  p->off_rows_num = off;
+  off = align_up(off + static_cast<size_t>(m) * sizeof(int32_t));
+  p->off_scan = off;
+  off = align_up(off + static_cast<size_t>((m + kScanTile - 1) / kScanTile + 1) * sizeof(int64_t));
+  p->off_psym = off;
+  if (p->sym_P > 1) off = align_up(off + static_cast<size_t>(nB) * (p->sym_P + 1) * sizeof(int32_t));
+  p->off_pnum = off;
+  if (p->num_P > 1) off = align_up(off + static_cast<size_t>(nB) * (p->num_P + 1) * sizeof(int32_t));
+  p->ws_bytes = off;
+  p->state = kCreated;
+  p->c_ptr = nullptr;
+  *out = p;
+  return SPG_OK;
+}
+
+spg_status spg_workspace_size(const spg_plan* p, size_t* bytes) {
+  if (!p || !bytes) return SPG_E_INVALID;
+  *bytes = p->ws_bytes;
+  return SPG_OK;
+}
+
+spg_status spg_plan_stats(const spg_plan* p, int64_t* flops, int64_t* nslices) {
+  if (!p) return SPG_E_INVALID;
+  if (p->state < kSymbolicDone) return SPG_E_STATE;
+  if (flops) *flops = p->flops_total;
+  if (nslices) *nslices = p->op.m;
+  return SPG_OK;
+}
+
+spg_status spg_plan_destroy(spg_plan* p) {
+  delete p;
+  return SPG_OK;
+}
+
+spg_status spg_symbolic(spg_plan* p, void* ws, int64_t* c_ptr, int64_t* c_nnz) {
+  if (!p || !c_ptr || !c_nnz) return SPG_E_INVALID;
+  if (!ws && p->ws_bytes > 0) return SPG_E_NOMEM;
+  if (reinterpret_cast<uintptr_t>(ws) % kAlign != 0) return SPG_E_INVALID;
+  hipStream_t s = p->stream;
+  unsigned char* w = static_cast<unsigned char*>(ws);
+  auto* ctr = reinterpret_cast<unsigned long long*>(w + p->off_ctr);
+  auto* flops = reinterpret_cast<int64_t*>(w + p->off_flops);
+  auto* rows_sym = reinterpret_cast<int32_t*>(w + p->off_rows_sym);
+  auto* rows_num = reinterpret_cast<int32_t*>(w + p->off_rows_num);
+  auto* scan = reinterpret_cast<int64_t*>(w + p->off_scan);
+  auto* psym = reinterpret_cast<int32_t*>(w + p->off_psym);
+  const Operands& op = p->op;
+  const int32_t m = op.m;
+
+  SPG_TRY_HIP(launch_fill_u64(reinterpret_cast<uint64_t*>(ctr), kCtrWords, 0, s));
+  if (p->opt.validate) {
+    if ((op.m == 0 && p->a_nnz != 0) || (op.n == 0 && p->b_nnz != 0)) return SPG_E_INVALID;
+    int* err = reinterpret_cast<int*>(ctr + kCtrMisc + 1);
+    SPG_TRY_HIP(launch_validate(op.a_ptr, op.a_idx, op.m, p->a_nnz, op.n, err, s));
+    SPG_TRY_HIP(launch_validate(op.b_ptr, op.b_idx, op.n, p->b_nnz, op.k, err, s));
+    int herr = 0;
+    SPG_TRY_HIP(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, s));
+    SPG_TRY_HIP(hipStreamSynchronize(s));
+    if (herr) return SPG_E_INVALID;
+  }
+  SPG_TRY_HIP(launch_flops_bin(op, p->bp, flops, c_ptr, ctr + kCtrSym, ctr + kCtrMisc, s));
+  unsigned long long hcounts[kNumBins + 1];
+  SPG_TRY_HIP(hipMemcpyAsync(hcounts, ctr + kCtrSym, kNumBins * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+  SPG_TRY_HIP(hipMemcpyAsync(&hcounts[kNumBins], ctr + kCtrMisc, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+  SPG_TRY_HIP(hipStreamSynchronize(s));
+  std::memcpy(p->sym_counts, hcounts, sizeof(p->sym_counts));
+  p->flops_total = static_cast<int64_t>(hcounts[kNumBins]);
+
+  const BinOffsets so = offsets_of(p->sym_counts);
+  SPG_TRY_HIP(launch_scatter(0, m, flops, c_ptr, p->bp, so, ctr + kCtrCursor, rows_sym, s));
+  int64_t ndense = 0;
+  for (int b = kDenseBinBase; b < kNumBins; ++b) ndense += static_cast<int64_t>(p->sym_counts[b]);
+  if (ndense > 0 && p->sym_P > 1)
+    SPG_TRY_HIP(launch_panel_index(op.b_ptr, op.b_idx, op.n, p->sym_wlog2, p->sym_P, psym, s));
+  for (int c = 1; c < kDenseBinBase; ++c) {
+    if (!p->sym_counts[c]) continue;
+    SPG_TRY_HIP(launch_hash_sym(op, rows_sym + so.v[c], static_cast<int64_t>(p->sym_counts[c]),
+                                hash_table_size(c), hash_threads(c), p->opt.short_seg, c_ptr, s));
+  }
+  if (ndense > 0)
+    SPG_TRY_HIP(launch_dense_sym(op, rows_sym + so.v[kDenseBinBase], ndense, p->sym_wlog2, p->sym_P,
+                                 psym, p->opt.dense_threads, p->opt.short_seg, c_ptr, s));
+  SPG_TRY_HIP(launch_count_num_bins(m, flops, c_ptr, p->bp, ctr + kCtrNum, s));
+  SPG_TRY_HIP(launch_scan_inplace(c_ptr + 1, m, scan, s));
+  int64_t total = 0;
+  SPG_TRY_HIP(hipMemcpyAsync(p->num_counts, ctr + kCtrNum, kNumBins * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+  SPG_TRY_HIP(hipMemcpyAsync(&total, c_ptr + m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  SPG_TRY_HIP(hipStreamSynchronize(s));
+  const BinOffsets no = offsets_of(p->num_counts);
+  SPG_TRY_HIP(launch_fill_u64(reinterpret_cast<uint64_t*>(ctr + kCtrCursor), kNumBins, 0, s));
+  SPG_TRY_HIP(launch_scatter(1, m, flops, c_ptr, p->bp, no, ctr + kCtrCursor, rows_num, s));
+  SPG_TRY_HIP(hipGetLastError());
+  p->c_nnz = total;
+  p->c_ptr = c_ptr;
+  p->state = kSymbolicDone;
+  *c_nnz = total;
+  return SPG_OK;
+}
+
+spg_status spg_numeric(spg_plan* p, void* ws, int32_t* c_idx, void* c_val) {
+  if (!p) return SPG_E_INVALID;
+  if (p->state != kSymbolicDone) return SPG_E_STATE;
+  if (p->c_nnz > 0 && !c_idx) return SPG_E_INVALID;
+  if (p->c_nnz > 0 && !c_val && p->sr != 7) return SPG_E_INVALID;
+  hipStream_t s = p->stream;
+  unsigned char* w = static_cast<unsigned char*>(ws);
+  auto* rows_num = reinterpret_cast<int32_t*>(w + p->off_rows_num);
+  auto* pnum = reinterpret_cast<int32_t*>(w + p->off_pnum);
+  const Operands& op = p->op;
+  const BinOffsets no = offsets_of(p->num_counts);
+  int64_t ndense = 0;
+  for (int b = kDenseBinBase; b < kNumBins; ++b) ndense += static_cast<int64_t>(p->num_counts[b]);
+  if (ndense > 0 && p->num_P > 1)
+    SPG_TRY_HIP(launch_panel_index(op.b_ptr, op.b_idx, op.n, p->num_wlog2, p->num_P, pnum, s));
+  for (int c = 1; c < kDenseBinBase; ++c) {
+    if (!p->num_counts[c]) continue;
+    SPG_TRY_HIP(launch_hash_num(p->sr, op, rows_num + no.v[c], static_cast<int64_t>(p->num_counts[c]),
+                                hash_table_size(c), hash_threads(c), p->opt.short_seg, p->c_ptr, c_idx,
+                                c_val, s));
+  }
+  if (ndense > 0)
+    SPG_TRY_HIP(launch_dense_num(p->sr, op, rows_num + no.v[kDenseBinBase], ndense, p->num_wlog2,
+                                 p->num_P, pnum, p->opt.dense_threads, p->opt.short_seg, p->c_ptr,
+                                 c_idx, c_val, s));
+  return SPG_OK;
+}
+
+spg_status spg_prune_workspace_size(const spg_matrix* C, size_t* bytes) {
+  spg_status st = check_matrix(C);
+  if (st != SPG_OK) return st;
+  if (!bytes) return SPG_E_INVALID;
+  const int64_t nmajor = C->layout == SPG_CSR ? C->nrows : C->ncols;
+  *bytes = align_up(static_cast<size_t>((nmajor + kScanTile - 1) / kScanTile + 1) * sizeof(int64_t));
+  return SPG_OK;
+}
+
+spg_status spg_prune_count_f32(const spg_matrix* C, float thresh, void* ws, void* stream,
+                               int64_t* new_ptr, int64_t* new_nnz) {
+  spg_status st = check_matrix(C);
+  if (st != SPG_OK) return st;
+  if (!new_ptr || !new_nnz || !ws) return SPG_E_INVALID;
+  if (C->nnz > 0 && !C->val) return SPG_E_SEMIRING;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int64_t nmajor = C->layout == SPG_CSR ? C->nrows : C->ncols;
+  SPG_TRY_HIP(launch_prune_count(C->ptr, static_cast<const float*>(C->val), nmajor, thresh, new_ptr, s));
+  SPG_TRY_HIP(launch_scan_inplace(new_ptr + 1, nmajor, static_cast<int64_t*>(ws), s));
+  int64_t total = 0;
+  SPG_TRY_HIP(hipMemcpyAsync(&total, new_ptr + nmajor, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  SPG_TRY_HIP(hipStreamSynchronize(s));
+  *new_nnz = total;
+  return SPG_OK;
+}
+
+spg_status spg_prune_apply_f32(const spg_matrix* C, float thresh, void* ws, void* stream,
+                               const int64_t* new_ptr, int32_t* new_idx, float* new_val) {
+  spg_status st = check_matrix(C);
+  if (st != SPG_OK) return st;
+  (void)ws;
+  if (!new_ptr) return SPG_E_INVALID;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int64_t nmajor = C->layout == SPG_CSR ? C->nrows : C->ncols;
+  SPG_TRY_HIP(launch_prune_apply(C->ptr, C->idx, static_cast<const float*>(C->val), nmajor, thresh,
+                                 new_ptr, new_idx, new_val, s));
+  return SPG_OK;
+}
+
+}  // extern "C"

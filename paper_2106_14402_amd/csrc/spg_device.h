@@ -1,0 +1,375 @@
+// Device-side building blocks of the semiring sparse product on gfx950:
+// semiring traits, block-wide scans, and the row enumerator that feeds every
+// accumulator (LDS hash table or dense LDS panel).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace spg {
+
+constexpr int kWave = 64;
+constexpr int kEmpty = -1;  // empty hash slot (column ids are >= 0)
+constexpr int kPieceUnroll = 4;
+constexpr int kPiece = kWave * kPieceUnroll;  // products per wave work unit
+
+// ---------------------------------------------------------------------------
+// Semirings.  Each trait gives the input value type In, the LDS storage type
+// S (which may be an order-preserving integer encoding), the output type Out,
+// the storage value of an untouched slot, the product a (x) b as storage, an
+// atomic (+) into LDS, and the decoding to Out.  (Paper Sec. 1: semirings over
+// user value types; the set here is fixed.)
+// ---------------------------------------------------------------------------
+
+// Float total order with -0 < +0 mapped onto unsigned integer order.
+__device__ __forceinline__ uint32_t f32_key(float x) {
+  uint32_t b = __float_as_uint(x);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__device__ __forceinline__ float f32_unkey(uint32_t k) {
+  return __uint_as_float((k & 0x80000000u) ? (k ^ 0x80000000u) : ~k);
+}
+__device__ __forceinline__ unsigned long long f64_key(double x) {
+  unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(x));
+  return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+__device__ __forceinline__ double f64_unkey(unsigned long long k) {
+  unsigned long long b = (k >> 63) ? (k ^ 0x8000000000000000ull) : ~k;
+  return __longlong_as_double(static_cast<long long>(b));
+}
+
+struct SrPlusTimesF64 {
+  static constexpr bool kNullable = false;
+  using In = double;
+  using S = double;
+  using Out = double;
+  static constexpr bool kPattern = false;
+  __device__ static S identity() { return 0.0; }
+  __device__ static S mul(In a, In b) { return a * b; }
+  __device__ static void combine(S* p, S v) { atomicAdd(p, v); }
+  __device__ static Out out(S s) { return s; }
+};
+struct SrPlusTimesF32 {
+  static constexpr bool kNullable = false;
+  using In = float;
+  using S = float;
+  using Out = float;
+  static constexpr bool kPattern = false;
+  __device__ static S identity() { return 0.0f; }
+  __device__ static S mul(In a, In b) { return a * b; }
+  __device__ static void combine(S* p, S v) { atomicAdd(p, v); }
+  __device__ static Out out(S s) { return s; }
+};
+struct SrMinPlusI32 {
+  static constexpr bool kNullable = false;
+  using In = int32_t;
+  using S = int32_t;
+  using Out = int32_t;
+  static constexpr bool kPattern = false;
+  __device__ static S identity() { return INT32_MAX; }
+  __device__ static S mul(In a, In b) {
+    long long s = static_cast<long long>(a) + static_cast<long long>(b);
+    s = s > INT32_MAX ? INT32_MAX : s;
+    s = s < INT32_MIN ? INT32_MIN : s;
+    return static_cast<S>(s);
+  }
+  __device__ static void combine(S* p, S v) { atomicMin(p, v); }
+  __device__ static Out out(S s) { return s; }
+};
+struct SrMinPlusF32 {
+  static constexpr bool kNullable = false;
+  using In = float;
+  using S = uint32_t;
+  using Out = float;
+  static constexpr bool kPattern = false;
+  __device__ static S identity() { return 0xFFFFFFFFu; }
+  __device__ static S mul(In a, In b) { return f32_key(a + b); }
+  __device__ static void combine(S* p, S v) { atomicMin(p, v); }
+  __device__ static Out out(S s) { return f32_unkey(s); }
+};
+struct SrOrAndBool {  // a NULL value array on either operand reads as all true
+  using In = uint8_t;
+  using S = uint32_t;
+  using Out = uint8_t;
+  static constexpr bool kPattern = false;
+  static constexpr bool kNullable = true;
+  __device__ static S identity() { return 0u; }
+  __device__ static S mul(In a, In b) { return (a != 0 && b != 0) ? 1u : 0u; }
+  __device__ static void combine(S* p, S v) {
+    if (v) atomicOr(p, v);
+  }
+  __device__ static Out out(S s) { return static_cast<Out>(s != 0); }
+};
+// (OR,AND) with NULL values on both operands: only the pattern is computed.
+struct SrPattern {
+  static constexpr bool kNullable = false;
+  using In = uint8_t;
+  using S = uint32_t;
+  using Out = uint8_t;
+  static constexpr bool kPattern = true;
+  __device__ static S identity() { return 0u; }
+  __device__ static S mul(In, In) { return 1u; }
+  __device__ static void combine(S*, S) {}
+  __device__ static Out out(S) { return 1; }
+};
+struct SrMaxTimesF64 {
+  static constexpr bool kNullable = false;
+  using In = double;
+  using S = unsigned long long;
+  using Out = double;
+  static constexpr bool kPattern = false;
+  __device__ static S identity() { return 0ull; }
+  __device__ static S mul(In a, In b) { return f64_key(a * b); }
+  __device__ static void combine(S* p, S v) { atomicMax(p, v); }
+  __device__ static Out out(S s) { return f64_unkey(s); }
+};
+struct SrMaxTimesF32 {
+  static constexpr bool kNullable = false;
+  using In = float;
+  using S = uint32_t;
+  using Out = float;
+  static constexpr bool kPattern = false;
+  __device__ static S identity() { return 0u; }
+  __device__ static S mul(In a, In b) { return f32_key(a * b); }
+  __device__ static void combine(S* p, S v) { atomicMax(p, v); }
+  __device__ static Out out(S s) { return f32_unkey(s); }
+};
+
+// ---------------------------------------------------------------------------
+// Operands of one CSR product C = A * B (A: m x n, B: n x k).
+// ---------------------------------------------------------------------------
+struct Operands {
+  const int64_t* a_ptr;
+  const int32_t* a_idx;
+  const void* a_val;
+  const int64_t* b_ptr;
+  const int32_t* b_idx;
+  const void* b_val;
+  int32_t m, n, k;
+};
+
+// ---------------------------------------------------------------------------
+// Block-wide scans (blockDim.x a multiple of 64, at most 1024).  tmp needs 16
+// elements of LDS.  Every thread of the block must call them.
+// ---------------------------------------------------------------------------
+template <class T>
+__device__ __forceinline__ T wave_inclusive_scan(T x) {
+  const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    T y = __shfl_up(x, d, kWave);
+    if (lane >= d) x += y;
+  }
+  return x;
+}
+
+template <class T>
+__device__ __forceinline__ T wave_sum(T x) {
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) x += __shfl_xor(x, d, kWave);
+  return x;
+}
+
+template <class T>
+__device__ T block_exclusive_scan(T v, T* tmp, T* total) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+  T x = wave_inclusive_scan(v);
+  if (lane == kWave - 1) tmp[wid] = x;
+  __syncthreads();
+  if (wid == 0) {
+    T w = lane < nw ? tmp[lane] : T(0);
+    w = wave_inclusive_scan(w);
+    if (lane < nw) tmp[lane] = w;
+  }
+  __syncthreads();
+  T off = wid > 0 ? tmp[wid - 1] : T(0);
+  *total = tmp[nw - 1];
+  __syncthreads();
+  return off + x - v;
+}
+
+template <class T>
+__device__ T block_sum(T v, T* tmp) {
+  T t;
+  block_exclusive_scan(v, tmp, &t);
+  return t;
+}
+
+// ---------------------------------------------------------------------------
+// Row enumerator.
+//
+// Feeds every product A(i,k) (x) B(k,j) of one row i of C to a sink, as
+// Gustavson's row formulation does (paper Sec. 4.1).  The row's A entries are
+// taken NT at a time (one per thread).  For each, the segment of B(k,:) that
+// falls in the current column panel is looked up.  Short segments are walked
+// by their own lane.  Long ones are queued in LDS and cut into pieces of
+// kPiece products that the waves of the block take dynamically, so one
+// heavy B row is shared by all waves and every load in a piece is coalesced.
+//
+// Panels: when `paneled`, only columns [c0, c0 + W) are enumerated and the
+// segment bounds come from the panel index pidx (P+1 offsets per B row,
+// relative to the row start); otherwise the whole B row is the segment.
+// Columns are passed to the sink relative to c0.
+// ---------------------------------------------------------------------------
+template <class In>
+struct RowQueue {
+  int* ctr;       // [0] queued entries, [1] next piece, [2..17] scan scratch
+  int64_t* lo;    // segment start in B
+  int32_t* len;   // segment length
+  int32_t* pfx;   // exclusive prefix of piece counts (nq + 1 entries)
+  In* a;          // A value of the entry
+
+  __device__ static RowQueue carve(unsigned char* base, int nt) {
+    RowQueue q;
+    q.ctr = reinterpret_cast<int*>(base);
+    unsigned char* p = base + 32 * sizeof(int);
+    q.lo = reinterpret_cast<int64_t*>(p);
+    p += static_cast<size_t>(nt) * sizeof(int64_t);
+    q.a = reinterpret_cast<In*>(p);
+    p += static_cast<size_t>(nt) * 8;
+    q.len = reinterpret_cast<int32_t*>(p);
+    p += static_cast<size_t>(nt) * sizeof(int32_t);
+    q.pfx = reinterpret_cast<int32_t*>(p);
+    return q;
+  }
+};
+
+// LDS bytes of a RowQueue for nt threads, rounded up to 16.
+__host__ __device__ inline size_t row_queue_bytes(int nt) {
+  size_t b = 32 * sizeof(int) + static_cast<size_t>(nt) * (sizeof(int64_t) + 8 + sizeof(int32_t)) +
+             static_cast<size_t>(nt + 1) * sizeof(int32_t);
+  return (b + 15) & ~static_cast<size_t>(15);
+}
+
+template <class SR>
+__device__ __forceinline__ typename SR::In load_val(const void* v, int64_t p) {
+  if constexpr (SR::kPattern) {
+    return typename SR::In(1);
+  } else {
+    if constexpr (SR::kNullable) {
+      if (v == nullptr) return typename SR::In(1);
+    }
+    return static_cast<const typename SR::In*>(v)[p];
+  }
+}
+
+template <class SR, class Sink>
+__device__ void enumerate_row(const Operands& op, int64_t a_lo, int64_t a_hi, bool paneled,
+                              const int32_t* __restrict__ pidx, int P, int p, int32_t c0,
+                              int short_seg, RowQueue<typename SR::In> q, Sink& sink) {
+  using In = typename SR::In;
+  const int tid = threadIdx.x;
+  const int nt = blockDim.x;
+  const int lane = tid & (kWave - 1);
+  const int32_t* __restrict__ bidx = op.b_idx;
+  if (tid == 0) {
+    q.ctr[0] = 0;
+    q.ctr[1] = 0;
+  }
+  __syncthreads();
+  for (int64_t base = a_lo; base < a_hi; base += nt) {
+    const int64_t pa = base + tid;
+    int64_t lo = 0;
+    int32_t len = 0;
+    In a = In(1);
+    if (pa < a_hi) {
+      const int32_t kk = op.a_idx[pa];
+      a = load_val<SR>(op.a_val, pa);
+      const int64_t bs = op.b_ptr[kk];
+      if (paneled) {
+        const int32_t* s = pidx + static_cast<int64_t>(kk) * (P + 1) + p;
+        lo = bs + s[0];
+        len = s[1] - s[0];
+      } else {
+        lo = bs;
+        len = static_cast<int32_t>(op.b_ptr[kk + 1] - bs);
+      }
+    }
+    if (len > short_seg) {
+      const int slot = atomicAdd(&q.ctr[0], 1);
+      q.lo[slot] = lo;
+      q.len[slot] = len;
+      q.a[slot] = a;
+    } else {
+      // Walked by this lane alone; loads are independent of one another.
+      for (int32_t t = 0; t < len; ++t) {
+        const int64_t qq = lo + t;
+        sink.add(bidx[qq] - c0, SR::mul(a, load_val<SR>(op.b_val, qq)));
+      }
+    }
+    __syncthreads();
+    const int nq = q.ctr[0];
+    if (nq > 0) {
+      int pieces = tid < nq ? (q.len[tid] + kPiece - 1) / kPiece : 0;
+      int ptotal;
+      const int off = block_exclusive_scan(pieces, q.ctr + 2, &ptotal);
+      if (tid < nq) q.pfx[tid] = off;
+      if (tid == 0) q.pfx[nq] = ptotal;
+      __syncthreads();
+      for (;;) {
+        int u = 0;
+        if (lane == 0) u = atomicAdd(&q.ctr[1], 1);
+        u = __shfl(u, 0, kWave);
+        if (u >= ptotal) break;
+        // entry e: last one with pfx[e] <= u
+        int lo_e = 0, hi_e = nq;  // invariant: pfx[lo_e] <= u < pfx[hi_e]
+        while (hi_e - lo_e > 1) {
+          const int mid = (lo_e + hi_e) >> 1;
+          if (q.pfx[mid] <= u)
+            lo_e = mid;
+          else
+            hi_e = mid;
+        }
+        const int e = lo_e;
+        const int64_t s0 = q.lo[e] + static_cast<int64_t>(u - q.pfx[e]) * kPiece;
+        const int64_t s1 = q.lo[e] + q.len[e];
+        const In ae = q.a[e];
+        int32_t cols[kPieceUnroll];
+        In bv[kPieceUnroll];
+#pragma unroll
+        for (int r = 0; r < kPieceUnroll; ++r) {
+          const int64_t qq = s0 + r * kWave + lane;
+          if (qq < s1) {
+            cols[r] = bidx[qq];
+            bv[r] = load_val<SR>(op.b_val, qq);
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < kPieceUnroll; ++r) {
+          const int64_t qq = s0 + r * kWave + lane;
+          if (qq < s1) sink.add(cols[r] - c0, SR::mul(ae, bv[r]));
+        }
+      }
+    }
+    __syncthreads();
+    if (tid == 0) {
+      q.ctr[0] = 0;
+      q.ctr[1] = 0;
+    }
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ uint32_t hash_slot(int32_t key, uint32_t mask) {
+  return (static_cast<uint32_t>(key) * 2654435761u) & mask;
+}
+
+// Position (0..31) of the r-th set bit (r counted from 0) of w.
+__device__ __forceinline__ int select_bit(uint32_t w, int r) {
+  int pos = 0;
+  int c = __popc(w & 0xFFFFu);
+  if (r >= c) { r -= c; w >>= 16; pos += 16; }
+  c = __popc(w & 0xFFu);
+  if (r >= c) { r -= c; w >>= 8; pos += 8; }
+  c = __popc(w & 0xFu);
+  if (r >= c) { r -= c; w >>= 4; pos += 4; }
+  c = __popc(w & 0x3u);
+  if (r >= c) { r -= c; w >>= 2; pos += 2; }
+  c = static_cast<int>(w & 0x1u);
+  if (r >= c) { pos += 1; }
+  return pos;
+}
+
+}  // namespace spg

@@ -1,0 +1,107 @@
+// Host-side launchers of the gfx950 kernels (internal to libspg).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "spg_device.h"
+
+namespace spg {
+
+constexpr int kNumBins = 64;
+constexpr int kDenseBinBase = 16;  // bins >= this use a dense accumulator
+constexpr int kScanTile = 8192;    // elements per scan block
+
+struct BinParams {
+  int64_t hash_max_flops;  // symbolic: hash when flops <= this
+  int64_t hash_max_nnz;    // numeric: hash when nnz <= this
+};
+
+struct BinOffsets {
+  int64_t v[kNumBins];
+};
+
+__host__ __device__ inline int floor_log2_u64(uint64_t x) {
+  int r = -1;
+  while (x) {
+    x >>= 1;
+    ++r;
+  }
+  return r;
+}
+__host__ __device__ inline int ceil_log2_u64(uint64_t x) {
+  return x <= 1 ? 0 : floor_log2_u64(x - 1) + 1;
+}
+
+// Hash classes 1..15 cover bound 32 << (c-1); dense classes 16..63 are
+// ordered by decreasing flops so the heaviest rows are dispatched first.
+__host__ __device__ inline int dense_bin(int64_t flops) {
+  int fl = floor_log2_u64(static_cast<uint64_t>(flops));
+  fl = fl > 47 ? 47 : fl;
+  return kDenseBinBase + (47 - fl);
+}
+__host__ __device__ inline int hash_class(int64_t bound) {
+  const int c = ceil_log2_u64(static_cast<uint64_t>(bound));
+  return (c < 5 ? 5 : c) - 4;
+}
+__host__ __device__ inline int sym_bin(int64_t flops, const BinParams& bp) {
+  if (flops <= 0) return 0;
+  if (flops <= bp.hash_max_flops) return hash_class(flops);
+  return dense_bin(flops);
+}
+__host__ __device__ inline int num_bin(int64_t nnz, int64_t flops, const BinParams& bp) {
+  if (nnz <= 0) return 0;
+  if (nnz <= bp.hash_max_nnz) return hash_class(nnz);
+  return dense_bin(flops);
+}
+// Hash table size and workgroup size of hash class c.
+inline int hash_table_size(int c) { return 64 << (c - 1); }
+inline int hash_threads(int c) {
+  int t = hash_table_size(c) / 16;
+  return t < 64 ? 64 : (t > 1024 ? 1024 : t);
+}
+
+// ---- launchers (all enqueue on `s`; return hipGetLastError()) ------------
+hipError_t launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s);
+hipError_t launch_validate(const int64_t* ptr, const int32_t* idx, int64_t nmajor, int64_t nnz,
+                           int32_t nminor, int* err, hipStream_t s);
+hipError_t launch_flops_bin(const Operands& op, BinParams bp, int64_t* flops, int64_t* c_ptr,
+                            unsigned long long* counts, unsigned long long* total, hipStream_t s);
+hipError_t launch_count_num_bins(int32_t m, const int64_t* flops, const int64_t* c_ptr, BinParams bp,
+                                 unsigned long long* counts, hipStream_t s);
+// mode 0: bins by flops; mode 1: bins by nnz = c_ptr[i+1]-c_ptr[i] (scanned)
+hipError_t launch_scatter(int mode, int32_t m, const int64_t* flops, const int64_t* c_ptr,
+                          BinParams bp, const BinOffsets& offs, unsigned long long* cursors,
+                          int32_t* rows_out, hipStream_t s);
+hipError_t launch_panel_index(const int64_t* b_ptr, const int32_t* b_idx, int32_t nrows, int wlog2,
+                              int P, int32_t* pidx, hipStream_t s);
+// In-place inclusive scan of x[0..len); then x[-1] = 0 (x points one past a
+// leading slot).  partials: ceil(len / kScanTile) + 1 int64.
+hipError_t launch_scan_inplace(int64_t* x, int64_t len, int64_t* partials, hipStream_t s);
+
+hipError_t launch_hash_sym(const Operands& op, const int32_t* rows, int64_t nrows, int T, int nt,
+                           int short_seg, int64_t* c_ptr, hipStream_t s);
+hipError_t launch_dense_sym(const Operands& op, const int32_t* rows, int64_t nrows, int wlog2, int P,
+                            const int32_t* pidx, int nt, int short_seg, int64_t* c_ptr,
+                            hipStream_t s);
+// sr: semiring code 0..6, or 7 for the pattern-only boolean product.
+hipError_t launch_hash_num(int sr, const Operands& op, const int32_t* rows, int64_t nrows, int T,
+                           int nt, int short_seg, const int64_t* c_ptr, int32_t* c_idx,
+                           void* c_val, hipStream_t s);
+hipError_t launch_dense_num(int sr, const Operands& op, const int32_t* rows, int64_t nrows,
+                            int wlog2, int P, const int32_t* pidx, int nt, int short_seg,
+                            const int64_t* c_ptr, int32_t* c_idx, void* c_val, hipStream_t s);
+size_t storage_bytes(int sr);  // bytes per LDS accumulator value (0 for pattern)
+size_t hash_num_lds(int sr, int T, int nt);
+size_t dense_num_lds(int sr, int wlog2, int nt);
+size_t dense_sym_lds(int wlog2, int nt);
+size_t hash_sym_lds(int T, int nt);
+int max_lds_bytes();
+
+hipError_t launch_prune_count(const int64_t* ptr, const float* val, int64_t nmajor, float thresh,
+                              int64_t* new_ptr, hipStream_t s);
+hipError_t launch_prune_apply(const int64_t* ptr, const int32_t* idx, const float* val,
+                              int64_t nmajor, float thresh, const int64_t* new_ptr,
+                              int32_t* new_idx, float* new_val, hipStream_t s);
+
+}  // namespace spg

@@ -1,0 +1,127 @@
+"""Python front end of the semiring sparse product on one MI355X.
+
+torch supplies device memory and streams; every step of the product runs in
+libspg's kernels through the C entry points in ``binding``.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Optional
+
+import torch
+
+from . import binding as B_
+
+IN_DTYPE = {
+    "plus_times_f64": torch.float64, "plus_times_f32": torch.float32, "min_plus_i32": torch.int32,
+    "min_plus_f32": torch.float32, "or_and_bool": torch.uint8, "max_times_f64": torch.float64,
+    "max_times_f32": torch.float32,
+}
+OUT_DTYPE = dict(IN_DTYPE)
+
+
+@dataclasses.dataclass
+class DeviceMatrix:
+    """Compressed sparse matrix on the device (int64 ptr, int32 idx)."""
+
+    nrows: int
+    ncols: int
+    layout: str          # "csr" or "csc"
+    ptr: torch.Tensor
+    idx: torch.Tensor
+    val: Optional[torch.Tensor]
+
+    @property
+    def nnz(self) -> int:
+        return int(self.idx.numel())
+
+    def descriptor(self) -> B_.spg_matrix:
+        lay = B_.SPG_CSR if self.layout == "csr" else B_.SPG_CSC
+        return B_.make_matrix(self.nrows, self.ncols, lay, self.ptr, self.idx, self.val)
+
+
+def to_device(M, device="cuda", value_dtype: Optional[torch.dtype] = None) -> DeviceMatrix:
+    """Copy a host matrix with numpy ``ptr``/``idx``/``val`` arrays to the device."""
+    ptr = torch.from_numpy(M.ptr).to(device=device, dtype=torch.int64)
+    idx = torch.from_numpy(M.idx).to(device=device, dtype=torch.int32)
+    val = None
+    if M.val is not None:
+        val = torch.from_numpy(M.val).to(device=device)
+        if value_dtype is not None:
+            val = val.to(value_dtype)
+    return DeviceMatrix(M.nrows, M.ncols, M.layout, ptr, idx, val)
+
+
+class Product:
+    """One product C = A (x).(+) B: plan, workspace, symbolic and numeric."""
+
+    def __init__(self, A: DeviceMatrix, B: DeviceMatrix, semiring: str,
+                 options: Optional[B_.spg_options] = None, stream=None):
+        self.A, self.B, self.semiring = A, B, semiring
+        self.stream = stream if stream is not None else torch.cuda.current_stream(A.ptr.device)
+        self._da, self._db = A.descriptor(), B.descriptor()
+        self.plan = B_.spg_plan_create(self._da, self._db, semiring, options, self.stream)
+        self.ws = torch.empty(max(1, B_.spg_workspace_size(self.plan)), dtype=torch.uint8,
+                              device=A.ptr.device)
+        if A.layout == "csr":
+            self.nslices, self.out_rows, self.out_cols = A.nrows, A.nrows, B.ncols
+        else:
+            self.nslices, self.out_rows, self.out_cols = B.ncols, A.nrows, B.ncols
+        self.c_ptr = None
+        self.c_nnz = None
+
+    def symbolic(self) -> int:
+        self.c_ptr = torch.empty(self.nslices + 1, dtype=torch.int64, device=self.A.ptr.device)
+        self.c_nnz = B_.spg_symbolic(self.plan, self.ws, self.c_ptr)
+        return self.c_nnz
+
+    def pattern_only(self) -> bool:
+        return self.semiring == "or_and_bool" and self.A.val is None and self.B.val is None
+
+    def numeric(self, c_idx: Optional[torch.Tensor] = None, c_val: Optional[torch.Tensor] = None) -> DeviceMatrix:
+        dev = self.A.ptr.device
+        if c_idx is None:
+            c_idx = torch.empty(self.c_nnz, dtype=torch.int32, device=dev)
+        if c_val is None and not self.pattern_only():
+            c_val = torch.empty(self.c_nnz, dtype=OUT_DTYPE[self.semiring], device=dev)
+        B_.spg_numeric(self.plan, self.ws, c_idx, c_val)
+        return DeviceMatrix(self.out_rows, self.out_cols, self.A.layout, self.c_ptr, c_idx, c_val)
+
+    def stats(self):
+        return B_.spg_plan_stats(self.plan)
+
+    def close(self):
+        if self.plan:
+            B_.spg_plan_destroy(self.plan)
+            self.plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def spgemm(A: DeviceMatrix, B: DeviceMatrix, semiring: str, options=None, stream=None) -> DeviceMatrix:
+    """C = A (x).(+) B; both operands in one layout, C in that layout."""
+    p = Product(A, B, semiring, options, stream)
+    try:
+        p.symbolic()
+        return p.numeric()
+    finally:
+        p.close()
+
+
+def prune_f32(C: DeviceMatrix, thresh: float, stream=None) -> DeviceMatrix:
+    """Keep the entries of a float32 matrix with value >= thresh."""
+    stream = stream if stream is not None else torch.cuda.current_stream(C.ptr.device)
+    d = C.descriptor()
+    dev = C.ptr.device
+    ws = torch.empty(max(1, B_.spg_prune_workspace_size(d)), dtype=torch.uint8, device=dev)
+    nmajor = C.nrows if C.layout == "csr" else C.ncols
+    new_ptr = torch.empty(nmajor + 1, dtype=torch.int64, device=dev)
+    nnz = B_.spg_prune_count_f32(d, thresh, ws, new_ptr, stream)
+    new_idx = torch.empty(nnz, dtype=torch.int32, device=dev)
+    new_val = torch.empty(nnz, dtype=torch.float32, device=dev)
+    B_.spg_prune_apply_f32(d, thresh, ws, new_ptr, new_idx, new_val, stream)
+    return DeviceMatrix(C.nrows, C.ncols, C.layout, new_ptr, new_idx, new_val)
