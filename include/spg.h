@@ -113,8 +113,24 @@ typedef struct spg_options {
                               columns (default 20, i.e. 128 KiB) */
   int32_t lds_budget;      /* bytes of LDS a dense numeric workgroup may use for
                               its panel (default 131072) */
-  int32_t reserved[9];
+  int32_t timing;          /* 1: record HIP events around every phase on the
+                              plan's stream (read with spg_plan_timings) */
+  int32_t reserved[8];
 } spg_options;
+
+/* Phases reported by spg_plan_timings, in milliseconds. */
+enum {
+  SPG_PHASE_VALIDATE = 0,    /* operand check kernels */
+  SPG_PHASE_FLOPS_BIN = 1,   /* per-row flop count, binning, row lists */
+  SPG_PHASE_SYM_HASH = 2,    /* symbolic, LDS hash rows */
+  SPG_PHASE_SYM_DENSE = 3,   /* symbolic, dense bitmap rows */
+  SPG_PHASE_SCAN = 4,        /* offsets scan and numeric binning */
+  SPG_PHASE_NUM_HASH = 5,    /* numeric, LDS hash rows (with in-row sort) */
+  SPG_PHASE_NUM_DENSE = 6,   /* numeric, dense panel rows */
+  SPG_PHASE_SYM_PANELS = 7,  /* panel index of B for the symbolic bitmap */
+  SPG_PHASE_NUM_PANELS = 8,  /* panel index of B for the numeric panels */
+  SPG_NUM_PHASES = 9
+};
 
 typedef struct spg_plan spg_plan;
 
@@ -155,6 +171,18 @@ spg_status spg_numeric(spg_plan* plan, void* ws, int32_t* c_idx, void* c_val);
  * paper's count of nonzero multiplications) and number of output slices. */
 spg_status spg_plan_stats(const spg_plan* plan, int64_t* flops, int64_t* nslices);
 
+/* Elapsed time of each phase of the last symbolic + numeric calls (ms[i]
+ * for phase i < SPG_NUM_PHASES; 0 for a phase that did not run), measured
+ * with HIP events on the plan's stream.  Needs options.timing = 1;
+ * synchronises the stream. */
+spg_status spg_plan_timings(spg_plan* plan, float* ms);
+
+/* Number of output slices per accumulator class after the symbolic phase:
+ * counts[0] empty, counts[1..15] LDS hash classes (class c holds slices of at
+ * most 32 << (c-1) products in symbolic / entries in numeric), counts[16..63]
+ * dense classes.  sym and num each receive 64 entries; either may be NULL. */
+spg_status spg_plan_bins(const spg_plan* plan, int64_t* sym, int64_t* num);
+
 spg_status spg_plan_destroy(spg_plan* plan);
 
 const char* spg_status_str(spg_status s);
@@ -172,6 +200,50 @@ spg_status spg_prune_count_f32(const spg_matrix* C, float thresh, void* ws, void
                                int64_t* new_ptr, int64_t* new_nnz);
 spg_status spg_prune_apply_f32(const spg_matrix* C, float thresh, void* ws, void* stream,
                                const int64_t* new_ptr, int32_t* new_idx, float* new_val);
+
+/* ------------------------------------------------------------------------
+ * Batched products: nprod independent products C_b = A_b (x).(+) B_b, such
+ * as the block products of one 3D Sparse SUMMA stage (paper Sec. 3) or a set
+ * of per-graph squares.  All rows of all products share one binning and one
+ * launch per accumulator class and semiring; the numeric phase can be
+ * captured into a hipGraph and replayed.  Each product follows the rules of
+ * spg_plan_create (its own layout and semiring; at most 8 distinct kernel
+ * semirings per batch).  Outputs are pooled:
+ *   c_ptr_pool  device int64, sum over b of (nslices_b + 1) entries; product
+ *               b's offsets (starting at 0) begin at sum_{b'<b} (nslices_b' + 1)
+ *   c_idx pool  device int32; product b's ids begin at idx_off[b]
+ *   c_val pool  device bytes; product b's values begin at byte val_off[b]
+ *               (8-byte aligned), in its semiring's output type
+ * ------------------------------------------------------------------------ */
+typedef struct spg_batch_plan spg_batch_plan;
+
+/* Host-only checks of all descriptors; semirings[b] is an spg_semiring code. */
+spg_status spg_batch_plan_create(int nprod, const spg_matrix* A, const spg_matrix* B,
+                                 const int* semirings, const spg_options* opt, void* stream,
+                                 spg_batch_plan** out);
+spg_status spg_batch_workspace_size(const spg_batch_plan* plan, size_t* bytes);
+
+/* Symbolic phase of all products.  Host outputs (nprod+1 entries for
+ * idx_off and val_off, the last holding the pool totals; nprod for c_nnz).
+ * Synchronises the stream. */
+spg_status spg_batch_symbolic(spg_batch_plan* plan, void* ws, int64_t* c_ptr_pool, int64_t* c_nnz,
+                              int64_t* idx_off, int64_t* val_off);
+
+/* Numeric phase of all products into the pools (val_off from the symbolic
+ * call).  Enqueues the kernels and returns. */
+spg_status spg_batch_numeric(spg_batch_plan* plan, void* ws, int32_t* c_idx, void* c_val,
+                             const int64_t* val_off);
+
+/* Captures the numeric phase (same arguments) into a hipGraph held by the
+ * plan, without running it; spg_batch_graph_launch replays it on the plan's
+ * stream.  The capture stays valid while the inputs, workspace and pools do. */
+spg_status spg_batch_graph_capture(spg_batch_plan* plan, void* ws, int32_t* c_idx, void* c_val,
+                                   const int64_t* val_off);
+spg_status spg_batch_graph_launch(spg_batch_plan* plan);
+
+/* Total products and rows of the batch after the symbolic phase. */
+spg_status spg_batch_stats(const spg_batch_plan* plan, int64_t* flops, int64_t* rows);
+spg_status spg_batch_plan_destroy(spg_batch_plan* plan);
 
 #ifdef __cplusplus
 }

@@ -57,7 +57,8 @@ class spg_options(ctypes.Structure):
         ("dense_threads", ctypes.c_int32),
         ("sym_panel_log2", ctypes.c_int32),
         ("lds_budget", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 9),
+        ("timing", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 8),
     ]
 
 
@@ -87,6 +88,10 @@ def load(path: str = LIB_PATH):
     L.spg_numeric.argtypes = [vp, vp, vp, vp]
     L.spg_plan_stats.restype = st
     L.spg_plan_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    L.spg_plan_timings.restype = st
+    L.spg_plan_timings.argtypes = [vp, ctypes.POINTER(ctypes.c_float)]
+    L.spg_plan_bins.restype = st
+    L.spg_plan_bins.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     L.spg_plan_destroy.restype = st
     L.spg_plan_destroy.argtypes = [vp]
     L.spg_prune_workspace_size.restype = st
@@ -101,21 +106,26 @@ def load(path: str = LIB_PATH):
 
 
 def _declare_batch(L):
-    """Declare the batched entry points when the library has them."""
-    if not hasattr(L, "spg_batch_plan_create"):
-        return
+    """Declare the batched entry points."""
     vp, i64, st = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
     pm = ctypes.POINTER(spg_matrix)
     po = ctypes.POINTER(spg_options)
+    pi64 = ctypes.POINTER(i64)
     L.spg_batch_plan_create.restype = st
     L.spg_batch_plan_create.argtypes = [ctypes.c_int, pm, pm, ctypes.POINTER(ctypes.c_int), po, vp,
                                         ctypes.POINTER(vp)]
     L.spg_batch_workspace_size.restype = st
     L.spg_batch_workspace_size.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
     L.spg_batch_symbolic.restype = st
-    L.spg_batch_symbolic.argtypes = [vp, vp, vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    L.spg_batch_symbolic.argtypes = [vp, vp, vp, pi64, pi64, pi64]
     L.spg_batch_numeric.restype = st
-    L.spg_batch_numeric.argtypes = [vp, vp, vp, vp, ctypes.POINTER(i64)]
+    L.spg_batch_numeric.argtypes = [vp, vp, vp, vp, pi64]
+    L.spg_batch_graph_capture.restype = st
+    L.spg_batch_graph_capture.argtypes = [vp, vp, vp, vp, pi64]
+    L.spg_batch_graph_launch.restype = st
+    L.spg_batch_graph_launch.argtypes = [vp]
+    L.spg_batch_stats.restype = st
+    L.spg_batch_stats.argtypes = [vp, pi64, pi64]
     L.spg_batch_plan_destroy.restype = st
     L.spg_batch_plan_destroy.argtypes = [vp]
 
@@ -189,6 +199,23 @@ def spg_plan_stats(plan):
     return int(f.value), int(n.value)
 
 
+PHASES = ["validate", "flops_bin", "sym_hash", "sym_dense", "scan", "num_hash", "num_dense",
+          "sym_panels", "num_panels"]
+
+
+def spg_plan_timings(plan) -> dict:
+    ms = (ctypes.c_float * len(PHASES))()
+    _check(load().spg_plan_timings(plan, ms), "spg_plan_timings")
+    return {name: float(ms[i]) for i, name in enumerate(PHASES)}
+
+
+def spg_plan_bins(plan):
+    sym = (ctypes.c_int64 * 64)()
+    num = (ctypes.c_int64 * 64)()
+    _check(load().spg_plan_bins(plan, sym, num), "spg_plan_bins")
+    return list(sym), list(num)
+
+
 def spg_plan_destroy(plan) -> None:
     if plan:
         load().spg_plan_destroy(plan)
@@ -211,3 +238,60 @@ def spg_prune_apply_f32(C: spg_matrix, thresh: float, ws, new_ptr, new_idx, new_
     _check(load().spg_prune_apply_f32(ctypes.byref(C), float(thresh), _addr(ws), _stream(stream),
                                       _addr(new_ptr), _addr(new_idx), _addr(new_val)),
            "spg_prune_apply_f32")
+
+
+# ---- batched entry points ---------------------------------------------------
+def spg_batch_plan_create(As, Bs, semirings, options: Optional[spg_options] = None, stream=None):
+    n = len(As)
+    arrA = (spg_matrix * max(1, n))(*As)
+    arrB = (spg_matrix * max(1, n))(*Bs)
+    codes = (ctypes.c_int * max(1, n))(*[SEMIRINGS[x] if isinstance(x, str) else int(x) for x in semirings])
+    plan = ctypes.c_void_p()
+    _check(load().spg_batch_plan_create(n, arrA, arrB, codes,
+                                        ctypes.byref(options) if options is not None else None,
+                                        _stream(stream), ctypes.byref(plan)), "spg_batch_plan_create")
+    return plan
+
+
+def spg_batch_workspace_size(plan) -> int:
+    n = ctypes.c_size_t()
+    _check(load().spg_batch_workspace_size(plan, ctypes.byref(n)), "spg_batch_workspace_size")
+    return int(n.value)
+
+
+def spg_batch_symbolic(plan, ws, c_ptr_pool, nprod: int):
+    """Returns (c_nnz[nprod], idx_off[nprod+1], val_off[nprod+1]) as lists."""
+    nnz = (ctypes.c_int64 * max(1, nprod))()
+    io = (ctypes.c_int64 * (nprod + 1))()
+    vo = (ctypes.c_int64 * (nprod + 1))()
+    _check(load().spg_batch_symbolic(plan, _addr(ws), _addr(c_ptr_pool), nnz, io, vo), "spg_batch_symbolic")
+    return list(nnz)[:nprod], list(io), list(vo)
+
+
+def _i64_array(values):
+    return (ctypes.c_int64 * max(1, len(values)))(*values)
+
+
+def spg_batch_numeric(plan, ws, c_idx, c_val, val_off) -> None:
+    _check(load().spg_batch_numeric(plan, _addr(ws), _addr(c_idx), _addr(c_val), _i64_array(val_off)),
+           "spg_batch_numeric")
+
+
+def spg_batch_graph_capture(plan, ws, c_idx, c_val, val_off) -> None:
+    _check(load().spg_batch_graph_capture(plan, _addr(ws), _addr(c_idx), _addr(c_val), _i64_array(val_off)),
+           "spg_batch_graph_capture")
+
+
+def spg_batch_graph_launch(plan) -> None:
+    _check(load().spg_batch_graph_launch(plan), "spg_batch_graph_launch")
+
+
+def spg_batch_stats(plan):
+    f, r = ctypes.c_int64(), ctypes.c_int64()
+    _check(load().spg_batch_stats(plan, ctypes.byref(f), ctypes.byref(r)), "spg_batch_stats")
+    return int(f.value), int(r.value)
+
+
+def spg_batch_plan_destroy(plan) -> None:
+    if plan:
+        load().spg_batch_plan_destroy(plan)

@@ -39,9 +39,28 @@ struct spg_plan {
   int64_t* c_ptr;
   unsigned long long sym_counts[kNumBins];
   unsigned long long num_counts[kNumBins];
+  // phase timing (options.timing)
+  hipEvent_t ev[2 * SPG_NUM_PHASES];
+  bool ev_made;
+  bool ran[SPG_NUM_PHASES];
 };
 
 namespace {
+
+// Phase timing: an event pair per phase on the plan's stream.
+struct PhaseTimer {
+  spg_plan* p;
+  int phase;
+  PhaseTimer(spg_plan* plan, int ph) : p(plan), phase(ph) {
+    if (p->opt.timing && p->ev_made) {
+      (void)hipEventRecord(p->ev[2 * phase], p->stream);
+      p->ran[phase] = true;
+    }
+  }
+  ~PhaseTimer() {
+    if (p->opt.timing && p->ev_made) (void)hipEventRecord(p->ev[2 * phase + 1], p->stream);
+  }
+};
 
 // Counter block inside the workspace (uint64 words).
 constexpr int kCtrSym = 0;                 // [64] symbolic bin counts
@@ -217,6 +236,17 @@ spg_status spg_plan_create(const spg_matrix* A, const spg_matrix* B, spg_semirin
   p->ws_bytes = off;
   p->state = kCreated;
   p->c_ptr = nullptr;
+  p->ev_made = false;
+  for (int i = 0; i < SPG_NUM_PHASES; ++i) p->ran[i] = false;
+  if (p->opt.timing) {
+    bool ok = true;
+    for (int i = 0; i < 2 * SPG_NUM_PHASES; ++i) ok = ok && hipEventCreate(&p->ev[i]) == hipSuccess;
+    if (!ok) {
+      delete p;
+      return SPG_E_DEVICE;
+    }
+    p->ev_made = true;
+  }
   *out = p;
   return SPG_OK;
 }
@@ -235,7 +265,31 @@ spg_status spg_plan_stats(const spg_plan* p, int64_t* flops, int64_t* nslices) {
   return SPG_OK;
 }
 
+spg_status spg_plan_timings(spg_plan* p, float* ms) {
+  if (!p || !ms) return SPG_E_INVALID;
+  if (!p->ev_made) return SPG_E_STATE;
+  SPG_TRY_HIP(hipStreamSynchronize(p->stream));
+  for (int i = 0; i < SPG_NUM_PHASES; ++i) {
+    ms[i] = 0.0f;
+    if (p->ran[i]) SPG_TRY_HIP(hipEventElapsedTime(&ms[i], p->ev[2 * i], p->ev[2 * i + 1]));
+  }
+  return SPG_OK;
+}
+
+spg_status spg_plan_bins(const spg_plan* p, int64_t* sym, int64_t* num) {
+  if (!p) return SPG_E_INVALID;
+  if (p->state < kSymbolicDone) return SPG_E_STATE;
+  for (int b = 0; b < kNumBins; ++b) {
+    if (sym) sym[b] = static_cast<int64_t>(p->sym_counts[b]);
+    if (num) num[b] = static_cast<int64_t>(p->num_counts[b]);
+  }
+  return SPG_OK;
+}
+
 spg_status spg_plan_destroy(spg_plan* p) {
+  if (!p) return SPG_OK;
+  if (p->ev_made)
+    for (int i = 0; i < 2 * SPG_NUM_PHASES; ++i) (void)hipEventDestroy(p->ev[i]);
   delete p;
   return SPG_OK;
 }
@@ -255,8 +309,10 @@ spg_status spg_symbolic(spg_plan* p, void* ws, int64_t* c_ptr, int64_t* c_nnz) {
   const Operands& op = p->op;
   const int32_t m = op.m;
 
+  for (int i = 0; i < SPG_NUM_PHASES; ++i) p->ran[i] = false;
   SPG_TRY_HIP(launch_fill_u64(reinterpret_cast<uint64_t*>(ctr), kCtrWords, 0, s));
   if (p->opt.validate) {
+    PhaseTimer t(p, SPG_PHASE_VALIDATE);
     if ((op.m == 0 && p->a_nnz != 0) || (op.n == 0 && p->b_nnz != 0)) return SPG_E_INVALID;
     int* err = reinterpret_cast<int*>(ctr + kCtrMisc + 1);
     SPG_TRY_HIP(launch_validate(op.a_ptr, op.a_idx, op.m, p->a_nnz, op.n, err, s));
@@ -266,8 +322,11 @@ spg_status spg_symbolic(spg_plan* p, void* ws, int64_t* c_ptr, int64_t* c_nnz) {
     SPG_TRY_HIP(hipStreamSynchronize(s));
     if (herr) return SPG_E_INVALID;
   }
-  SPG_TRY_HIP(launch_flops_bin(op, p->bp, flops, c_ptr, ctr + kCtrSym, ctr + kCtrMisc, s));
   unsigned long long hcounts[kNumBins + 1];
+  {
+    PhaseTimer t(p, SPG_PHASE_FLOPS_BIN);
+    SPG_TRY_HIP(launch_flops_bin(op, p->bp, flops, c_ptr, ctr + kCtrSym, ctr + kCtrMisc, s));
+  }
   SPG_TRY_HIP(hipMemcpyAsync(hcounts, ctr + kCtrSym, kNumBins * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
   SPG_TRY_HIP(hipMemcpyAsync(&hcounts[kNumBins], ctr + kCtrMisc, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
   SPG_TRY_HIP(hipStreamSynchronize(s));
@@ -275,22 +334,32 @@ spg_status spg_symbolic(spg_plan* p, void* ws, int64_t* c_ptr, int64_t* c_nnz) {
   p->flops_total = static_cast<int64_t>(hcounts[kNumBins]);
 
   const BinOffsets so = offsets_of(p->sym_counts);
-  SPG_TRY_HIP(launch_scatter(0, m, flops, c_ptr, p->bp, so, ctr + kCtrCursor, rows_sym, s));
   int64_t ndense = 0;
   for (int b = kDenseBinBase; b < kNumBins; ++b) ndense += static_cast<int64_t>(p->sym_counts[b]);
-  if (ndense > 0 && p->sym_P > 1)
-    SPG_TRY_HIP(launch_panel_index(op.b_ptr, op.b_idx, op.n, p->sym_wlog2, p->sym_P, psym, s));
-  for (int c = 1; c < kDenseBinBase; ++c) {
-    if (!p->sym_counts[c]) continue;
-    SPG_TRY_HIP(launch_hash_sym(op, rows_sym + so.v[c], static_cast<int64_t>(p->sym_counts[c]),
-                                hash_table_size(c), hash_threads(c), p->opt.short_seg, c_ptr, s));
+  {
+    PhaseTimer t(p, SPG_PHASE_SYM_HASH);
+    SPG_TRY_HIP(launch_scatter(0, m, flops, c_ptr, p->bp, so, ctr + kCtrCursor, rows_sym, s));
+    for (int c = 1; c < kDenseBinBase; ++c) {
+      if (!p->sym_counts[c]) continue;
+      SPG_TRY_HIP(launch_hash_sym(op, rows_sym + so.v[c], static_cast<int64_t>(p->sym_counts[c]),
+                                  hash_table_size(c), hash_threads(c), p->opt.short_seg, c_ptr, s));
+    }
   }
-  if (ndense > 0)
+  if (ndense > 0) {
+    if (p->sym_P > 1) {
+      PhaseTimer tp(p, SPG_PHASE_SYM_PANELS);
+      SPG_TRY_HIP(launch_panel_index(op.b_ptr, op.b_idx, op.n, p->sym_wlog2, p->sym_P, psym, s));
+    }
+    PhaseTimer t(p, SPG_PHASE_SYM_DENSE);
     SPG_TRY_HIP(launch_dense_sym(op, rows_sym + so.v[kDenseBinBase], ndense, p->sym_wlog2, p->sym_P,
                                  psym, p->opt.dense_threads, p->opt.short_seg, c_ptr, s));
-  SPG_TRY_HIP(launch_count_num_bins(m, flops, c_ptr, p->bp, ctr + kCtrNum, s));
-  SPG_TRY_HIP(launch_scan_inplace(c_ptr + 1, m, scan, s));
+  }
   int64_t total = 0;
+  {
+    PhaseTimer t(p, SPG_PHASE_SCAN);
+    SPG_TRY_HIP(launch_count_num_bins(m, flops, c_ptr, p->bp, ctr + kCtrNum, s));
+    SPG_TRY_HIP(launch_scan_inplace(c_ptr + 1, m, scan, s));
+  }
   SPG_TRY_HIP(hipMemcpyAsync(p->num_counts, ctr + kCtrNum, kNumBins * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
   SPG_TRY_HIP(hipMemcpyAsync(&total, c_ptr + m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   SPG_TRY_HIP(hipStreamSynchronize(s));
@@ -318,18 +387,26 @@ spg_status spg_numeric(spg_plan* p, void* ws, int32_t* c_idx, void* c_val) {
   const BinOffsets no = offsets_of(p->num_counts);
   int64_t ndense = 0;
   for (int b = kDenseBinBase; b < kNumBins; ++b) ndense += static_cast<int64_t>(p->num_counts[b]);
-  if (ndense > 0 && p->num_P > 1)
-    SPG_TRY_HIP(launch_panel_index(op.b_ptr, op.b_idx, op.n, p->num_wlog2, p->num_P, pnum, s));
-  for (int c = 1; c < kDenseBinBase; ++c) {
-    if (!p->num_counts[c]) continue;
-    SPG_TRY_HIP(launch_hash_num(p->sr, op, rows_num + no.v[c], static_cast<int64_t>(p->num_counts[c]),
-                                hash_table_size(c), hash_threads(c), p->opt.short_seg, p->c_ptr, c_idx,
-                                c_val, s));
+  p->ran[SPG_PHASE_NUM_HASH] = p->ran[SPG_PHASE_NUM_DENSE] = p->ran[SPG_PHASE_NUM_PANELS] = false;
+  {
+    PhaseTimer t(p, SPG_PHASE_NUM_HASH);
+    for (int c = 1; c < kDenseBinBase; ++c) {
+      if (!p->num_counts[c]) continue;
+      SPG_TRY_HIP(launch_hash_num(p->sr, op, rows_num + no.v[c], static_cast<int64_t>(p->num_counts[c]),
+                                  hash_table_size(c), hash_threads(c), p->opt.short_seg, p->c_ptr,
+                                  c_idx, c_val, s));
+    }
   }
-  if (ndense > 0)
+  if (ndense > 0) {
+    if (p->num_P > 1) {
+      PhaseTimer tp(p, SPG_PHASE_NUM_PANELS);
+      SPG_TRY_HIP(launch_panel_index(op.b_ptr, op.b_idx, op.n, p->num_wlog2, p->num_P, pnum, s));
+    }
+    PhaseTimer t(p, SPG_PHASE_NUM_DENSE);
     SPG_TRY_HIP(launch_dense_num(p->sr, op, rows_num + no.v[kDenseBinBase], ndense, p->num_wlog2,
                                  p->num_P, pnum, p->opt.dense_threads, p->opt.short_seg, p->c_ptr,
                                  c_idx, c_val, s));
+  }
   return SPG_OK;
 }
 

@@ -10,7 +10,7 @@ namespace spg {
 
 constexpr int kWave = 64;
 constexpr int kEmpty = -1;  // empty hash slot (column ids are >= 0)
-constexpr int kPieceUnroll = 4;
+constexpr int kPieceUnroll = 16;
 constexpr int kPiece = kWave * kPieceUnroll;  // products per wave work unit
 
 // ---------------------------------------------------------------------------
@@ -217,10 +217,19 @@ template <class In>
 struct RowQueue {
   int* ctr;       // [0] queued entries, [1] next piece, [2..17] scan scratch
   int64_t* lo;    // segment start in B
+  In* a;          // A value of the entry
   int32_t* len;   // segment length
   int32_t* pfx;   // exclusive prefix of piece counts (nq + 1 entries)
-  In* a;          // A value of the entry
 
+  __host__ __device__ static size_t a_bytes(int nt) {
+    return (static_cast<size_t>(nt) * sizeof(In) + 7) & ~static_cast<size_t>(7);
+  }
+  // LDS bytes for nt threads, rounded up to 16.
+  __host__ __device__ static size_t bytes(int nt) {
+    size_t b = 32 * sizeof(int) + static_cast<size_t>(nt) * sizeof(int64_t) + a_bytes(nt) +
+               static_cast<size_t>(nt) * sizeof(int32_t) + static_cast<size_t>(nt + 1) * sizeof(int32_t);
+    return (b + 15) & ~static_cast<size_t>(15);
+  }
   __device__ static RowQueue carve(unsigned char* base, int nt) {
     RowQueue q;
     q.ctr = reinterpret_cast<int*>(base);
@@ -228,20 +237,13 @@ struct RowQueue {
     q.lo = reinterpret_cast<int64_t*>(p);
     p += static_cast<size_t>(nt) * sizeof(int64_t);
     q.a = reinterpret_cast<In*>(p);
-    p += static_cast<size_t>(nt) * 8;
+    p += a_bytes(nt);
     q.len = reinterpret_cast<int32_t*>(p);
     p += static_cast<size_t>(nt) * sizeof(int32_t);
     q.pfx = reinterpret_cast<int32_t*>(p);
     return q;
   }
 };
-
-// LDS bytes of a RowQueue for nt threads, rounded up to 16.
-__host__ __device__ inline size_t row_queue_bytes(int nt) {
-  size_t b = 32 * sizeof(int) + static_cast<size_t>(nt) * (sizeof(int64_t) + 8 + sizeof(int32_t)) +
-             static_cast<size_t>(nt + 1) * sizeof(int32_t);
-  return (b + 15) & ~static_cast<size_t>(15);
-}
 
 template <class SR>
 __device__ __forceinline__ typename SR::In load_val(const void* v, int64_t p) {
@@ -254,6 +256,8 @@ __device__ __forceinline__ typename SR::In load_val(const void* v, int64_t p) {
     return static_cast<const typename SR::In*>(v)[p];
   }
 }
+
+constexpr int kShortUnroll = 8;  // loads in flight per lane on a short segment
 
 template <class SR, class Sink>
 __device__ void enumerate_row(const Operands& op, int64_t a_lo, int64_t a_hi, bool paneled,
@@ -293,10 +297,20 @@ __device__ void enumerate_row(const Operands& op, int64_t a_lo, int64_t a_hi, bo
       q.len[slot] = len;
       q.a[slot] = a;
     } else {
-      // Walked by this lane alone; loads are independent of one another.
-      for (int32_t t = 0; t < len; ++t) {
-        const int64_t qq = lo + t;
-        sink.add(bidx[qq] - c0, SR::mul(a, load_val<SR>(op.b_val, qq)));
+      // Walked by this lane alone, kShortUnroll independent loads at a time.
+      for (int32_t t = 0; t < len; t += kShortUnroll) {
+        int32_t cols[kShortUnroll];
+        In bv[kShortUnroll];
+#pragma unroll
+        for (int u = 0; u < kShortUnroll; ++u) {
+          if (t + u < len) {
+            cols[u] = bidx[lo + t + u];
+            bv[u] = load_val<SR>(op.b_val, lo + t + u);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kShortUnroll; ++u)
+          if (t + u < len) sink.add(cols[u] - c0, SR::mul(a, bv[u]));
       }
     }
     __syncthreads();
@@ -308,13 +322,13 @@ __device__ void enumerate_row(const Operands& op, int64_t a_lo, int64_t a_hi, bo
       if (tid < nq) q.pfx[tid] = off;
       if (tid == 0) q.pfx[nq] = ptotal;
       __syncthreads();
+      int e_lo = 0;  // pieces are taken in increasing order by each wave
       for (;;) {
         int u = 0;
         if (lane == 0) u = atomicAdd(&q.ctr[1], 1);
         u = __shfl(u, 0, kWave);
         if (u >= ptotal) break;
-        // entry e: last one with pfx[e] <= u
-        int lo_e = 0, hi_e = nq;  // invariant: pfx[lo_e] <= u < pfx[hi_e]
+        int lo_e = e_lo, hi_e = nq;  // pfx[lo_e] <= u < pfx[hi_e]
         while (hi_e - lo_e > 1) {
           const int mid = (lo_e + hi_e) >> 1;
           if (q.pfx[mid] <= u)
@@ -323,6 +337,7 @@ __device__ void enumerate_row(const Operands& op, int64_t a_lo, int64_t a_hi, bo
             hi_e = mid;
         }
         const int e = lo_e;
+        e_lo = e;
         const int64_t s0 = q.lo[e] + static_cast<int64_t>(u - q.pfx[e]) * kPiece;
         const int64_t s1 = q.lo[e] + q.len[e];
         const In ae = q.a[e];

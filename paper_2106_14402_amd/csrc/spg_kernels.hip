@@ -339,45 +339,37 @@ struct DenseSink {
 
 // ---------------------------------------------------------------------------
 // Symbolic phase (paper Sec. 4.1 phase 2): size of every output row.
+//
+// Each accumulator is a per-row device function that uses the block's
+// dynamic LDS; a single-product kernel and a batched kernel (rows of many
+// products in one grid-stride launch, operands read from a descriptor table)
+// wrap the same function.
 // ---------------------------------------------------------------------------
-size_t hash_sym_lds(int T, int nt) { return row_queue_bytes(nt) + static_cast<size_t>(T) * 4; }
+using PatQueue = RowQueue<SrPattern::In>;
 
-__global__ __launch_bounds__(1024) void k_hash_sym(Operands op, const int32_t* __restrict__ rows,
-                                                   int T, int short_seg, int64_t* __restrict__ c_ptr) {
-  extern __shared__ __align__(16) unsigned char smem[];
+size_t hash_sym_lds(int T, int nt) { return PatQueue::bytes(nt) + static_cast<size_t>(T) * 4; }
+size_t dense_sym_lds(int wlog2, int nt) {
+  return PatQueue::bytes(nt) + (static_cast<size_t>(1) << wlog2) / 8;
+}
+
+__device__ int64_t hash_sym_row(const Operands& op, int32_t row, int T, int short_seg,
+                                unsigned char* smem) {
   const int nt = blockDim.x;
-  auto q = RowQueue<SrPattern::In>::carve(smem, nt);
-  int32_t* keys = reinterpret_cast<int32_t*>(smem + row_queue_bytes(nt));
-  const int32_t row = rows[blockIdx.x];
+  auto q = PatQueue::carve(smem, nt);
+  int32_t* keys = reinterpret_cast<int32_t*>(smem + PatQueue::bytes(nt));
   for (int t = threadIdx.x; t < T; t += nt) keys[t] = kEmpty;
   __syncthreads();
   HashSetSink sink{keys, static_cast<uint32_t>(T - 1), 0};
   enumerate_row<SrPattern>(op, op.a_ptr[row], op.a_ptr[row + 1], false, nullptr, 1, 0, 0, short_seg,
                            q, sink);
-  const int total = block_sum(sink.count, q.ctr + 2);
-  if (threadIdx.x == 0) c_ptr[row + 1] = total;
+  return block_sum(sink.count, q.ctr + 2);
 }
 
-hipError_t launch_hash_sym(const Operands& op, const int32_t* rows, int64_t nrows, int T, int nt,
-                           int short_seg, int64_t* c_ptr, hipStream_t s) {
-  if (nrows <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_hash_sym, dim3(static_cast<unsigned>(nrows)), dim3(nt), hash_sym_lds(T, nt),
-                     s, op, rows, T, short_seg, c_ptr);
-  return hipGetLastError();
-}
-
-size_t dense_sym_lds(int wlog2, int nt) {
-  return row_queue_bytes(nt) + (static_cast<size_t>(1) << wlog2) / 8;
-}
-
-__global__ __launch_bounds__(1024) void k_dense_sym(Operands op, const int32_t* __restrict__ rows,
-                                                    int wlog2, int P, const int32_t* __restrict__ pidx,
-                                                    int short_seg, int64_t* __restrict__ c_ptr) {
-  extern __shared__ __align__(16) unsigned char smem[];
+__device__ int64_t dense_sym_row(const Operands& op, int32_t row, int wlog2, int P,
+                                 const int32_t* __restrict__ pidx, int short_seg, unsigned char* smem) {
   const int nt = blockDim.x;
-  auto q = RowQueue<SrPattern::In>::carve(smem, nt);
-  uint32_t* bits = reinterpret_cast<uint32_t*>(smem + row_queue_bytes(nt));
-  const int32_t row = rows[blockIdx.x];
+  auto q = PatQueue::carve(smem, nt);
+  uint32_t* bits = reinterpret_cast<uint32_t*>(smem + PatQueue::bytes(nt));
   const int64_t a_lo = op.a_ptr[row], a_hi = op.a_ptr[row + 1];
   int64_t total = 0;
   for (int p = 0; p < P; ++p) {
@@ -392,15 +384,113 @@ __global__ __launch_bounds__(1024) void k_dense_sym(Operands op, const int32_t* 
     for (int t = threadIdx.x; t < nwords; t += nt) cnt += __popc(bits[t]);
     total += block_sum(cnt, q.ctr + 2);
   }
-  if (threadIdx.x == 0) c_ptr[row + 1] = total;
+  return total;
+}
+
+// Product of global row r in a batch: the last b with row_off[b] <= r.
+__device__ __forceinline__ int batch_product(const int64_t* __restrict__ row_off, int nprod, int64_t r) {
+  int lo = 0, hi = nprod;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (row_off[mid] <= r)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(1024) void k_hash_sym(Operands op, const int32_t* __restrict__ rows,
+                                                   int64_t nrows, int T, int short_seg,
+                                                   int64_t* __restrict__ c_ptr) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  for (int64_t it = blockIdx.x; it < nrows; it += gridDim.x) {
+    const int32_t row = rows[it];
+    const int64_t nz = hash_sym_row(op, row, T, short_seg, smem);
+    if (threadIdx.x == 0) c_ptr[row + 1] = nz;
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_dense_sym(Operands op, const int32_t* __restrict__ rows,
+                                                    int64_t nrows, int wlog2, int P,
+                                                    const int32_t* __restrict__ pidx, int short_seg,
+                                                    int64_t* __restrict__ c_ptr) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  for (int64_t it = blockIdx.x; it < nrows; it += gridDim.x) {
+    const int32_t row = rows[it];
+    const int64_t nz = dense_sym_row(op, row, wlog2, P, pidx, short_seg, smem);
+    if (threadIdx.x == 0) c_ptr[row + 1] = nz;
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_hash_sym_b(const BatchDesc* __restrict__ descs,
+                                                     const int64_t* __restrict__ row_off, int nprod,
+                                                     const int32_t* __restrict__ items, int64_t nitems,
+                                                     int T, int short_seg) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const int64_t r = items[it];
+    const int b = batch_product(row_off, nprod, r);
+    const BatchDesc& d = descs[b];
+    const int32_t row = static_cast<int32_t>(r - row_off[b]);
+    const int64_t nz = hash_sym_row(d.op, row, T, short_seg, smem);
+    if (threadIdx.x == 0) d.c_ptr[row + 1] = nz;
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_dense_sym_b(const BatchDesc* __restrict__ descs,
+                                                      const int64_t* __restrict__ row_off, int nprod,
+                                                      const int32_t* __restrict__ items, int64_t nitems,
+                                                      int short_seg) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const int64_t r = items[it];
+    const int b = batch_product(row_off, nprod, r);
+    const BatchDesc& d = descs[b];
+    const int32_t row = static_cast<int32_t>(r - row_off[b]);
+    const int64_t nz = dense_sym_row(d.op, row, d.sym_wlog2, d.sym_P, d.psym, short_seg, smem);
+    if (threadIdx.x == 0) d.c_ptr[row + 1] = nz;
+    __syncthreads();
+  }
+}
+
+static unsigned grid_for(int64_t items, int64_t cap) {
+  return static_cast<unsigned>(cap > 0 && items > cap ? cap : items);
+}
+
+hipError_t launch_hash_sym(const Operands& op, const int32_t* rows, int64_t nrows, int T, int nt,
+                           int short_seg, int64_t* c_ptr, hipStream_t s) {
+  if (nrows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_hash_sym, dim3(grid_for(nrows, 0)), dim3(nt), hash_sym_lds(T, nt), s, op, rows,
+                     nrows, T, short_seg, c_ptr);
+  return hipGetLastError();
 }
 
 hipError_t launch_dense_sym(const Operands& op, const int32_t* rows, int64_t nrows, int wlog2, int P,
                             const int32_t* pidx, int nt, int short_seg, int64_t* c_ptr,
                             hipStream_t s) {
   if (nrows <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_dense_sym, dim3(static_cast<unsigned>(nrows)), dim3(nt),
-                     dense_sym_lds(wlog2, nt), s, op, rows, wlog2, P, pidx, short_seg, c_ptr);
+  hipLaunchKernelGGL(k_dense_sym, dim3(grid_for(nrows, 0)), dim3(nt), dense_sym_lds(wlog2, nt), s, op,
+                     rows, nrows, wlog2, P, pidx, short_seg, c_ptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_hash_sym_b(const BatchDesc* descs, const int64_t* row_off, int nprod,
+                             const int32_t* items, int64_t nitems, int T, int nt, int short_seg,
+                             int64_t grid_cap, hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_hash_sym_b, dim3(grid_for(nitems, grid_cap)), dim3(nt), hash_sym_lds(T, nt), s,
+                     descs, row_off, nprod, items, nitems, T, short_seg);
+  return hipGetLastError();
+}
+
+hipError_t launch_dense_sym_b(const BatchDesc* descs, const int64_t* row_off, int nprod,
+                              const int32_t* items, int64_t nitems, int wlog2_max, int nt,
+                              int short_seg, int64_t grid_cap, hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_dense_sym_b, dim3(grid_for(nitems, grid_cap)), dim3(nt),
+                     dense_sym_lds(wlog2_max, nt), s, descs, row_off, nprod, items, nitems, short_seg);
   return hipGetLastError();
 }
 
@@ -433,20 +523,18 @@ __device__ void bitonic_sort(int32_t* keys, S* vals, int N, bool with_vals) {
 
 constexpr int kMaxSlotsPerThread = 16;
 
+// LDS hash accumulator for one row, then compaction, bitonic sort and
+// coalesced stores of the row's entries into [out, out_end).
 template <class SR>
-__global__ __launch_bounds__(1024) void k_hash_num(Operands op, const int32_t* __restrict__ rows,
-                                                   int T, int short_seg,
-                                                   const int64_t* __restrict__ c_ptr,
-                                                   int32_t* __restrict__ c_idx,
-                                                   typename SR::Out* __restrict__ c_val) {
+__device__ void hash_num_row(const Operands& op, int32_t row, int T, int short_seg, int64_t out,
+                             int64_t out_end, int32_t* __restrict__ c_idx,
+                             typename SR::Out* __restrict__ c_val, unsigned char* smem) {
   using S = typename SR::S;
-  extern __shared__ __align__(16) unsigned char smem[];
   const int nt = blockDim.x;
   const int tid = threadIdx.x;
   auto q = RowQueue<typename SR::In>::carve(smem, nt);
-  int32_t* keys = reinterpret_cast<int32_t*>(smem + row_queue_bytes(nt));
+  int32_t* keys = reinterpret_cast<int32_t*>(smem + RowQueue<typename SR::In>::bytes(nt));
   S* vals = reinterpret_cast<S*>(keys + T);
-  const int32_t row = rows[blockIdx.x];
   for (int t = tid; t < T; t += nt) {
     keys[t] = kEmpty;
     if constexpr (!SR::kPattern) vals[t] = SR::identity();
@@ -455,7 +543,6 @@ __global__ __launch_bounds__(1024) void k_hash_num(Operands op, const int32_t* _
   HashMapSink<SR> sink{keys, vals, static_cast<uint32_t>(T - 1)};
   enumerate_row<SR>(op, op.a_ptr[row], op.a_ptr[row + 1], false, nullptr, 1, 0, 0, short_seg, q,
                     sink);
-  __syncthreads();
   // Compact occupied slots to the front: every thread takes a contiguous
   // block of T/nt slots into registers, then writes them at its scanned offset.
   const int per = T / nt;
@@ -487,35 +574,35 @@ __global__ __launch_bounds__(1024) void k_hash_num(Operands op, const int32_t* _
   for (int t = nnz + tid; t < N; t += nt) keys[t] = INT32_MAX;
   __syncthreads();
   bitonic_sort<S>(keys, vals, N, !SR::kPattern);
-  const int64_t out = c_ptr[row];
   // The symbolic count and this one agree; the clamp keeps writes inside the
   // row's range of C regardless.
-  const int lim = static_cast<int>(min(static_cast<int64_t>(nnz), c_ptr[row + 1] - out));
+  const int lim = static_cast<int>(min(static_cast<int64_t>(nnz), out_end - out));
   for (int e = tid; e < lim; e += nt) {
     c_idx[out + e] = keys[e];
     if constexpr (!SR::kPattern) c_val[out + e] = SR::out(vals[e]);
   }
+  __syncthreads();
 }
 
+// Dense LDS panel accumulator for one row: presence bits plus one value per
+// column of the panel, emitted in column order into [out, out_end).
 template <class SR>
-__global__ __launch_bounds__(1024) void k_dense_num(Operands op, const int32_t* __restrict__ rows,
-                                                    int wlog2, int P, const int32_t* __restrict__ pidx,
-                                                    int short_seg, const int64_t* __restrict__ c_ptr,
-                                                    int32_t* __restrict__ c_idx,
-                                                    typename SR::Out* __restrict__ c_val) {
+__device__ void dense_num_row(const Operands& op, int32_t row, int wlog2, int P,
+                              const int32_t* __restrict__ pidx, int short_seg, int64_t out,
+                              int64_t out_end, int32_t* __restrict__ c_idx,
+                              typename SR::Out* __restrict__ c_val, unsigned char* smem) {
   using S = typename SR::S;
-  extern __shared__ __align__(16) unsigned char smem[];
+  using Q = RowQueue<typename SR::In>;
   const int nt = blockDim.x;
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wid = tid >> 6;
+  const int nw = nt >> 6;
   const int W = 1 << wlog2;
-  auto q = RowQueue<typename SR::In>::carve(smem, nt);
-  unsigned char* p0 = smem + row_queue_bytes(nt);
-  int32_t* wpre = reinterpret_cast<int32_t*>(p0);  // per-wave exclusive bit counts, nt entries
-  uint32_t* bits = reinterpret_cast<uint32_t*>(p0 + static_cast<size_t>(nt) * 4);
-  S* vals = reinterpret_cast<S*>(p0 + static_cast<size_t>(nt) * 4 + static_cast<size_t>(W) / 8);
-  const int32_t row = rows[blockIdx.x];
+  auto q = Q::carve(smem, nt);
+  unsigned char* p0 = smem + Q::bytes(nt);
+  uint32_t* bits = reinterpret_cast<uint32_t*>(p0);
+  S* vals = reinterpret_cast<S*>(p0 + static_cast<size_t>(W) / 8);
   const int64_t a_lo = op.a_ptr[row], a_hi = op.a_ptr[row + 1];
   const int32_t wcols_max = min(W, op.k);
   for (int t = tid; t < (wcols_max + 31) >> 5; t += nt) bits[t] = 0u;
@@ -523,74 +610,121 @@ __global__ __launch_bounds__(1024) void k_dense_num(Operands op, const int32_t* 
     for (int t = tid; t < wcols_max; t += nt) vals[t] = SR::identity();
   }
   __syncthreads();
-  int64_t out = c_ptr[row];
-  const int64_t row_end = c_ptr[row + 1];
   for (int p = 0; p < P; ++p) {
     const int32_t c0 = p << wlog2;
     const int32_t wcols = min(W, op.k - c0);
     const int nwords = (wcols + 31) >> 5;
     DenseSink<SR> sink{bits, vals};
     enumerate_row<SR>(op, a_lo, a_hi, P > 1, pidx, P, p, c0, short_seg, q, sink);
-    // Emit the panel in column order, nt words per round.  Lane l of wave w
-    // owns word base + 64w + l; the wave then writes its entries with
-    // consecutive lanes on consecutive output slots.
-    for (int base = 0; base < nwords; base += nt) {
-      const int w = base + tid;
-      const uint32_t word = w < nwords ? bits[w] : 0u;
+    // Emit the panel in column order.  Wave w owns a contiguous range of
+    // words; one block scan of the wave totals places the ranges, then each
+    // wave walks its range 64 words at a time with no further barriers.
+    // Lane l writes the entries of its own word at consecutive slots, and
+    // resets what it read for the next panel.
+    const int wpw = (((nwords + nw - 1) / nw) + kWave - 1) & ~(kWave - 1);
+    const int w_begin = min(nwords, wid * wpw);
+    const int w_end = min(nwords, w_begin + wpw);
+    int cnt = 0;
+    for (int w = w_begin + lane; w < w_end; w += kWave) cnt += __popc(bits[w]);
+    cnt = wave_sum(cnt);
+    int ptotal;
+    const int woff = __shfl(block_exclusive_scan(lane == 0 ? cnt : 0, q.ctr + 2, &ptotal), 0, kWave);
+    int64_t o_base = out + woff;
+    for (int w0 = w_begin; w0 < w_end; w0 += kWave) {
+      const int w = w0 + lane;
+      const uint32_t word = w < w_end ? bits[w] : 0u;
       const int c = __popc(word);
       const int incl = wave_inclusive_scan(c);
-      wpre[tid] = incl - c;
-      int rtotal;
-      const int wave_total = __shfl(incl, kWave - 1, kWave);
-      const int wave_off = block_exclusive_scan(lane == 0 ? wave_total : 0, q.ctr + 2, &rtotal);
-      const int woff = __shfl(wave_off, 0, kWave);
-      const int32_t* wp = wpre + wid * kWave;
-      for (int s = lane; s < wave_total; s += kWave) {
-        int lo = 0, hi = kWave;  // last l with wp[l] <= s
-        while (hi - lo > 1) {
-          const int mid = (lo + hi) >> 1;
-          if (wp[mid] <= s)
-            lo = mid;
-          else
-            hi = mid;
-        }
-        const int wsrc = base + wid * kWave + lo;
-        const int bit = select_bit(bits[wsrc], s - wp[lo]);
-        const int col = (wsrc << 5) + bit;
-        const int64_t o = out + woff + s;
-        if (o < row_end) {
+      int64_t o = o_base + (incl - c);
+      uint32_t x = word;
+      while (x) {
+        const int b = __ffs(x) - 1;
+        const int col = (w << 5) + b;
+        if (o < out_end) {
           c_idx[o] = c0 + col;
           if constexpr (!SR::kPattern) c_val[o] = SR::out(vals[col]);
         }
+        if constexpr (!SR::kPattern) vals[col] = SR::identity();
+        x &= x - 1;
+        ++o;
       }
-      __syncthreads();
-      // Reset what this thread's word touched for the next panel.
-      if (w < nwords && word) {
-        bits[w] = 0u;
-        if constexpr (!SR::kPattern) {
-          uint32_t x = word;
-          while (x) {
-            const int b = __ffs(x) - 1;
-            vals[(w << 5) + b] = SR::identity();
-            x &= x - 1;
-          }
-        }
-      }
-      out += rtotal;
+      if (word) bits[w] = 0u;
+      o_base += __shfl(incl, kWave - 1, kWave);
     }
+    out += ptotal;
     __syncthreads();
   }
 }
 
 template <class SR>
+__global__ __launch_bounds__(1024) void k_hash_num(Operands op, const int32_t* __restrict__ rows,
+                                                   int64_t nrows, int T, int short_seg,
+                                                   const int64_t* __restrict__ c_ptr,
+                                                   int32_t* __restrict__ c_idx,
+                                                   typename SR::Out* __restrict__ c_val) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  for (int64_t it = blockIdx.x; it < nrows; it += gridDim.x) {
+    const int32_t row = rows[it];
+    hash_num_row<SR>(op, row, T, short_seg, c_ptr[row], c_ptr[row + 1], c_idx, c_val, smem);
+  }
+}
+
+template <class SR>
+__global__ __launch_bounds__(1024) void k_dense_num(Operands op, const int32_t* __restrict__ rows,
+                                                    int64_t nrows, int wlog2, int P,
+                                                    const int32_t* __restrict__ pidx, int short_seg,
+                                                    const int64_t* __restrict__ c_ptr,
+                                                    int32_t* __restrict__ c_idx,
+                                                    typename SR::Out* __restrict__ c_val) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  for (int64_t it = blockIdx.x; it < nrows; it += gridDim.x) {
+    const int32_t row = rows[it];
+    dense_num_row<SR>(op, row, wlog2, P, pidx, short_seg, c_ptr[row], c_ptr[row + 1], c_idx, c_val,
+                      smem);
+  }
+}
+
+template <class SR>
+__global__ __launch_bounds__(1024) void k_hash_num_b(const BatchDesc* __restrict__ descs,
+                                                     const int64_t* __restrict__ row_off, int nprod,
+                                                     const int32_t* __restrict__ items, int64_t nitems,
+                                                     int T, int short_seg) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const int64_t r = items[it];
+    const int b = batch_product(row_off, nprod, r);
+    const BatchDesc& d = descs[b];
+    const int32_t row = static_cast<int32_t>(r - row_off[b]);
+    hash_num_row<SR>(d.op, row, T, short_seg, d.c_ptr[row], d.c_ptr[row + 1], d.c_idx,
+                     static_cast<typename SR::Out*>(d.c_val), smem);
+  }
+}
+
+template <class SR>
+__global__ __launch_bounds__(1024) void k_dense_num_b(const BatchDesc* __restrict__ descs,
+                                                      const int64_t* __restrict__ row_off, int nprod,
+                                                      const int32_t* __restrict__ items, int64_t nitems,
+                                                      int short_seg) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const int64_t r = items[it];
+    const int b = batch_product(row_off, nprod, r);
+    const BatchDesc& d = descs[b];
+    const int32_t row = static_cast<int32_t>(r - row_off[b]);
+    dense_num_row<SR>(d.op, row, d.num_wlog2, d.num_P, d.pnum, short_seg, d.c_ptr[row],
+                      d.c_ptr[row + 1], d.c_idx, static_cast<typename SR::Out*>(d.c_val), smem);
+  }
+}
+
+template <class SR>
 static size_t hash_num_lds_t(int T, int nt) {
-  return row_queue_bytes(nt) + static_cast<size_t>(T) * (4 + (SR::kPattern ? 0 : sizeof(typename SR::S)));
+  return RowQueue<typename SR::In>::bytes(nt) +
+         static_cast<size_t>(T) * (4 + (SR::kPattern ? 0 : sizeof(typename SR::S)));
 }
 template <class SR>
 static size_t dense_num_lds_t(int wlog2, int nt) {
   const size_t W = static_cast<size_t>(1) << wlog2;
-  return row_queue_bytes(nt) + static_cast<size_t>(nt) * 4 + W / 8 +
-         (SR::kPattern ? 0 : W * sizeof(typename SR::S));
+  return RowQueue<typename SR::In>::bytes(nt) + W / 8 + (SR::kPattern ? 0 : W * sizeof(typename SR::S));
 }
 
 template <class SR>
@@ -598,9 +732,8 @@ static hipError_t hash_num_t(const Operands& op, const int32_t* rows, int64_t nr
                              int short_seg, const int64_t* c_ptr, int32_t* c_idx, void* c_val,
                              hipStream_t s) {
   if (nrows <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_hash_num<SR>, dim3(static_cast<unsigned>(nrows)), dim3(nt),
-                     hash_num_lds_t<SR>(T, nt), s, op, rows, T, short_seg, c_ptr, c_idx,
-                     static_cast<typename SR::Out*>(c_val));
+  hipLaunchKernelGGL(k_hash_num<SR>, dim3(grid_for(nrows, 0)), dim3(nt), hash_num_lds_t<SR>(T, nt), s,
+                     op, rows, nrows, T, short_seg, c_ptr, c_idx, static_cast<typename SR::Out*>(c_val));
   return hipGetLastError();
 }
 
@@ -609,9 +742,30 @@ static hipError_t dense_num_t(const Operands& op, const int32_t* rows, int64_t n
                               int P, const int32_t* pidx, int nt, int short_seg,
                               const int64_t* c_ptr, int32_t* c_idx, void* c_val, hipStream_t s) {
   if (nrows <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_dense_num<SR>, dim3(static_cast<unsigned>(nrows)), dim3(nt),
-                     dense_num_lds_t<SR>(wlog2, nt), s, op, rows, wlog2, P, pidx, short_seg, c_ptr,
-                     c_idx, static_cast<typename SR::Out*>(c_val));
+  hipLaunchKernelGGL(k_dense_num<SR>, dim3(grid_for(nrows, 0)), dim3(nt), dense_num_lds_t<SR>(wlog2, nt),
+                     s, op, rows, nrows, wlog2, P, pidx, short_seg, c_ptr, c_idx,
+                     static_cast<typename SR::Out*>(c_val));
+  return hipGetLastError();
+}
+
+template <class SR>
+static hipError_t hash_num_b_t(const BatchDesc* descs, const int64_t* row_off, int nprod,
+                               const int32_t* items, int64_t nitems, int T, int nt, int short_seg,
+                               int64_t grid_cap, hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_hash_num_b<SR>, dim3(grid_for(nitems, grid_cap)), dim3(nt),
+                     hash_num_lds_t<SR>(T, nt), s, descs, row_off, nprod, items, nitems, T, short_seg);
+  return hipGetLastError();
+}
+
+template <class SR>
+static hipError_t dense_num_b_t(const BatchDesc* descs, const int64_t* row_off, int nprod,
+                                const int32_t* items, int64_t nitems, int wlog2_max, int nt,
+                                int short_seg, int64_t grid_cap, hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_dense_num_b<SR>, dim3(grid_for(nitems, grid_cap)), dim3(nt),
+                     dense_num_lds_t<SR>(wlog2_max, nt), s, descs, row_off, nprod, items, nitems,
+                     short_seg);
   return hipGetLastError();
 }
 
@@ -638,6 +792,19 @@ hipError_t launch_dense_num(int sr, const Operands& op, const int32_t* rows, int
                             const int64_t* c_ptr, int32_t* c_idx, void* c_val, hipStream_t s) {
   SPG_DISPATCH(sr, dense_num_t, op, rows, nrows, wlog2, P, pidx, nt, short_seg, c_ptr, c_idx, c_val,
                s)
+}
+
+hipError_t launch_hash_num_b(int sr, const BatchDesc* descs, const int64_t* row_off, int nprod,
+                             const int32_t* items, int64_t nitems, int T, int nt, int short_seg,
+                             int64_t grid_cap, hipStream_t s) {
+  SPG_DISPATCH(sr, hash_num_b_t, descs, row_off, nprod, items, nitems, T, nt, short_seg, grid_cap, s)
+}
+
+hipError_t launch_dense_num_b(int sr, const BatchDesc* descs, const int64_t* row_off, int nprod,
+                              const int32_t* items, int64_t nitems, int wlog2_max, int nt,
+                              int short_seg, int64_t grid_cap, hipStream_t s) {
+  SPG_DISPATCH(sr, dense_num_b_t, descs, row_off, nprod, items, nitems, wlog2_max, nt, short_seg,
+               grid_cap, s)
 }
 
 size_t hash_num_lds(int sr, int T, int nt) { SPG_DISPATCH(sr, hash_num_lds_t, T, nt) }

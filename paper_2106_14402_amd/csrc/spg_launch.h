@@ -54,6 +54,19 @@ __host__ __device__ inline int num_bin(int64_t nnz, int64_t flops, const BinPara
   if (nnz <= bp.hash_max_nnz) return hash_class(nnz);
   return dense_bin(flops);
 }
+// One product of a batch, as the batched kernels see it.
+struct BatchDesc {
+  Operands op;             // oriented CSR problem
+  int64_t* c_ptr;          // the product's row offsets inside the pooled array
+  int32_t* c_idx;          // start of the product's ids in the pooled array
+  void* c_val;             // start of the product's values in the pooled array
+  const int32_t* psym;     // panel index for the symbolic bitmap (sym_P > 1)
+  const int32_t* pnum;     // panel index for the numeric panels (num_P > 1)
+  int32_t sym_wlog2, sym_P, num_wlog2, num_P;
+  int32_t sr;              // kernel semiring code
+  int32_t pad;
+};
+
 // Hash table size and workgroup size of hash class c.
 inline int hash_table_size(int c) { return 64 << (c - 1); }
 inline int hash_threads(int c) {
@@ -91,6 +104,18 @@ hipError_t launch_hash_num(int sr, const Operands& op, const int32_t* rows, int6
 hipError_t launch_dense_num(int sr, const Operands& op, const int32_t* rows, int64_t nrows,
                             int wlog2, int P, const int32_t* pidx, int nt, int short_seg,
                             const int64_t* c_ptr, int32_t* c_idx, void* c_val, hipStream_t s);
+hipError_t launch_hash_sym_b(const BatchDesc* descs, const int64_t* row_off, int nprod,
+                             const int32_t* items, int64_t nitems, int T, int nt, int short_seg,
+                             int64_t grid_cap, hipStream_t s);
+hipError_t launch_dense_sym_b(const BatchDesc* descs, const int64_t* row_off, int nprod,
+                              const int32_t* items, int64_t nitems, int wlog2_max, int nt,
+                              int short_seg, int64_t grid_cap, hipStream_t s);
+hipError_t launch_hash_num_b(int sr, const BatchDesc* descs, const int64_t* row_off, int nprod,
+                             const int32_t* items, int64_t nitems, int T, int nt, int short_seg,
+                             int64_t grid_cap, hipStream_t s);
+hipError_t launch_dense_num_b(int sr, const BatchDesc* descs, const int64_t* row_off, int nprod,
+                              const int32_t* items, int64_t nitems, int wlog2_max, int nt,
+                              int short_seg, int64_t grid_cap, hipStream_t s);
 size_t storage_bytes(int sr);  // bytes per LDS accumulator value (0 for pattern)
 size_t hash_num_lds(int sr, int T, int nt);
 size_t dense_num_lds(int sr, int wlog2, int nt);

@@ -70,8 +70,10 @@ class Product:
         self.c_ptr = None
         self.c_nnz = None
 
-    def symbolic(self) -> int:
-        self.c_ptr = torch.empty(self.nslices + 1, dtype=torch.int64, device=self.A.ptr.device)
+    def symbolic(self, c_ptr: Optional[torch.Tensor] = None) -> int:
+        if c_ptr is None:
+            c_ptr = torch.empty(self.nslices + 1, dtype=torch.int64, device=self.A.ptr.device)
+        self.c_ptr = c_ptr
         self.c_nnz = B_.spg_symbolic(self.plan, self.ws, self.c_ptr)
         return self.c_nnz
 
@@ -89,6 +91,12 @@ class Product:
 
     def stats(self):
         return B_.spg_plan_stats(self.plan)
+
+    def timings(self) -> dict:
+        return B_.spg_plan_timings(self.plan)
+
+    def bins(self):
+        return B_.spg_plan_bins(self.plan)
 
     def close(self):
         if self.plan:
