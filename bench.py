@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target host time of the oracle sample (0 disables)")
     ap.add_argument("--semirings", default="or_and_bool,min_plus_i32")
+    ap.add_argument("--bitmap-mib", type=int, default=24576,
+                    help="workspace for symbolic bitmaps kept for the pattern-only numeric phase")
     return ap.parse_args()
 
 
@@ -83,8 +85,9 @@ def main():
     mats = {"or_and_bool": Apat, "min_plus_i32": Ad}
     s_in = {"or_and_bool": 0, "min_plus_i32": 4}
     s_out = {"or_and_bool": 0, "min_plus_i32": 4}
-    opts = B.make_options(timing=1)
-    prods = {sr: S.Product(mats[sr], mats[sr], sr, opts) for sr in semirings}
+    opts = {"or_and_bool": B.make_options(timing=1, bitmap_mib=args.bitmap_mib),
+            "min_plus_i32": B.make_options(timing=1, seg_mib=20480)}
+    prods = {sr: S.Product(mats[sr], mats[sr], sr, opts[sr]) for sr in semirings}
     c_ptr = torch.empty(H.nrows + 1, dtype=torch.int64, device=dev)
 
     # sizes (one symbolic pass, outside timing) and output buffers
@@ -136,6 +139,8 @@ def main():
         num_dense_rows = rownnz > 4096
         sym_dense_rows = fl > 8192
         cands = {
+            "k_expand_rows": (phase_ms[sr].get("num_expand", 0.0), 0),
+            "k_hash_num_seg": (phase_ms[sr].get("num_hash", 0.0), 0),
             "k_dense_num": (phase_ms[sr]["num_dense"], alg_bytes_dense(
                 H, int(deg[num_dense_rows].sum()), int(num_dense_rows.sum()),
                 int(rownnz[num_dense_rows].sum()), s_in[sr], s_out[sr], False)),

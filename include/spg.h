@@ -115,7 +115,22 @@ typedef struct spg_options {
                               its panel (default 131072) */
   int32_t timing;          /* 1: record HIP events around every phase on the
                               plan's stream (read with spg_plan_timings) */
-  int32_t reserved[8];
+  int32_t split_panels;    /* numeric phase of rows that took the dense
+                              symbolic path, when the value panels are
+                              narrower than C: 0 (default) splits each such
+                              row into one work item per column panel, binned
+                              by that panel's exact size; -1 processes the
+                              panels of a row in sequence in one workgroup */
+  int32_t bitmap_mib;      /* pattern-only (OR,AND) products: MiB of workspace
+                              in which the symbolic phase keeps the column
+                              bitmaps of its heaviest rows, so the numeric
+                              phase expands them instead of recomputing
+                              (default 0: off) */
+  int32_t seg_mib;         /* MiB of workspace for the segment lists of
+                              (row, panel) pieces (default 16384); a product
+                              that needs more falls back to re-walking each
+                              row per piece */
+  int32_t reserved[5];
 } spg_options;
 
 /* Phases reported by spg_plan_timings, in milliseconds. */
@@ -129,7 +144,10 @@ enum {
   SPG_PHASE_NUM_DENSE = 6,   /* numeric, dense panel rows */
   SPG_PHASE_SYM_PANELS = 7,  /* panel index of B for the symbolic bitmap */
   SPG_PHASE_NUM_PANELS = 8,  /* panel index of B for the numeric panels */
-  SPG_NUM_PHASES = 9
+  SPG_PHASE_NUM_EXPAND = 9,  /* numeric, rows expanded from kept bitmaps */
+  SPG_PHASE_SEG_COUNT = 10,  /* symbolic, segment counts of (row, panel) pieces */
+  SPG_PHASE_SEG_WRITE = 11,  /* numeric, segment lists of (row, panel) pieces */
+  SPG_NUM_PHASES = 12
 };
 
 typedef struct spg_plan spg_plan;
@@ -186,6 +204,28 @@ spg_status spg_plan_bins(const spg_plan* plan, int64_t* sym, int64_t* num);
 spg_status spg_plan_destroy(spg_plan* plan);
 
 const char* spg_status_str(spg_status s);
+
+/* Column panels.  A dense row accumulator covers 2^wlog2 columns of C at a
+ * time; when C is wider, the plan uses P = ceil(ncols(C) / 2^wlog2) panels
+ * and a panel index of the right-hand CSR operand: for every row k of it,
+ * P+1 int32 offsets (relative to the row start) of the first entry with
+ * column >= p * 2^wlog2.  A caller that multiplies many left operands by one
+ * resident right operand (a served adjacency matrix) can build the index
+ * once and hand it to every plan.
+ *   spg_plan_panels:        the plan's widths and panel counts (host), after
+ *                           plan creation
+ *   spg_panel_index_size:   bytes of the index for operand R (CSR, the
+ *                           right-hand operand as the kernels see it)
+ *   spg_panel_index_build:  builds it into `out` (device) on `stream`
+ *   spg_plan_set_panels:    which = 0 symbolic, 1 numeric; `pidx` (device,
+ *                           caller-owned, built with the plan's wlog2) is used
+ *                           instead of building one in the workspace.
+ * Errors: SPG_E_INVALID for a wlog2 that does not match the plan. */
+spg_status spg_plan_panels(const spg_plan* plan, int* sym_wlog2, int* sym_P, int* num_wlog2,
+                           int* num_P);
+spg_status spg_panel_index_size(const spg_matrix* R, int wlog2, size_t* bytes);
+spg_status spg_panel_index_build(const spg_matrix* R, int wlog2, void* out, void* stream);
+spg_status spg_plan_set_panels(spg_plan* plan, int which, const void* pidx, int wlog2);
 
 /* Pruning of a float32 matrix (the Markov-clustering step after expansion):
  * keep entries with value >= thresh, drop the rest, order unchanged.  Two

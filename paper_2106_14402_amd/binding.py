@@ -58,7 +58,10 @@ class spg_options(ctypes.Structure):
         ("sym_panel_log2", ctypes.c_int32),
         ("lds_budget", ctypes.c_int32),
         ("timing", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 8),
+        ("split_panels", ctypes.c_int32),
+        ("bitmap_mib", ctypes.c_int32),
+        ("seg_mib", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 5),
     ]
 
 
@@ -94,6 +97,15 @@ def load(path: str = LIB_PATH):
     L.spg_plan_bins.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     L.spg_plan_destroy.restype = st
     L.spg_plan_destroy.argtypes = [vp]
+    pint = ctypes.POINTER(ctypes.c_int)
+    L.spg_plan_panels.restype = st
+    L.spg_plan_panels.argtypes = [vp, pint, pint, pint, pint]
+    L.spg_panel_index_size.restype = st
+    L.spg_panel_index_size.argtypes = [pm, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]
+    L.spg_panel_index_build.restype = st
+    L.spg_panel_index_build.argtypes = [pm, ctypes.c_int, vp, vp]
+    L.spg_plan_set_panels.restype = st
+    L.spg_plan_set_panels.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int]
     L.spg_prune_workspace_size.restype = st
     L.spg_prune_workspace_size.argtypes = [pm, ctypes.POINTER(ctypes.c_size_t)]
     L.spg_prune_count_f32.restype = st
@@ -200,7 +212,7 @@ def spg_plan_stats(plan):
 
 
 PHASES = ["validate", "flops_bin", "sym_hash", "sym_dense", "scan", "num_hash", "num_dense",
-          "sym_panels", "num_panels"]
+          "sym_panels", "num_panels", "num_expand", "seg_count", "seg_write"]
 
 
 def spg_plan_timings(plan) -> dict:
@@ -219,6 +231,28 @@ def spg_plan_bins(plan):
 def spg_plan_destroy(plan) -> None:
     if plan:
         load().spg_plan_destroy(plan)
+
+
+def spg_plan_panels(plan):
+    """(sym_wlog2, sym_P, num_wlog2, num_P)"""
+    v = [ctypes.c_int() for _ in range(4)]
+    _check(load().spg_plan_panels(plan, *[ctypes.byref(x) for x in v]), "spg_plan_panels")
+    return tuple(int(x.value) for x in v)
+
+
+def spg_panel_index_size(R: spg_matrix, wlog2: int) -> int:
+    n = ctypes.c_size_t()
+    _check(load().spg_panel_index_size(ctypes.byref(R), int(wlog2), ctypes.byref(n)), "spg_panel_index_size")
+    return int(n.value)
+
+
+def spg_panel_index_build(R: spg_matrix, wlog2: int, out, stream=None) -> None:
+    _check(load().spg_panel_index_build(ctypes.byref(R), int(wlog2), _addr(out), _stream(stream)),
+           "spg_panel_index_build")
+
+
+def spg_plan_set_panels(plan, which: int, pidx, wlog2: int) -> None:
+    _check(load().spg_plan_set_panels(plan, int(which), _addr(pidx), int(wlog2)), "spg_plan_set_panels")
 
 
 def spg_prune_workspace_size(C: spg_matrix) -> int:

@@ -32,7 +32,20 @@ struct spg_plan {
   int sym_wlog2, sym_P, num_wlog2, num_P;
   // workspace layout (byte offsets)
   size_t off_ctr, off_flops, off_rows_sym, off_rows_num, off_scan, off_psym, off_pnum, ws_bytes;
+  bool split;                    // heavy rows go to the numeric phase as (row, panel) pieces
+  size_t off_subcnt, off_suboff, off_subitems, off_wend;
+  int64_t n_dense_sym;
+  bool keep;                     // pattern-only: keep heavy rows' symbolic bitmaps
+  size_t off_rowslot, off_store;
+  int64_t keep_nwords, keep_min_flops;
+  unsigned int keep_cap;
+  size_t off_segoff, off_segs;   // (row, panel) segment lists
+  int64_t seg_cap, seg_total;
+  bool pnum_ready;
+  unsigned long long sub_counts[kNumBins];
   int64_t a_nnz, b_nnz;  // entries of the oriented operands
+  const int32_t* ext_psym;  // caller-built panel indexes (NULL: build in workspace)
+  const int32_t* ext_pnum;
   int state;
   int64_t flops_total;
   int64_t c_nnz;
@@ -67,7 +80,8 @@ constexpr int kCtrSym = 0;                 // [64] symbolic bin counts
 constexpr int kCtrNum = kNumBins;          // [64] numeric bin counts
 constexpr int kCtrCursor = 2 * kNumBins;   // [64] scatter cursors
 constexpr int kCtrMisc = 3 * kNumBins;     // [0] total flops, [1] validation error bits
-constexpr int kCtrWords = 4 * kNumBins;
+constexpr int kCtrSub = 4 * kNumBins;      // [64] (row, panel) piece bin counts
+constexpr int kCtrWords = 5 * kNumBins;
 
 spg_status from_hip(hipError_t e) { return e == hipSuccess ? SPG_OK : SPG_E_DEVICE; }
 
@@ -99,6 +113,7 @@ void resolve_options(const spg_options* in, spg_options* o) {
   if (o->dense_threads <= 0) o->dense_threads = 1024;
   if (o->sym_panel_log2 <= 0) o->sym_panel_log2 = 20;
   if (o->lds_budget <= 0) o->lds_budget = 131072;
+  if (o->seg_mib <= 0) o->seg_mib = 16384;
 }
 
 spg_status check_options(const spg_options& o, int sr) {
@@ -186,12 +201,15 @@ spg_status spg_plan_create(const spg_matrix* A, const spg_matrix* B, spg_semirin
   p->sr = (bool_sr && !A->val && !B->val) ? 7 : sr;
 
   resolve_options(opt_in, &p->opt);
+  if (!opt_in || opt_in->hash_max_nnz <= 0)  // a hash table of 16K slots fits LDS for 4-byte values
+    p->opt.hash_max_nnz = storage_bytes(p->sr == 7 ? 2 : p->sr) <= 4 ? 8192 : 4096;
   if ((st = check_options(p->opt, p->sr)) != SPG_OK) {
     delete p;
     return st;
   }
   p->bp.hash_max_flops = p->opt.hash_max_flops;
   p->bp.hash_max_nnz = p->opt.hash_max_nnz;
+  p->bp.split_heavy = 0;
 
   // Dense panels.  Symbolic: a bitmap of 2^sym_panel_log2 columns.  Numeric:
   // presence bits plus one accumulator value per column, as wide as the LDS
@@ -214,6 +232,9 @@ spg_status spg_plan_create(const spg_matrix* A, const spg_matrix* B, spg_semirin
   const int64_t kk = std::max<int64_t>(1, p->op.k);
   p->sym_P = static_cast<int>((kk + (int64_t(1) << p->sym_wlog2) - 1) >> p->sym_wlog2);
   p->num_P = static_cast<int>((kk + (int64_t(1) << p->num_wlog2) - 1) >> p->num_wlog2);
+  p->split = p->opt.split_panels >= 0 && p->sr != 7 && p->num_P > 1 && p->sym_wlog2 >= p->num_wlog2 &&
+             static_cast<int64_t>(p->op.m) * p->num_P < (int64_t(1) << 31);
+  p->bp.split_heavy = p->split ? 1 : 0;
 
   // Workspace layout.
   const int64_t m = p->op.m;
@@ -228,14 +249,54 @@ spg_status spg_plan_create(const spg_matrix* A, const spg_matrix* B, spg_semirin
   p->off_rows_num = off;
   off = align_up(off + static_cast<size_t>(m) * sizeof(int32_t));
   p->off_scan = off;
-  off = align_up(off + static_cast<size_t>((m + kScanTile - 1) / kScanTile + 1) * sizeof(int64_t));
+  {
+    // scan partials for the row offsets and for the piece segment offsets
+    const int64_t slen = std::max<int64_t>(m, 1) * std::max(1, p->num_P) + 1;
+    off = align_up(off + static_cast<size_t>((slen + kScanTile - 1) / kScanTile + 1) * sizeof(int64_t));
+  }
   p->off_psym = off;
   if (p->sym_P > 1) off = align_up(off + static_cast<size_t>(nB) * (p->sym_P + 1) * sizeof(int32_t));
   p->off_pnum = off;
   if (p->num_P > 1) off = align_up(off + static_cast<size_t>(nB) * (p->num_P + 1) * sizeof(int32_t));
+  p->keep = p->sr == 7 && p->sym_P == 1 && p->opt.bitmap_mib > 0 && p->op.k > 0;
+  p->keep_nwords = (static_cast<int64_t>(p->op.k) + 31) / 32;
+  p->keep_min_flops = 4 * p->keep_nwords;
+  p->keep_cap = 0;
+  if (p->keep) {
+    const int64_t cap = (static_cast<int64_t>(p->opt.bitmap_mib) << 20) / (p->keep_nwords * 4);
+    p->keep_cap = static_cast<unsigned int>(std::min<int64_t>(cap, std::max<int64_t>(m, 1)));
+    if (p->keep_cap == 0) p->keep = false;
+  }
+  p->off_rowslot = off;
+  if (p->keep) off = align_up(off + static_cast<size_t>(m) * sizeof(int32_t));
+  p->off_store = off;
+  if (p->keep) off = align_up(off + static_cast<size_t>(p->keep_cap) * p->keep_nwords * 4);
+  const size_t nsub = p->split ? static_cast<size_t>(m) * p->num_P : 0;
+  p->off_subcnt = off;
+  off = align_up(off + nsub * sizeof(int32_t));
+  p->off_suboff = off;
+  off = align_up(off + nsub * sizeof(int32_t));
+  p->off_subitems = off;
+  off = align_up(off + nsub * sizeof(int32_t));
+  p->off_wend = off;
+  off = align_up(off + nsub * sizeof(int32_t));
+  p->off_segoff = off;
+  if (p->split) off = align_up(off + (nsub + 1) * sizeof(int64_t));
+  p->off_segs = off;
+  p->seg_cap = 0;
+  if (p->split) {
+    const int64_t bound = p->a_nnz * static_cast<int64_t>(p->num_P);
+    const int64_t budget = (static_cast<int64_t>(p->opt.seg_mib) << 20) / static_cast<int64_t>(seg_desc_bytes());
+    p->seg_cap = std::min(bound, budget);
+    off = align_up(off + static_cast<size_t>(p->seg_cap) * seg_desc_bytes());
+  }
+  p->seg_total = 0;
+  p->pnum_ready = false;
   p->ws_bytes = off;
   p->state = kCreated;
   p->c_ptr = nullptr;
+  p->ext_psym = nullptr;
+  p->ext_pnum = nullptr;
   p->ev_made = false;
   for (int i = 0; i < SPG_NUM_PHASES; ++i) p->ran[i] = false;
   if (p->opt.timing) {
@@ -282,6 +343,49 @@ spg_status spg_plan_bins(const spg_plan* p, int64_t* sym, int64_t* num) {
   for (int b = 0; b < kNumBins; ++b) {
     if (sym) sym[b] = static_cast<int64_t>(p->sym_counts[b]);
     if (num) num[b] = static_cast<int64_t>(p->num_counts[b]);
+  }
+  return SPG_OK;
+}
+
+spg_status spg_plan_panels(const spg_plan* p, int* sym_wlog2, int* sym_P, int* num_wlog2, int* num_P) {
+  if (!p) return SPG_E_INVALID;
+  if (sym_wlog2) *sym_wlog2 = p->sym_wlog2;
+  if (sym_P) *sym_P = p->sym_P;
+  if (num_wlog2) *num_wlog2 = p->num_wlog2;
+  if (num_P) *num_P = p->num_P;
+  return SPG_OK;
+}
+
+spg_status spg_panel_index_size(const spg_matrix* R, int wlog2, size_t* bytes) {
+  spg_status st = check_matrix(R);
+  if (st != SPG_OK) return st;
+  if (!bytes || wlog2 < 1 || wlog2 > 30 || R->layout != SPG_CSR) return SPG_E_INVALID;
+  const int64_t W = int64_t(1) << wlog2;
+  const int64_t P = (std::max<int64_t>(1, R->ncols) + W - 1) / W;
+  *bytes = static_cast<size_t>(R->nrows) * static_cast<size_t>(P + 1) * sizeof(int32_t);
+  return SPG_OK;
+}
+
+spg_status spg_panel_index_build(const spg_matrix* R, int wlog2, void* out, void* stream) {
+  size_t bytes = 0;
+  spg_status st = spg_panel_index_size(R, wlog2, &bytes);
+  if (st != SPG_OK) return st;
+  if (!out && bytes > 0) return SPG_E_INVALID;
+  const int64_t W = int64_t(1) << wlog2;
+  const int P = static_cast<int>((std::max<int64_t>(1, R->ncols) + W - 1) / W);
+  SPG_TRY_HIP(launch_panel_index(R->ptr, R->idx, R->nrows, wlog2, P, static_cast<int32_t*>(out),
+                                 static_cast<hipStream_t>(stream)));
+  return SPG_OK;
+}
+
+spg_status spg_plan_set_panels(spg_plan* p, int which, const void* pidx, int wlog2) {
+  if (!p || (which != 0 && which != 1)) return SPG_E_INVALID;
+  if (which == 0) {
+    if (pidx && wlog2 != p->sym_wlog2) return SPG_E_INVALID;
+    p->ext_psym = static_cast<const int32_t*>(pidx);
+  } else {
+    if (pidx && wlog2 != p->num_wlog2) return SPG_E_INVALID;
+    p->ext_pnum = static_cast<const int32_t*>(pidx);
   }
   return SPG_OK;
 }
@@ -346,26 +450,71 @@ spg_status spg_symbolic(spg_plan* p, void* ws, int64_t* c_ptr, int64_t* c_nnz) {
     }
   }
   if (ndense > 0) {
-    if (p->sym_P > 1) {
+    if (p->sym_P > 1 && p->ext_psym) {
+      psym = const_cast<int32_t*>(p->ext_psym);
+    } else if (p->sym_P > 1) {
       PhaseTimer tp(p, SPG_PHASE_SYM_PANELS);
       SPG_TRY_HIP(launch_panel_index(op.b_ptr, op.b_idx, op.n, p->sym_wlog2, p->sym_P, psym, s));
     }
     PhaseTimer t(p, SPG_PHASE_SYM_DENSE);
+    KeepBitmaps kb{};
+    if (p->keep) {
+      kb.store = reinterpret_cast<uint32_t*>(w + p->off_store);
+      kb.row_slot = reinterpret_cast<int32_t*>(w + p->off_rowslot);
+      kb.counter = reinterpret_cast<unsigned int*>(ctr + kCtrMisc + 2);
+      kb.flops = flops;
+      kb.min_flops = p->keep_min_flops;
+      kb.nwords = p->keep_nwords;
+      kb.capacity = p->keep_cap;
+    }
     SPG_TRY_HIP(launch_dense_sym(op, rows_sym + so.v[kDenseBinBase], ndense, p->sym_wlog2, p->sym_P,
-                                 psym, p->opt.dense_threads, p->opt.short_seg, c_ptr, s));
+                                 psym, p->opt.dense_threads, p->opt.short_seg, c_ptr, s,
+                                 p->split ? p->num_wlog2 : 0, p->split ? p->num_P : 0,
+                                 p->split ? reinterpret_cast<int32_t*>(w + p->off_subcnt) : nullptr, kb));
   }
   int64_t total = 0;
+  p->n_dense_sym = ndense;
+  p->bp.row_slot = (p->keep && ndense > 0) ? reinterpret_cast<const int32_t*>(w + p->off_rowslot) : nullptr;
   {
     PhaseTimer t(p, SPG_PHASE_SCAN);
     SPG_TRY_HIP(launch_count_num_bins(m, flops, c_ptr, p->bp, ctr + kCtrNum, s));
     SPG_TRY_HIP(launch_scan_inplace(c_ptr + 1, m, scan, s));
+    if (p->split && ndense > 0)
+      SPG_TRY_HIP(launch_sub_prepare(ndense, p->num_P, reinterpret_cast<int32_t*>(w + p->off_subcnt),
+                                     reinterpret_cast<int32_t*>(w + p->off_suboff),
+                                     reinterpret_cast<int32_t*>(w + p->off_wend), p->bp, ctr + kCtrSub, s));
   }
+  p->pnum_ready = false;
+  p->seg_total = 0;
+  if (p->split && ndense > 0) {
+    auto* pnum = reinterpret_cast<int32_t*>(w + p->off_pnum);
+    if (!p->ext_pnum) {
+      PhaseTimer tp(p, SPG_PHASE_NUM_PANELS);
+      SPG_TRY_HIP(launch_panel_index(op.b_ptr, op.b_idx, op.n, p->num_wlog2, p->num_P, pnum, s));
+    }
+    p->pnum_ready = true;
+    PhaseTimer tc(p, SPG_PHASE_SEG_COUNT);
+    auto* segoff = reinterpret_cast<int64_t*>(w + p->off_segoff);
+    SPG_TRY_HIP(launch_seg_count(op, rows_sym + so.v[kDenseBinBase], ndense, p->num_P,
+                                 p->ext_pnum ? p->ext_pnum : pnum,
+                                 reinterpret_cast<const int32_t*>(w + p->off_wend), segoff + 1, s));
+    SPG_TRY_HIP(launch_scan_inplace(segoff + 1, ndense * p->num_P, scan, s));
+    SPG_TRY_HIP(hipMemcpyAsync(&p->seg_total, segoff + ndense * p->num_P, sizeof(int64_t),
+                               hipMemcpyDeviceToHost, s));
+  }
+  SPG_TRY_HIP(hipMemcpyAsync(p->sub_counts, ctr + kCtrSub, kNumBins * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
   SPG_TRY_HIP(hipMemcpyAsync(p->num_counts, ctr + kCtrNum, kNumBins * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
   SPG_TRY_HIP(hipMemcpyAsync(&total, c_ptr + m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   SPG_TRY_HIP(hipStreamSynchronize(s));
   const BinOffsets no = offsets_of(p->num_counts);
   SPG_TRY_HIP(launch_fill_u64(reinterpret_cast<uint64_t*>(ctr + kCtrCursor), kNumBins, 0, s));
   SPG_TRY_HIP(launch_scatter(1, m, flops, c_ptr, p->bp, no, ctr + kCtrCursor, rows_num, s));
+  if (p->split && ndense > 0) {
+    const BinOffsets sbo = offsets_of(p->sub_counts);
+    SPG_TRY_HIP(launch_fill_u64(reinterpret_cast<uint64_t*>(ctr + kCtrSym), kNumBins, 0, s));
+    SPG_TRY_HIP(launch_sub_scatter(ndense, p->num_P, reinterpret_cast<const int32_t*>(w + p->off_subcnt), p->bp,
+                                   sbo, ctr + kCtrSym, reinterpret_cast<int32_t*>(w + p->off_subitems), s));
+  }
   SPG_TRY_HIP(hipGetLastError());
   p->c_nnz = total;
   p->c_ptr = c_ptr;
@@ -388,24 +537,79 @@ spg_status spg_numeric(spg_plan* p, void* ws, int32_t* c_idx, void* c_val) {
   int64_t ndense = 0;
   for (int b = kDenseBinBase; b < kNumBins; ++b) ndense += static_cast<int64_t>(p->num_counts[b]);
   p->ran[SPG_PHASE_NUM_HASH] = p->ran[SPG_PHASE_NUM_DENSE] = p->ran[SPG_PHASE_NUM_PANELS] = false;
+  p->ran[SPG_PHASE_NUM_EXPAND] = false;
+  const bool sub = p->split && p->n_dense_sym > 0;
+  const BinOffsets sbo = offsets_of(p->sub_counts);
+  int64_t nsub_dense = 0;
+  for (int b = kDenseBinBase; b < kNumBins; ++b) nsub_dense += static_cast<int64_t>(p->sub_counts[b]);
+  const int32_t* rows_dense_sym =
+      reinterpret_cast<const int32_t*>(w + p->off_rows_sym) + offsets_of(p->sym_counts).v[kDenseBinBase];
+  const int32_t* subitems = reinterpret_cast<const int32_t*>(w + p->off_subitems);
+  const int32_t* subcnt = reinterpret_cast<const int32_t*>(w + p->off_subcnt);
+  const int32_t* suboff = reinterpret_cast<const int32_t*>(w + p->off_suboff);
+  const int32_t* wend = reinterpret_cast<const int32_t*>(w + p->off_wend);
+  p->ran[SPG_PHASE_SEG_WRITE] = false;
+  if ((ndense > 0 || sub) && p->num_P > 1) {
+    if (p->ext_pnum) {
+      pnum = const_cast<int32_t*>(p->ext_pnum);
+    } else if (!p->pnum_ready) {
+      PhaseTimer tp(p, SPG_PHASE_NUM_PANELS);
+      SPG_TRY_HIP(launch_panel_index(op.b_ptr, op.b_idx, op.n, p->num_wlog2, p->num_P, pnum, s));
+    }
+  }
+  const bool use_segs = sub && p->seg_total <= p->seg_cap;
+  const auto* segoff = reinterpret_cast<const int64_t*>(w + p->off_segoff);
+  void* segs = w + p->off_segs;
+  if (use_segs) {
+    PhaseTimer tw(p, SPG_PHASE_SEG_WRITE);
+    SPG_TRY_HIP(launch_seg_write(op, rows_dense_sym, p->n_dense_sym, p->num_P, pnum, wend, segoff, segs, s));
+  }
   {
     PhaseTimer t(p, SPG_PHASE_NUM_HASH);
-    for (int c = 1; c < kDenseBinBase; ++c) {
+    for (int c = 1; c < kExpandBin; ++c) {
       if (!p->num_counts[c]) continue;
       SPG_TRY_HIP(launch_hash_num(p->sr, op, rows_num + no.v[c], static_cast<int64_t>(p->num_counts[c]),
                                   hash_table_size(c), hash_threads(c), p->opt.short_seg, p->c_ptr,
                                   c_idx, c_val, s));
     }
-  }
-  if (ndense > 0) {
-    if (p->num_P > 1) {
-      PhaseTimer tp(p, SPG_PHASE_NUM_PANELS);
-      SPG_TRY_HIP(launch_panel_index(op.b_ptr, op.b_idx, op.n, p->num_wlog2, p->num_P, pnum, s));
+    if (sub) {
+      for (int c = 1; c < kDenseBinBase; ++c) {
+        if (!p->sub_counts[c]) continue;
+        if (use_segs)
+          SPG_TRY_HIP(launch_hash_num_seg(p->sr, op, rows_dense_sym, subitems + sbo.v[c],
+                                          static_cast<int64_t>(p->sub_counts[c]), hash_table_size(c),
+                                          hash_threads(c), p->opt.short_seg, p->num_P, p->num_wlog2, segoff,
+                                          segs, subcnt, suboff, p->c_ptr, c_idx, c_val, s));
+        else
+          SPG_TRY_HIP(launch_hash_num_sub(p->sr, op, rows_dense_sym, subitems + sbo.v[c],
+                                          static_cast<int64_t>(p->sub_counts[c]), hash_table_size(c),
+                                          hash_threads(c), p->opt.short_seg, p->num_P, p->num_wlog2, pnum,
+                                          subcnt, suboff, wend, p->c_ptr, c_idx, c_val, s));
+      }
     }
+  }
+  if (p->num_counts[kExpandBin]) {
+    PhaseTimer t(p, SPG_PHASE_NUM_EXPAND);
+    SPG_TRY_HIP(launch_expand_rows(rows_num + no.v[kExpandBin], static_cast<int64_t>(p->num_counts[kExpandBin]),
+                                   static_cast<int>(p->keep_nwords),
+                                   reinterpret_cast<const uint32_t*>(w + p->off_store),
+                                   reinterpret_cast<const int32_t*>(w + p->off_rowslot), p->c_ptr, c_idx,
+                                   1024, s));
+  }
+  if (ndense > 0 || nsub_dense > 0) {
     PhaseTimer t(p, SPG_PHASE_NUM_DENSE);
-    SPG_TRY_HIP(launch_dense_num(p->sr, op, rows_num + no.v[kDenseBinBase], ndense, p->num_wlog2,
-                                 p->num_P, pnum, p->opt.dense_threads, p->opt.short_seg, p->c_ptr,
-                                 c_idx, c_val, s));
+    if (ndense > 0)
+      SPG_TRY_HIP(launch_dense_num(p->sr, op, rows_num + no.v[kDenseBinBase], ndense, p->num_wlog2,
+                                   p->num_P, pnum, p->opt.dense_threads, p->opt.short_seg, p->c_ptr,
+                                   c_idx, c_val, s));
+    if (sub && nsub_dense > 0 && use_segs)
+      SPG_TRY_HIP(launch_dense_num_seg(p->sr, op, rows_dense_sym, subitems + sbo.v[kDenseBinBase], nsub_dense,
+                                       p->opt.dense_threads, p->opt.short_seg, p->num_P, p->num_wlog2, segoff,
+                                       segs, subcnt, suboff, p->c_ptr, c_idx, c_val, s));
+    else if (sub && nsub_dense > 0)
+      SPG_TRY_HIP(launch_dense_num_sub(p->sr, op, rows_dense_sym, subitems + sbo.v[kDenseBinBase], nsub_dense,
+                                       p->opt.dense_threads, p->opt.short_seg, p->num_P, p->num_wlog2, pnum,
+                                       subcnt, suboff, p->c_ptr, c_idx, c_val, s));
   }
   return SPG_OK;
 }

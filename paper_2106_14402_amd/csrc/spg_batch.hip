@@ -307,6 +307,7 @@ spg_status spg_batch_plan_create(int nprod, const spg_matrix* A, const spg_matri
   }
   p->bp.hash_max_flops = p->opt.hash_max_flops;
   p->bp.hash_max_nnz = p->opt.hash_max_nnz;
+  p->bp.split_heavy = 0;
   p->desc.resize(nprod);
   p->slot_of.resize(nprod);
   p->row_off.assign(nprod + 1, 0);
@@ -611,10 +612,18 @@ spg_status spg_batch_graph_capture(spg_batch_plan* p, void* ws, int32_t* c_idx, 
     (void)hipGraphDestroy(p->graph);
     p->has_graph = false;
   }
-  SPG_TRY_HIP(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
-  st = enqueue_numeric(p, static_cast<unsigned char*>(ws));
+  // Capture on a private non-blocking stream (the null stream cannot be
+  // captured); the graph is launched later on the plan's stream.
+  hipStream_t cap = nullptr;
+  SPG_TRY_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+  hipStream_t saved = p->stream;
+  p->stream = cap;
+  hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) st = enqueue_numeric(p, static_cast<unsigned char*>(ws));
   hipGraph_t g = nullptr;
-  const hipError_t e = hipStreamEndCapture(p->stream, &g);
+  if (e == hipSuccess) e = hipStreamEndCapture(cap, &g);
+  p->stream = saved;
+  (void)hipStreamDestroy(cap);
   if (st != SPG_OK || e != hipSuccess || !g) {
     if (g) (void)hipGraphDestroy(g);
     return st != SPG_OK ? st : SPG_E_DEVICE;

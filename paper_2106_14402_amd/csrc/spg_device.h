@@ -259,10 +259,62 @@ __device__ __forceinline__ typename SR::In load_val(const void* v, int64_t p) {
 
 constexpr int kShortUnroll = 8;  // loads in flight per lane on a short segment
 
-template <class SR, class Sink>
-__device__ void enumerate_row(const Operands& op, int64_t a_lo, int64_t a_hi, bool paneled,
-                              const int32_t* __restrict__ pidx, int P, int p, int32_t c0,
-                              int short_seg, RowQueue<typename SR::In> q, Sink& sink) {
+// Where the segments of a row come from.  RowSource walks the A entries of
+// row i and looks the B segment up (whole row, or the part of it in one
+// column panel through the panel index).  SegSource walks a precomputed list
+// of non-empty segments of one (row, panel) piece.
+template <class SR>
+struct RowSource {
+  const Operands* op;
+  int64_t a_lo, a_hi;
+  bool paneled;
+  const int32_t* __restrict__ pidx;
+  int P, p;
+  int p_hi;  // panels [p, p_hi) form the column window (p_hi <= p means p + 1)
+  __device__ int64_t count() const { return a_hi - a_lo; }
+  __device__ void load(int64_t t, int64_t& lo, int32_t& len, typename SR::In& a) const {
+    const int64_t pa = a_lo + t;
+    const int32_t kk = op->a_idx[pa];
+    a = load_val<SR>(op->a_val, pa);
+    const int64_t bs = op->b_ptr[kk];
+    if (paneled) {
+      const int32_t* s = pidx + static_cast<int64_t>(kk) * (P + 1);
+      const int32_t s0 = s[p];
+      lo = bs + s0;
+      len = s[p_hi > p ? p_hi : p + 1] - s0;
+    } else {
+      lo = bs;
+      len = static_cast<int32_t>(op->b_ptr[kk + 1] - bs);
+    }
+  }
+};
+
+// One non-empty segment of a (row, panel) piece: entries [bpos, bpos+len) of
+// B, multiplied by A entry a_lo + apos.
+struct SegDesc {
+  int64_t bpos;
+  int32_t len;
+  int32_t apos;
+};
+
+template <class SR>
+struct SegSource {
+  const Operands* op;
+  int64_t a_lo;
+  const SegDesc* __restrict__ segs;
+  int64_t nseg;
+  __device__ int64_t count() const { return nseg; }
+  __device__ void load(int64_t t, int64_t& lo, int32_t& len, typename SR::In& a) const {
+    const SegDesc d = segs[t];
+    lo = d.bpos;
+    len = d.len;
+    a = load_val<SR>(op->a_val, a_lo + d.apos);
+  }
+};
+
+template <class SR, class Src, class Sink>
+__device__ void enumerate_src(const Operands& op, const Src& src, int32_t c0, int short_seg,
+                              RowQueue<typename SR::In> q, Sink& sink) {
   using In = typename SR::In;
   const int tid = threadIdx.x;
   const int nt = blockDim.x;
@@ -273,24 +325,12 @@ __device__ void enumerate_row(const Operands& op, int64_t a_lo, int64_t a_hi, bo
     q.ctr[1] = 0;
   }
   __syncthreads();
-  for (int64_t base = a_lo; base < a_hi; base += nt) {
-    const int64_t pa = base + tid;
+  const int64_t total = src.count();
+  for (int64_t base = 0; base < total; base += nt) {
     int64_t lo = 0;
     int32_t len = 0;
     In a = In(1);
-    if (pa < a_hi) {
-      const int32_t kk = op.a_idx[pa];
-      a = load_val<SR>(op.a_val, pa);
-      const int64_t bs = op.b_ptr[kk];
-      if (paneled) {
-        const int32_t* s = pidx + static_cast<int64_t>(kk) * (P + 1) + p;
-        lo = bs + s[0];
-        len = s[1] - s[0];
-      } else {
-        lo = bs;
-        len = static_cast<int32_t>(op.b_ptr[kk + 1] - bs);
-      }
-    }
+    if (base + tid < total) src.load(base + tid, lo, len, a);
     if (len > short_seg) {
       const int slot = atomicAdd(&q.ctr[0], 1);
       q.lo[slot] = lo;
@@ -365,6 +405,14 @@ __device__ void enumerate_row(const Operands& op, int64_t a_lo, int64_t a_hi, bo
     }
     __syncthreads();
   }
+}
+
+template <class SR, class Sink>
+__device__ void enumerate_row(const Operands& op, int64_t a_lo, int64_t a_hi, bool paneled,
+                              const int32_t* __restrict__ pidx, int P, int p, int32_t c0,
+                              int short_seg, RowQueue<typename SR::In> q, Sink& sink) {
+  RowSource<SR> src{&op, a_lo, a_hi, paneled, pidx, P, p, p + 1};
+  enumerate_src<SR>(op, src, c0, short_seg, q, sink);
 }
 
 __device__ __forceinline__ uint32_t hash_slot(int32_t key, uint32_t mask) {

@@ -127,7 +127,11 @@ __global__ void k_count_num_bins(int32_t m, const int64_t* __restrict__ flops,
   if (tid < kNumBins) lc[tid] = 0;
   __syncthreads();
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + tid;
-  if (i < m) atomicAdd(&lc[num_bin(c_ptr[i + 1], flops[i], bp)], 1u);
+  if (i < m) {
+    const bool split = bp.split_heavy && flops[i] > bp.hash_max_flops;
+    const bool kept = bp.row_slot && flops[i] > bp.hash_max_flops && bp.row_slot[i] >= 0;
+    atomicAdd(&lc[kept ? kExpandBin : (split ? 0 : num_bin(c_ptr[i + 1], flops[i], bp))], 1u);
+  }
   __syncthreads();
   if (tid < kNumBins && lc[tid]) atomicAdd(&counts[tid], static_cast<unsigned long long>(lc[tid]));
 }
@@ -155,7 +159,12 @@ __global__ void k_scatter(int mode, int32_t m, const int64_t* __restrict__ flops
   int bin = 0;
   unsigned int local = 0;
   if (i < m) {
-    bin = mode == 0 ? sym_bin(flops[i], bp) : num_bin(c_ptr[i + 1] - c_ptr[i], flops[i], bp);
+    if (mode == 0)
+      bin = sym_bin(flops[i], bp);
+    else if (bp.row_slot && flops[i] > bp.hash_max_flops && bp.row_slot[i] >= 0)
+      bin = kExpandBin;
+    else
+      bin = (bp.split_heavy && flops[i] > bp.hash_max_flops) ? 0 : num_bin(c_ptr[i + 1] - c_ptr[i], flops[i], bp);
     if (bin > 0) local = atomicAdd(&lc[bin], 1u);
   }
   __syncthreads();
@@ -365,9 +374,17 @@ __device__ int64_t hash_sym_row(const Operands& op, int32_t row, int T, int shor
   return block_sum(sink.count, q.ctr + 2);
 }
 
+// Dense symbolic row.  With sub_cnt, also records the pattern size of every
+// numeric column panel (2^sub_wlog2 columns, no wider than a bitmap panel),
+// so a heavy row can later be split into (row, panel) pieces.
 __device__ int64_t dense_sym_row(const Operands& op, int32_t row, int wlog2, int P,
-                                 const int32_t* __restrict__ pidx, int short_seg, unsigned char* smem) {
+                                 const int32_t* __restrict__ pidx, int short_seg, unsigned char* smem,
+                                 int sub_wlog2 = 0, int32_t* __restrict__ sub_cnt = nullptr,
+                                 uint32_t* __restrict__ keep = nullptr) {
   const int nt = blockDim.x;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x >> 6;
+  const int nw = nt >> 6;
   auto q = PatQueue::carve(smem, nt);
   uint32_t* bits = reinterpret_cast<uint32_t*>(smem + PatQueue::bytes(nt));
   const int64_t a_lo = op.a_ptr[row], a_hi = op.a_ptr[row + 1];
@@ -380,8 +397,23 @@ __device__ int64_t dense_sym_row(const Operands& op, int32_t row, int wlog2, int
     __syncthreads();
     BitmapSink sink{bits};
     enumerate_row<SrPattern>(op, a_lo, a_hi, P > 1, pidx, P, p, c0, short_seg, q, sink);
+    if (sub_cnt) {
+      const int wps = 1 << (sub_wlog2 - 5);  // words per numeric panel
+      const int s0 = c0 >> sub_wlog2;
+      const int nsub = (wcols + (1 << sub_wlog2) - 1) >> sub_wlog2;
+      for (int j = wid; j < nsub; j += nw) {
+        int c = 0;
+        for (int t = j * wps + lane; t < min((j + 1) * wps, nwords); t += kWave) c += __popc(bits[t]);
+        c = wave_sum(c);
+        if (lane == 0) sub_cnt[s0 + j] = c;
+      }
+    }
     int cnt = 0;
-    for (int t = threadIdx.x; t < nwords; t += nt) cnt += __popc(bits[t]);
+    for (int t = threadIdx.x; t < nwords; t += nt) {
+      const uint32_t x = bits[t];
+      cnt += __popc(x);
+      if (keep) keep[t] = x;
+    }
     total += block_sum(cnt, q.ctr + 2);
   }
   return total;
@@ -414,11 +446,29 @@ __global__ __launch_bounds__(1024) void k_hash_sym(Operands op, const int32_t* _
 __global__ __launch_bounds__(1024) void k_dense_sym(Operands op, const int32_t* __restrict__ rows,
                                                     int64_t nrows, int wlog2, int P,
                                                     const int32_t* __restrict__ pidx, int short_seg,
-                                                    int64_t* __restrict__ c_ptr) {
+                                                    int64_t* __restrict__ c_ptr, int sub_wlog2, int subP,
+                                                    int32_t* __restrict__ sub_cnt, KeepBitmaps kb) {
   extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int slot_s;
   for (int64_t it = blockIdx.x; it < nrows; it += gridDim.x) {
     const int32_t row = rows[it];
-    const int64_t nz = dense_sym_row(op, row, wlog2, P, pidx, short_seg, smem);
+    uint32_t* keep = nullptr;
+    if (kb.store) {
+      // The heaviest rows come first; each takes a bitmap slot while any is left.
+      if (threadIdx.x == 0) {
+        int sl = -1;
+        if (kb.flops[row] >= kb.min_flops) {
+          const unsigned int v = atomicAdd(kb.counter, 1u);
+          if (v < kb.capacity) sl = static_cast<int>(v);
+        }
+        slot_s = sl;
+        kb.row_slot[row] = sl;
+      }
+      __syncthreads();
+      if (slot_s >= 0) keep = kb.store + static_cast<int64_t>(slot_s) * kb.nwords;
+    }
+    const int64_t nz = dense_sym_row(op, row, wlog2, P, pidx, short_seg, smem, sub_wlog2,
+                                     sub_cnt ? sub_cnt + it * subP : nullptr, keep);
     if (threadIdx.x == 0) c_ptr[row + 1] = nz;
     __syncthreads();
   }
@@ -469,10 +519,179 @@ hipError_t launch_hash_sym(const Operands& op, const int32_t* rows, int64_t nrow
 
 hipError_t launch_dense_sym(const Operands& op, const int32_t* rows, int64_t nrows, int wlog2, int P,
                             const int32_t* pidx, int nt, int short_seg, int64_t* c_ptr,
-                            hipStream_t s) {
+                            hipStream_t s, int sub_wlog2, int subP, int32_t* sub_cnt, KeepBitmaps kb) {
   if (nrows <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_dense_sym, dim3(grid_for(nrows, 0)), dim3(nt), dense_sym_lds(wlog2, nt), s, op,
-                     rows, nrows, wlog2, P, pidx, short_seg, c_ptr);
+                     rows, nrows, wlog2, P, pidx, short_seg, c_ptr, sub_wlog2, subP, sub_cnt, kb);
+  return hipGetLastError();
+}
+
+// Numeric phase of a pattern-only row whose bitmap the symbolic phase kept:
+// load it into LDS and emit its set bits in column order.
+__device__ void emit_bitmap(const uint32_t* bits, int nwords, int64_t out, int64_t out_end,
+                            int32_t* __restrict__ c_idx, int* tmp) {
+  const int nt = blockDim.x;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x >> 6;
+  const int nw = nt >> 6;
+  const int wpw = (((nwords + nw - 1) / nw) + kWave - 1) & ~(kWave - 1);
+  const int w_begin = min(nwords, wid * wpw);
+  const int w_end = min(nwords, w_begin + wpw);
+  int cnt = 0;
+  for (int w = w_begin + lane; w < w_end; w += kWave) cnt += __popc(bits[w]);
+  cnt = wave_sum(cnt);
+  int ptotal;
+  const int woff = __shfl(block_exclusive_scan(lane == 0 ? cnt : 0, tmp, &ptotal), 0, kWave);
+  int64_t o_base = out + woff;
+  for (int w0 = w_begin; w0 < w_end; w0 += kWave) {
+    const int w = w0 + lane;
+    const uint32_t word = w < w_end ? bits[w] : 0u;
+    const int c = __popc(word);
+    const int incl = wave_inclusive_scan(c);
+    int64_t o = o_base + (incl - c);
+    uint32_t x = word;
+    while (x) {
+      const int b = __ffs(x) - 1;
+      if (o < out_end) c_idx[o] = (w << 5) + b;
+      x &= x - 1;
+      ++o;
+    }
+    o_base += __shfl(incl, kWave - 1, kWave);
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_expand_rows(const int32_t* __restrict__ rows, int64_t nrows,
+                                                      int nwords, const uint32_t* __restrict__ store,
+                                                      const int32_t* __restrict__ row_slot,
+                                                      const int64_t* __restrict__ c_ptr,
+                                                      int32_t* __restrict__ c_idx) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  int* tmp = reinterpret_cast<int*>(smem);
+  uint32_t* bits = reinterpret_cast<uint32_t*>(smem + 256);
+  for (int64_t it = blockIdx.x; it < nrows; it += gridDim.x) {
+    const int32_t row = rows[it];
+    const uint32_t* src = store + static_cast<int64_t>(row_slot[row]) * nwords;
+    for (int t = threadIdx.x; t < nwords; t += blockDim.x) bits[t] = src[t];
+    __syncthreads();
+    emit_bitmap(bits, nwords, c_ptr[row], c_ptr[row + 1], c_idx, tmp);
+    __syncthreads();
+  }
+}
+
+hipError_t launch_expand_rows(const int32_t* rows, int64_t nrows, int nwords, const uint32_t* store,
+                              const int32_t* row_slot, const int64_t* c_ptr, int32_t* c_idx, int nt,
+                              hipStream_t s) {
+  if (nrows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_expand_rows, dim3(grid_for(nrows, 0)), dim3(nt),
+                     256 + static_cast<size_t>(nwords) * 4, s, rows, nrows, nwords, store, row_slot, c_ptr,
+                     c_idx);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// (row, panel) pieces of heavy rows for the numeric phase.  Piece g of slot
+// `slot` (the row's position in the dense symbolic list) and panel p is
+// g = slot * subP + p; its entries go to c_ptr[row] + sub_off[g].
+// ---------------------------------------------------------------------------
+__host__ __device__ inline int sub_bin(int64_t cnt, const BinParams& bp) {
+  if (cnt <= 0) return 0;
+  if (cnt <= bp.hash_max_nnz) return hash_class(cnt);
+  return dense_bin(cnt);
+}
+
+__global__ void k_sub_offsets(int64_t nslots, int subP, const int32_t* __restrict__ cnt,
+                              int32_t* __restrict__ off) {
+  const int64_t slot = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (slot >= nslots) return;
+  int32_t run = 0;
+  for (int p = 0; p < subP; ++p) {
+    off[slot * subP + p] = run;
+    run += cnt[slot * subP + p];
+  }
+}
+
+// Group the column panels of each heavy row into windows: consecutive panels
+// are merged while the window holds at most `cap` entries; a panel above cap
+// is a window by itself (dense accumulator).  cnt becomes the window size at
+// each window's first panel and 0 elsewhere; wend[g] is the window's end
+// panel at its first panel.  The entry offsets (sub_off) do not change.
+__global__ void k_sub_windows(int64_t nslots, int subP, int32_t cap, int32_t* __restrict__ cnt,
+                              int32_t* __restrict__ wend) {
+  const int64_t slot = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (slot >= nslots) return;
+  int32_t* c = cnt + slot * subP;
+  int32_t* e = wend + slot * subP;
+  int p = 0;
+  while (p < subP) {
+    int32_t sum = c[p];
+    int q = p + 1;
+    if (sum <= cap) {
+      while (q < subP && sum + c[q] <= cap) {
+        sum += c[q];
+        c[q] = 0;
+        e[q] = q + 1;
+        ++q;
+      }
+    }
+    c[p] = sum;
+    e[p] = q;
+    p = q;
+  }
+}
+
+__global__ void k_sub_count(int64_t nitems, const int32_t* __restrict__ cnt, BinParams bp,
+                            unsigned long long* counts) {
+  __shared__ unsigned int lc[kNumBins];
+  const int tid = threadIdx.x;
+  if (tid < kNumBins) lc[tid] = 0;
+  __syncthreads();
+  const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + tid;
+  if (g < nitems) atomicAdd(&lc[sub_bin(cnt[g], bp)], 1u);
+  __syncthreads();
+  if (tid < kNumBins && lc[tid]) atomicAdd(&counts[tid], static_cast<unsigned long long>(lc[tid]));
+}
+
+__global__ void k_sub_scatter(int64_t nitems, const int32_t* __restrict__ cnt, BinParams bp,
+                              BinOffsets offs, unsigned long long* cursors, int32_t* __restrict__ items) {
+  __shared__ unsigned int lc[kNumBins];
+  __shared__ unsigned long long lbase[kNumBins];
+  const int tid = threadIdx.x;
+  if (tid < kNumBins) lc[tid] = 0;
+  __syncthreads();
+  const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + tid;
+  int bin = 0;
+  unsigned int local = 0;
+  if (g < nitems) {
+    bin = sub_bin(cnt[g], bp);
+    if (bin > 0) local = atomicAdd(&lc[bin], 1u);
+  }
+  __syncthreads();
+  if (tid < kNumBins && lc[tid])
+    lbase[tid] = atomicAdd(&cursors[tid], static_cast<unsigned long long>(lc[tid]));
+  __syncthreads();
+  if (bin > 0) items[offs.v[bin] + static_cast<int64_t>(lbase[bin]) + local] = static_cast<int32_t>(g);
+}
+
+hipError_t launch_sub_prepare(int64_t nslots, int subP, int32_t* cnt, int32_t* off, int32_t* wend,
+                              BinParams bp, unsigned long long* counts, hipStream_t s) {
+  if (nslots <= 0) return hipSuccess;
+  const int64_t nitems = nslots * subP;
+  hipLaunchKernelGGL(k_sub_offsets, dim3(static_cast<unsigned>((nslots + 255) / 256)), dim3(256), 0, s,
+                     nslots, subP, cnt, off);
+  hipLaunchKernelGGL(k_sub_windows, dim3(static_cast<unsigned>((nslots + 255) / 256)), dim3(256), 0, s,
+                     nslots, subP, static_cast<int32_t>(bp.hash_max_nnz), cnt, wend);
+  hipLaunchKernelGGL(k_sub_count, dim3(static_cast<unsigned>((nitems + 255) / 256)), dim3(256), 0, s,
+                     nitems, cnt, bp, counts);
+  return hipGetLastError();
+}
+
+hipError_t launch_sub_scatter(int64_t nslots, int subP, const int32_t* cnt, BinParams bp,
+                              const BinOffsets& offs, unsigned long long* cursors, int32_t* items,
+                              hipStream_t s) {
+  if (nslots <= 0) return hipSuccess;
+  const int64_t nitems = nslots * subP;
+  hipLaunchKernelGGL(k_sub_scatter, dim3(static_cast<unsigned>((nitems + 255) / 256)), dim3(256), 0, s,
+                     nitems, cnt, bp, offs, cursors, items);
   return hipGetLastError();
 }
 
@@ -525,9 +744,9 @@ constexpr int kMaxSlotsPerThread = 16;
 
 // LDS hash accumulator for one row, then compaction, bitonic sort and
 // coalesced stores of the row's entries into [out, out_end).
-template <class SR>
-__device__ void hash_num_row(const Operands& op, int32_t row, int T, int short_seg, int64_t out,
-                             int64_t out_end, int32_t* __restrict__ c_idx,
+template <class SR, class Src>
+__device__ void hash_num_src(const Operands& op, const Src& src, int32_t c0, int T, int short_seg,
+                             int64_t out, int64_t out_end, int32_t* __restrict__ c_idx,
                              typename SR::Out* __restrict__ c_val, unsigned char* smem) {
   using S = typename SR::S;
   const int nt = blockDim.x;
@@ -541,8 +760,7 @@ __device__ void hash_num_row(const Operands& op, int32_t row, int T, int short_s
   }
   __syncthreads();
   HashMapSink<SR> sink{keys, vals, static_cast<uint32_t>(T - 1)};
-  enumerate_row<SR>(op, op.a_ptr[row], op.a_ptr[row + 1], false, nullptr, 1, 0, 0, short_seg, q,
-                    sink);
+  enumerate_src<SR>(op, src, c0, short_seg, q, sink);
   // Compact occupied slots to the front: every thread takes a contiguous
   // block of T/nt slots into registers, then writes them at its scanned offset.
   const int per = T / nt;
@@ -578,19 +796,29 @@ __device__ void hash_num_row(const Operands& op, int32_t row, int T, int short_s
   // row's range of C regardless.
   const int lim = static_cast<int>(min(static_cast<int64_t>(nnz), out_end - out));
   for (int e = tid; e < lim; e += nt) {
-    c_idx[out + e] = keys[e];
+    c_idx[out + e] = keys[e] + c0;
     if constexpr (!SR::kPattern) c_val[out + e] = SR::out(vals[e]);
   }
   __syncthreads();
 }
 
+template <class SR>
+__device__ void hash_num_row(const Operands& op, int32_t row, int T, int short_seg, int64_t out,
+                             int64_t out_end, int32_t* __restrict__ c_idx,
+                             typename SR::Out* __restrict__ c_val, unsigned char* smem,
+                             bool paneled = false, const int32_t* __restrict__ pidx = nullptr, int P = 1,
+                             int p = 0, int32_t c0 = 0, int p_hi = 0) {
+  RowSource<SR> src{&op, op.a_ptr[row], op.a_ptr[row + 1], paneled, pidx, P, p, p_hi};
+  hash_num_src<SR>(op, src, c0, T, short_seg, out, out_end, c_idx, c_val, smem);
+}
+
 // Dense LDS panel accumulator for one row: presence bits plus one value per
 // column of the panel, emitted in column order into [out, out_end).
-template <class SR>
-__device__ void dense_num_row(const Operands& op, int32_t row, int wlog2, int P,
-                              const int32_t* __restrict__ pidx, int short_seg, int64_t out,
-                              int64_t out_end, int32_t* __restrict__ c_idx,
-                              typename SR::Out* __restrict__ c_val, unsigned char* smem) {
+template <class SR, class MakeSrc>
+__device__ void dense_num_gen(const Operands& op, int wlog2, int p_begin, int p_end, int short_seg,
+                              int64_t out, int64_t out_end, int32_t* __restrict__ c_idx,
+                              typename SR::Out* __restrict__ c_val, unsigned char* smem,
+                              const MakeSrc& make) {
   using S = typename SR::S;
   using Q = RowQueue<typename SR::In>;
   const int nt = blockDim.x;
@@ -603,19 +831,18 @@ __device__ void dense_num_row(const Operands& op, int32_t row, int wlog2, int P,
   unsigned char* p0 = smem + Q::bytes(nt);
   uint32_t* bits = reinterpret_cast<uint32_t*>(p0);
   S* vals = reinterpret_cast<S*>(p0 + static_cast<size_t>(W) / 8);
-  const int64_t a_lo = op.a_ptr[row], a_hi = op.a_ptr[row + 1];
   const int32_t wcols_max = min(W, op.k);
   for (int t = tid; t < (wcols_max + 31) >> 5; t += nt) bits[t] = 0u;
   if constexpr (!SR::kPattern) {
     for (int t = tid; t < wcols_max; t += nt) vals[t] = SR::identity();
   }
   __syncthreads();
-  for (int p = 0; p < P; ++p) {
+  for (int p = p_begin; p < p_end; ++p) {
     const int32_t c0 = p << wlog2;
     const int32_t wcols = min(W, op.k - c0);
     const int nwords = (wcols + 31) >> 5;
     DenseSink<SR> sink{bits, vals};
-    enumerate_row<SR>(op, a_lo, a_hi, P > 1, pidx, P, p, c0, short_seg, q, sink);
+    enumerate_src<SR>(op, make(p), c0, short_seg, q, sink);
     // Emit the panel in column order.  Wave w owns a contiguous range of
     // words; one block scan of the wave totals places the ranges, then each
     // wave walks its range 64 words at a time with no further barriers.
@@ -657,6 +884,18 @@ __device__ void dense_num_row(const Operands& op, int32_t row, int wlog2, int P,
 }
 
 template <class SR>
+__device__ void dense_num_row(const Operands& op, int32_t row, int wlog2, int P,
+                              const int32_t* __restrict__ pidx, int short_seg, int64_t out,
+                              int64_t out_end, int32_t* __restrict__ c_idx,
+                              typename SR::Out* __restrict__ c_val, unsigned char* smem,
+                              int p_begin = 0, int p_end = -1) {
+  const int64_t a_lo = op.a_ptr[row], a_hi = op.a_ptr[row + 1];
+  auto make = [&](int p) { return RowSource<SR>{&op, a_lo, a_hi, P > 1, pidx, P, p, p + 1}; };
+  dense_num_gen<SR>(op, wlog2, p_begin, p_end < 0 ? P : p_end, short_seg, out, out_end, c_idx, c_val, smem,
+                    make);
+}
+
+template <class SR>
 __global__ __launch_bounds__(1024) void k_hash_num(Operands op, const int32_t* __restrict__ rows,
                                                    int64_t nrows, int T, int short_seg,
                                                    const int64_t* __restrict__ c_ptr,
@@ -681,6 +920,185 @@ __global__ __launch_bounds__(1024) void k_dense_num(Operands op, const int32_t* 
     const int32_t row = rows[it];
     dense_num_row<SR>(op, row, wlog2, P, pidx, short_seg, c_ptr[row], c_ptr[row + 1], c_idx, c_val,
                       smem);
+  }
+}
+
+// (row, panel) pieces of heavy rows: one panel of one row per work item.
+template <class SR>
+__global__ __launch_bounds__(1024) void k_hash_num_sub(Operands op, const int32_t* __restrict__ rows,
+                                                       const int32_t* __restrict__ items, int64_t nitems,
+                                                       int T, int short_seg, int subP, int sub_wlog2,
+                                                       const int32_t* __restrict__ pidx,
+                                                       const int32_t* __restrict__ sub_cnt,
+                                                       const int32_t* __restrict__ sub_off,
+                                                       const int32_t* __restrict__ wend,
+                                                       const int64_t* __restrict__ c_ptr,
+                                                       int32_t* __restrict__ c_idx,
+                                                       typename SR::Out* __restrict__ c_val) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const int32_t g = items[it];
+    const int32_t slot = g / subP;
+    const int p = g - slot * subP;
+    const int32_t row = rows[slot];
+    const int64_t out = c_ptr[row] + sub_off[g];
+    hash_num_row<SR>(op, row, T, short_seg, out, out + sub_cnt[g], c_idx, c_val, smem, true, pidx, subP,
+                     p, p << sub_wlog2, wend[g]);
+  }
+}
+
+template <class SR>
+__global__ __launch_bounds__(1024) void k_dense_num_sub(Operands op, const int32_t* __restrict__ rows,
+                                                        const int32_t* __restrict__ items, int64_t nitems,
+                                                        int short_seg, int subP, int sub_wlog2,
+                                                        const int32_t* __restrict__ pidx,
+                                                        const int32_t* __restrict__ sub_cnt,
+                                                        const int32_t* __restrict__ sub_off,
+                                                        const int64_t* __restrict__ c_ptr,
+                                                        int32_t* __restrict__ c_idx,
+                                                        typename SR::Out* __restrict__ c_val) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const int32_t g = items[it];
+    const int32_t slot = g / subP;
+    const int p = g - slot * subP;
+    const int32_t row = rows[slot];
+    const int64_t out = c_ptr[row] + sub_off[g];
+    dense_num_row<SR>(op, row, sub_wlog2, subP, pidx, short_seg, out, out + sub_cnt[g], c_idx, c_val, smem,
+                      p, p + 1);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Segment lists of (row, panel) pieces: every non-empty segment of a heavy
+// row, bucketed by column panel, so a piece walks only its own segments.
+// Slot s is the row's position in the dense symbolic list; piece g = s*P + p.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_seg_count(Operands op, const int32_t* __restrict__ rows,
+                                                   int64_t nslots, int P, const int32_t* __restrict__ pidx,
+                                                   const int32_t* __restrict__ wend,
+                                                   int64_t* __restrict__ cnt_out) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  unsigned int* lc = reinterpret_cast<unsigned int*>(smem);
+  int32_t* we = reinterpret_cast<int32_t*>(smem + static_cast<size_t>(P) * 4);
+  for (int64_t slot = blockIdx.x; slot < nslots; slot += gridDim.x) {
+    for (int t = threadIdx.x; t < P; t += blockDim.x) {
+      lc[t] = 0u;
+      we[t] = wend[slot * P + t];
+    }
+    __syncthreads();
+    const int32_t row = rows[slot];
+    for (int64_t e = op.a_ptr[row] + threadIdx.x; e < op.a_ptr[row + 1]; e += blockDim.x) {
+      const int32_t* sp = pidx + static_cast<int64_t>(op.a_idx[e]) * (P + 1);
+      for (int p = 0; p < P;) {
+        const int q = we[p];
+        if (sp[q] > sp[p]) atomicAdd(&lc[p], 1u);
+        p = q;
+      }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < P; t += blockDim.x) cnt_out[slot * P + t] = lc[t];
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void k_seg_write(Operands op, const int32_t* __restrict__ rows,
+                                                   int64_t nslots, int P, const int32_t* __restrict__ pidx,
+                                                   const int32_t* __restrict__ wend,
+                                                   const int64_t* __restrict__ segoff,
+                                                   SegDesc* __restrict__ segs) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  unsigned long long* cur = reinterpret_cast<unsigned long long*>(smem);
+  int32_t* we = reinterpret_cast<int32_t*>(smem + static_cast<size_t>(P) * 8);
+  for (int64_t slot = blockIdx.x; slot < nslots; slot += gridDim.x) {
+    for (int t = threadIdx.x; t < P; t += blockDim.x) {
+      cur[t] = static_cast<unsigned long long>(segoff[slot * P + t]);
+      we[t] = wend[slot * P + t];
+    }
+    __syncthreads();
+    const int32_t row = rows[slot];
+    const int64_t a_lo = op.a_ptr[row];
+    for (int64_t e = a_lo + threadIdx.x; e < op.a_ptr[row + 1]; e += blockDim.x) {
+      const int32_t k = op.a_idx[e];
+      const int64_t bs = op.b_ptr[k];
+      const int32_t* sp = pidx + static_cast<int64_t>(k) * (P + 1);
+      for (int p = 0; p < P;) {
+        const int q = we[p];
+        const int32_t s0 = sp[p], s1 = sp[q];
+        if (s1 > s0) {
+          const unsigned long long pos = atomicAdd(&cur[p], 1ull);
+          segs[pos] = SegDesc{bs + s0, s1 - s0, static_cast<int32_t>(e - a_lo)};
+        }
+        p = q;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_seg_count(const Operands& op, const int32_t* rows, int64_t nslots, int P,
+                            const int32_t* pidx, const int32_t* wend, int64_t* cnt_out, hipStream_t s) {
+  if (nslots <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_seg_count, dim3(grid_for(nslots, 0)), dim3(256), static_cast<size_t>(P) * 8, s, op, rows,
+                     nslots, P, pidx, wend, cnt_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_seg_write(const Operands& op, const int32_t* rows, int64_t nslots, int P,
+                            const int32_t* pidx, const int32_t* wend, const int64_t* segoff, void* segs,
+                            hipStream_t s) {
+  if (nslots <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_seg_write, dim3(grid_for(nslots, 0)), dim3(256), static_cast<size_t>(P) * 12, s, op, rows,
+                     nslots, P, pidx, wend, segoff, static_cast<SegDesc*>(segs));
+  return hipGetLastError();
+}
+
+template <class SR>
+__global__ __launch_bounds__(1024) void k_hash_num_seg(Operands op, const int32_t* __restrict__ rows,
+                                                       const int32_t* __restrict__ items, int64_t nitems,
+                                                       int T, int short_seg, int subP, int sub_wlog2,
+                                                       const int64_t* __restrict__ segoff,
+                                                       const SegDesc* __restrict__ segs,
+                                                       const int32_t* __restrict__ sub_cnt,
+                                                       const int32_t* __restrict__ sub_off,
+                                                       const int64_t* __restrict__ c_ptr,
+                                                       int32_t* __restrict__ c_idx,
+                                                       typename SR::Out* __restrict__ c_val) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const int32_t g = items[it];
+    const int32_t slot = g / subP;
+    const int p = g - slot * subP;
+    const int32_t row = rows[slot];
+    SegSource<SR> src{&op, op.a_ptr[row], segs + segoff[g], segoff[g + 1] - segoff[g]};
+    const int64_t out = c_ptr[row] + sub_off[g];
+    hash_num_src<SR>(op, src, p << sub_wlog2, T, short_seg, out, out + sub_cnt[g], c_idx, c_val, smem);
+  }
+}
+
+template <class SR>
+__global__ __launch_bounds__(1024) void k_dense_num_seg(Operands op, const int32_t* __restrict__ rows,
+                                                        const int32_t* __restrict__ items, int64_t nitems,
+                                                        int short_seg, int subP, int sub_wlog2,
+                                                        const int64_t* __restrict__ segoff,
+                                                        const SegDesc* __restrict__ segs,
+                                                        const int32_t* __restrict__ sub_cnt,
+                                                        const int32_t* __restrict__ sub_off,
+                                                        const int64_t* __restrict__ c_ptr,
+                                                        int32_t* __restrict__ c_idx,
+                                                        typename SR::Out* __restrict__ c_val) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const int32_t g = items[it];
+    const int32_t slot = g / subP;
+    const int p = g - slot * subP;
+    const int32_t row = rows[slot];
+    const int64_t a_lo = op.a_ptr[row];
+    const SegDesc* sg = segs + segoff[g];
+    const int64_t ns = segoff[g + 1] - segoff[g];
+    auto make = [&](int) { return SegSource<SR>{&op, a_lo, sg, ns}; };
+    const int64_t out = c_ptr[row] + sub_off[g];
+    dense_num_gen<SR>(op, sub_wlog2, p, p + 1, short_seg, out, out + sub_cnt[g], c_idx, c_val, smem, make);
   }
 }
 
@@ -769,6 +1187,59 @@ static hipError_t dense_num_b_t(const BatchDesc* descs, const int64_t* row_off, 
   return hipGetLastError();
 }
 
+template <class SR>
+static hipError_t hash_num_sub_t(const Operands& op, const int32_t* rows, const int32_t* items,
+                                 int64_t nitems, int T, int nt, int short_seg, int subP, int sub_wlog2,
+                                 const int32_t* pidx, const int32_t* cnt, const int32_t* off,
+                                 const int32_t* wend, const int64_t* c_ptr, int32_t* c_idx, void* c_val,
+                                 hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_hash_num_sub<SR>, dim3(grid_for(nitems, 0)), dim3(nt), hash_num_lds_t<SR>(T, nt), s,
+                     op, rows, items, nitems, T, short_seg, subP, sub_wlog2, pidx, cnt, off, wend, c_ptr, c_idx,
+                     static_cast<typename SR::Out*>(c_val));
+  return hipGetLastError();
+}
+
+template <class SR>
+static hipError_t dense_num_sub_t(const Operands& op, const int32_t* rows, const int32_t* items,
+                                  int64_t nitems, int nt, int short_seg, int subP, int sub_wlog2,
+                                  const int32_t* pidx, const int32_t* cnt, const int32_t* off,
+                                  const int64_t* c_ptr, int32_t* c_idx, void* c_val, hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_dense_num_sub<SR>, dim3(grid_for(nitems, 0)), dim3(nt),
+                     dense_num_lds_t<SR>(sub_wlog2, nt), s, op, rows, items, nitems, short_seg, subP,
+                     sub_wlog2, pidx, cnt, off, c_ptr, c_idx, static_cast<typename SR::Out*>(c_val));
+  return hipGetLastError();
+}
+
+template <class SR>
+static hipError_t hash_num_seg_t(const Operands& op, const int32_t* rows, const int32_t* items,
+                                 int64_t nitems, int T, int nt, int short_seg, int subP, int sub_wlog2,
+                                 const int64_t* segoff, const void* segs, const int32_t* cnt,
+                                 const int32_t* off, const int64_t* c_ptr, int32_t* c_idx, void* c_val,
+                                 hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_hash_num_seg<SR>, dim3(grid_for(nitems, 0)), dim3(nt), hash_num_lds_t<SR>(T, nt), s,
+                     op, rows, items, nitems, T, short_seg, subP, sub_wlog2, segoff,
+                     static_cast<const SegDesc*>(segs), cnt, off, c_ptr, c_idx,
+                     static_cast<typename SR::Out*>(c_val));
+  return hipGetLastError();
+}
+
+template <class SR>
+static hipError_t dense_num_seg_t(const Operands& op, const int32_t* rows, const int32_t* items,
+                                  int64_t nitems, int nt, int short_seg, int subP, int sub_wlog2,
+                                  const int64_t* segoff, const void* segs, const int32_t* cnt,
+                                  const int32_t* off, const int64_t* c_ptr, int32_t* c_idx, void* c_val,
+                                  hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_dense_num_seg<SR>, dim3(grid_for(nitems, 0)), dim3(nt),
+                     dense_num_lds_t<SR>(sub_wlog2, nt), s, op, rows, items, nitems, short_seg, subP,
+                     sub_wlog2, segoff, static_cast<const SegDesc*>(segs), cnt, off, c_ptr, c_idx,
+                     static_cast<typename SR::Out*>(c_val));
+  return hipGetLastError();
+}
+
 #define SPG_DISPATCH(sr, FN, ...)                           \
   switch (sr) {                                            \
     case 0: return FN<SrPlusTimesF64>(__VA_ARGS__);        \
@@ -806,6 +1277,43 @@ hipError_t launch_dense_num_b(int sr, const BatchDesc* descs, const int64_t* row
   SPG_DISPATCH(sr, dense_num_b_t, descs, row_off, nprod, items, nitems, wlog2_max, nt, short_seg,
                grid_cap, s)
 }
+
+hipError_t launch_hash_num_sub(int sr, const Operands& op, const int32_t* rows, const int32_t* items,
+                               int64_t nitems, int T, int nt, int short_seg, int subP, int sub_wlog2,
+                               const int32_t* pidx, const int32_t* cnt, const int32_t* off,
+                               const int32_t* wend, const int64_t* c_ptr, int32_t* c_idx, void* c_val,
+                               hipStream_t s) {
+  SPG_DISPATCH(sr, hash_num_sub_t, op, rows, items, nitems, T, nt, short_seg, subP, sub_wlog2, pidx, cnt,
+               off, wend, c_ptr, c_idx, c_val, s)
+}
+
+hipError_t launch_dense_num_sub(int sr, const Operands& op, const int32_t* rows, const int32_t* items,
+                                int64_t nitems, int nt, int short_seg, int subP, int sub_wlog2,
+                                const int32_t* pidx, const int32_t* cnt, const int32_t* off,
+                                const int64_t* c_ptr, int32_t* c_idx, void* c_val, hipStream_t s) {
+  SPG_DISPATCH(sr, dense_num_sub_t, op, rows, items, nitems, nt, short_seg, subP, sub_wlog2, pidx, cnt,
+               off, c_ptr, c_idx, c_val, s)
+}
+
+hipError_t launch_hash_num_seg(int sr, const Operands& op, const int32_t* rows, const int32_t* items,
+                               int64_t nitems, int T, int nt, int short_seg, int subP, int sub_wlog2,
+                               const int64_t* segoff, const void* segs, const int32_t* cnt,
+                               const int32_t* off, const int64_t* c_ptr, int32_t* c_idx, void* c_val,
+                               hipStream_t s) {
+  SPG_DISPATCH(sr, hash_num_seg_t, op, rows, items, nitems, T, nt, short_seg, subP, sub_wlog2, segoff, segs,
+               cnt, off, c_ptr, c_idx, c_val, s)
+}
+
+hipError_t launch_dense_num_seg(int sr, const Operands& op, const int32_t* rows, const int32_t* items,
+                                int64_t nitems, int nt, int short_seg, int subP, int sub_wlog2,
+                                const int64_t* segoff, const void* segs, const int32_t* cnt,
+                                const int32_t* off, const int64_t* c_ptr, int32_t* c_idx, void* c_val,
+                                hipStream_t s) {
+  SPG_DISPATCH(sr, dense_num_seg_t, op, rows, items, nitems, nt, short_seg, subP, sub_wlog2, segoff, segs,
+               cnt, off, c_ptr, c_idx, c_val, s)
+}
+
+size_t seg_desc_bytes() { return sizeof(SegDesc); }
 
 size_t hash_num_lds(int sr, int T, int nt) { SPG_DISPATCH(sr, hash_num_lds_t, T, nt) }
 size_t dense_num_lds(int sr, int wlog2, int nt) { SPG_DISPATCH(sr, dense_num_lds_t, wlog2, nt) }

@@ -15,6 +15,20 @@ constexpr int kScanTile = 8192;    // elements per scan block
 struct BinParams {
   int64_t hash_max_flops;  // symbolic: hash when flops <= this
   int64_t hash_max_nnz;    // numeric: hash when nnz <= this
+  int64_t split_heavy;     // numeric: rows past hash_max_flops go as (row, panel) pieces
+  const int32_t* row_slot; // numeric: rows with a kept bitmap (slot >= 0) are expanded
+};
+constexpr int kExpandBin = 15;  // numeric bin of rows whose bitmap was kept
+
+// Symbolic bitmaps kept for the numeric phase of pattern-only products.
+struct KeepBitmaps {
+  uint32_t* store;           // capacity slots of nwords words; NULL: keep none
+  int32_t* row_slot;         // per row: slot, or -1
+  unsigned int* counter;     // next free slot (zeroed before the launch)
+  const int64_t* flops;      // per row products
+  int64_t min_flops;         // rows with fewer products are recomputed instead
+  int64_t nwords;
+  unsigned int capacity;
 };
 
 struct BinOffsets {
@@ -96,7 +110,26 @@ hipError_t launch_hash_sym(const Operands& op, const int32_t* rows, int64_t nrow
                            int short_seg, int64_t* c_ptr, hipStream_t s);
 hipError_t launch_dense_sym(const Operands& op, const int32_t* rows, int64_t nrows, int wlog2, int P,
                             const int32_t* pidx, int nt, int short_seg, int64_t* c_ptr,
-                            hipStream_t s);
+                            hipStream_t s, int sub_wlog2 = 0, int subP = 0, int32_t* sub_cnt = nullptr,
+                            KeepBitmaps kb = KeepBitmaps{});
+hipError_t launch_expand_rows(const int32_t* rows, int64_t nrows, int nwords, const uint32_t* store,
+                              const int32_t* row_slot, const int64_t* c_ptr, int32_t* c_idx, int nt,
+                              hipStream_t s);
+// (row, panel) pieces: offsets within rows + bin counts, then the item lists.
+hipError_t launch_sub_prepare(int64_t nslots, int subP, int32_t* cnt, int32_t* off, int32_t* wend,
+                              BinParams bp, unsigned long long* counts, hipStream_t s);
+hipError_t launch_sub_scatter(int64_t nslots, int subP, const int32_t* cnt, BinParams bp,
+                              const BinOffsets& offs, unsigned long long* cursors, int32_t* items,
+                              hipStream_t s);
+hipError_t launch_hash_num_sub(int sr, const Operands& op, const int32_t* rows, const int32_t* items,
+                               int64_t nitems, int T, int nt, int short_seg, int subP, int sub_wlog2,
+                               const int32_t* pidx, const int32_t* cnt, const int32_t* off,
+                               const int32_t* wend, const int64_t* c_ptr, int32_t* c_idx, void* c_val,
+                               hipStream_t s);
+hipError_t launch_dense_num_sub(int sr, const Operands& op, const int32_t* rows, const int32_t* items,
+                                int64_t nitems, int nt, int short_seg, int subP, int sub_wlog2,
+                                const int32_t* pidx, const int32_t* cnt, const int32_t* off,
+                                const int64_t* c_ptr, int32_t* c_idx, void* c_val, hipStream_t s);
 // sr: semiring code 0..6, or 7 for the pattern-only boolean product.
 hipError_t launch_hash_num(int sr, const Operands& op, const int32_t* rows, int64_t nrows, int T,
                            int nt, int short_seg, const int64_t* c_ptr, int32_t* c_idx,
@@ -116,6 +149,23 @@ hipError_t launch_hash_num_b(int sr, const BatchDesc* descs, const int64_t* row_
 hipError_t launch_dense_num_b(int sr, const BatchDesc* descs, const int64_t* row_off, int nprod,
                               const int32_t* items, int64_t nitems, int wlog2_max, int nt,
                               int short_seg, int64_t grid_cap, hipStream_t s);
+// Segment lists of (row, panel) pieces.
+hipError_t launch_seg_count(const Operands& op, const int32_t* rows, int64_t nslots, int P,
+                            const int32_t* pidx, const int32_t* wend, int64_t* cnt_out, hipStream_t s);
+hipError_t launch_seg_write(const Operands& op, const int32_t* rows, int64_t nslots, int P,
+                            const int32_t* pidx, const int32_t* wend, const int64_t* segoff, void* segs,
+                            hipStream_t s);
+hipError_t launch_hash_num_seg(int sr, const Operands& op, const int32_t* rows, const int32_t* items,
+                               int64_t nitems, int T, int nt, int short_seg, int subP, int sub_wlog2,
+                               const int64_t* segoff, const void* segs, const int32_t* cnt,
+                               const int32_t* off, const int64_t* c_ptr, int32_t* c_idx, void* c_val,
+                               hipStream_t s);
+hipError_t launch_dense_num_seg(int sr, const Operands& op, const int32_t* rows, const int32_t* items,
+                                int64_t nitems, int nt, int short_seg, int subP, int sub_wlog2,
+                                const int64_t* segoff, const void* segs, const int32_t* cnt,
+                                const int32_t* off, const int64_t* c_ptr, int32_t* c_idx, void* c_val,
+                                hipStream_t s);
+size_t seg_desc_bytes();
 size_t storage_bytes(int sr);  // bytes per LDS accumulator value (0 for pattern)
 size_t hash_num_lds(int sr, int T, int nt);
 size_t dense_num_lds(int sr, int wlog2, int nt);

@@ -42,14 +42,21 @@ def test_skewed_rmat_default_bins(sr):
 
 
 @pytest.mark.parametrize("sr", ["plus_times_f64", "min_plus_i32", "or_and_bool", "max_times_f32"])
-@pytest.mark.parametrize("mode", ["all_dense", "many_panels", "all_hash_small_threads"])
+@pytest.mark.parametrize("mode", ["all_dense", "many_panels", "many_panels_in_sequence",
+                                  "many_panels_rewalk", "all_hash_small_threads"])
 def test_forced_paths(sr, mode):
     """The same product through forced accumulators: every row dense; dense
-    with many narrow panels (panel index in use); short segments split."""
+    with many narrow panels (panel index in use), as (row, panel) pieces or
+    panel after panel in one workgroup; short segments split."""
     A = with_semiring_values(_skewed(5000, 10, 4), sr, np.random.default_rng(5))
     o = {"all_dense": opts(hash_max_flops=32, hash_max_nnz=32),
          "many_panels": opts(hash_max_flops=32, hash_max_nnz=32, sym_panel_log2=8, lds_budget=1024,
                              dense_threads=256),
+         "many_panels_in_sequence": opts(hash_max_flops=32, hash_max_nnz=32, sym_panel_log2=8,
+                                         lds_budget=1024, dense_threads=256, split_panels=-1),
+         # no room for segment lists: pieces re-walk their rows
+         "many_panels_rewalk": opts(hash_max_flops=32, hash_max_nnz=32, sym_panel_log2=8, lds_budget=1024,
+                                    dense_threads=256, seg_mib=1),
          "all_hash_small_threads": opts(short_seg=1, dense_threads=64)}[mode]
     got = run_gpu(A, A, sr, o)
     assert_parity(A, A, sr, got)
@@ -60,6 +67,15 @@ def test_pattern_only_bool_null_values():
     assert A.val is None
     got = run_gpu(A, A, "or_and_bool")
     assert got[2] is None
+    assert_parity(A, A, "or_and_bool", got)
+
+
+@pytest.mark.parametrize("mib", [1, 64])
+def test_pattern_only_kept_bitmaps(mib):
+    """Heavy rows expanded from bitmaps kept by the symbolic phase (a small
+    budget keeps only some of them; the rest are recomputed)."""
+    A = _skewed(7000, 14, 6)
+    got = run_gpu(A, A, "or_and_bool", opts(bitmap_mib=mib, hash_max_flops=64))
     assert_parity(A, A, "or_and_bool", got)
 
 
