@@ -40,6 +40,13 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target host time of the oracle sample (0 disables)")
     ap.add_argument("--semirings", default="or_and_bool,min_plus_i32")
+    ap.add_argument("--workload", default="rmat", choices=["rmat", "er", "mcl", "batched", "served"],
+                    help="rmat (default) is the named benchmark workload; the others are the "
+                         "remaining configurations, printed in the same JSON form")
+    ap.add_argument("--nprod", type=int, default=512, help="batched: number of products")
+    ap.add_argument("--requests", type=int, default=2000, help="served: requests per arrival rate")
+    ap.add_argument("--opt", action="append", default=[],
+                    help="extra option for the valued product, key=value (e.g. split_panels=-1)")
     ap.add_argument("--bitmap-mib", type=int, default=24576,
                     help="workspace for symbolic bitmaps kept for the pattern-only numeric phase")
     return ap.parse_args()
@@ -67,7 +74,19 @@ def main():
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported by this build "
               f"(the product is a single-GPU kernel path)", file=sys.stderr)
         sys.exit(2)
+    run = {"rmat": run_rmat, "er": run_er, "mcl": run_mcl, "batched": run_batched,
+           "served": run_served}[args.workload]
+    out = run(args)
+    print(json.dumps(out), flush=True)
 
+
+def base_record(args, value, unit, ms_per_step, dtype, config, higher=True):
+    return {"metric": METRIC, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": higher,
+            "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config}
+
+
+def run_rmat(args):
     import torch
 
     import spgen
@@ -86,7 +105,8 @@ def main():
     s_in = {"or_and_bool": 0, "min_plus_i32": 4}
     s_out = {"or_and_bool": 0, "min_plus_i32": 4}
     opts = {"or_and_bool": B.make_options(timing=1, bitmap_mib=args.bitmap_mib),
-            "min_plus_i32": B.make_options(timing=1, seg_mib=20480)}
+            "min_plus_i32": B.make_options(timing=1, seg_mib=20480,
+                                           **{k: int(v) for k, v in (o.split("=") for o in args.opt)})}
     prods = {sr: S.Product(mats[sr], mats[sr], sr, opts[sr]) for sr in semirings}
     c_ptr = torch.empty(H.nrows + 1, dtype=torch.int64, device=dev)
 
@@ -192,7 +212,7 @@ def main():
 
     if args.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(H, list(prods), args.cpu_seconds)
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def cpu_baseline(H, semirings, target_s):
@@ -226,6 +246,197 @@ def cpu_baseline(H, semirings, target_s):
             "kind": "oracle",
             "sample": f"{sel.size} seeded random rows of {H.nrows} ({sample_flops} products over "
                       f"{len(semirings)} semirings, {dt:.1f} s)"}
+
+
+def timed(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t) * 1e3 / steps
+
+
+def run_er(args):
+    """Erdos-Renyi n=4096, 8 per row, (+,x) float64 (launch-latency bound)."""
+    import torch
+
+    import spgen
+    from paper_2106_14402_amd import spgemm as S
+    A = spgen.config_er()
+    dA = S.to_device(A)
+    p = S.Product(dA, dA, "plus_times_f64")
+    nnz = p.symbolic()
+    flops = p.stats()[0]
+    c_idx = torch.empty(nnz, dtype=torch.int32, device="cuda")
+    c_val = torch.empty(nnz, dtype=torch.float64, device="cuda")
+
+    def step():
+        p.symbolic(p.c_ptr)
+        p.numeric(c_idx, c_val)
+    ms = timed(step, args.steps, args.warmup)
+    out = base_record(args, round(2.0 * flops / (ms * 1e-3) / 1e9, 3), "GFLOP/s", ms, "f64",
+                      {"workload": "Erdos-Renyi n=4096, 8 per row, C=A*A over (+,x) float64",
+                       "flops": flops, "nnz_C": nnz})
+    out["us_per_product"] = round(ms * 1e3, 1)
+    if args.cpu_seconds > 0:
+        import oracle
+        nthreads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+        t = time.perf_counter()
+        reps = 0
+        while time.perf_counter() - t < min(args.cpu_seconds, 5):
+            oracle.spgemm(A, A, "plus_times_f64", nthreads=nthreads)
+            reps += 1
+        dt = (time.perf_counter() - t) / reps
+        out["cpu_baseline"] = {"value": round(2.0 * flops / dt / 1e9, 4), "unit": "GFLOP/s",
+                               "cores": nthreads, "kind": "oracle",
+                               "sample": f"whole product, mean of {reps} runs"}
+    p.close()
+    return out
+
+
+def run_mcl(args):
+    """Markov-clustering expansion: column-stochastic n=2^20 float32 CSC,
+    C=A*A over (+,x) float32, then prune entries < 1e-4."""
+    import torch
+
+    import spgen
+    from paper_2106_14402_amd import binding as B
+    from paper_2106_14402_amd import spgemm as S
+    t0 = time.time()
+    A = spgen.config_mcl()
+    log(f"[bench] MCL matrix n={A.ncols} nnz={A.nnz} in {time.time() - t0:.1f}s")
+    dA = S.to_device(A)
+    p = S.Product(dA, dA, "plus_times_f32", B.make_options(timing=1))
+    nnz = p.symbolic()
+    flops = p.stats()[0]
+    c_idx = torch.empty(nnz, dtype=torch.int32, device="cuda")
+    c_val = torch.empty(nnz, dtype=torch.float32, device="cuda")
+    state = {}
+
+    def step():
+        p.symbolic(p.c_ptr)
+        C = p.numeric(c_idx, c_val)
+        state["P"] = S.prune_f32(C, 1e-4)
+    ms = timed(step, args.steps, args.warmup)
+    kept = state["P"].nnz
+    out = base_record(args, round(2.0 * flops / (ms * 1e-3) / 1e9, 2), "GFLOP/s", ms, "f32",
+                      {"workload": "MCL expansion n=2^20, lognormal column degree mean 48 (sigma 1), "
+                                   "column-stochastic float32 CSC, C=A*A over (+,x) float32, prune < 1e-4",
+                       "n": A.ncols, "nnz_A": A.nnz, "flops": flops, "nnz_C": nnz, "nnz_pruned": kept})
+    out["phase_ms"] = {k: round(v, 3) for k, v in p.timings().items() if v > 0}
+    if args.cpu_seconds > 0:
+        out["cpu_baseline"] = cpu_baseline_generic(A, "plus_times_f32", args.cpu_seconds)
+    p.close()
+    return out
+
+
+def run_batched(args):
+    """512 uneven products (ER / R-MAT, (+,x) float64 / (min,+) int32): one
+    batched pass with the numeric phase replayed from a hipGraph, against one
+    call per product writing into the same pooled outputs."""
+    import torch
+
+    import spgen
+    from paper_2106_14402_amd import batch as BT
+    from paper_2106_14402_amd import spgemm as S
+    t0 = time.time()
+    items = spgen.batch_mix(nprod=args.nprod)
+    mats = [S.to_device(it.A) for it in items]
+    srs = [it.semiring for it in items]
+    log(f"[bench] {len(items)} products generated in {time.time() - t0:.1f}s")
+    bp = BT.BatchProduct(mats, mats, srs)
+    bp.symbolic()
+    bp.capture()
+    flops = bp.stats()[0]
+
+    def batched():
+        bp.symbolic()
+        bp.replay()
+    ms_b = timed(batched, args.steps, args.warmup)
+    singles = [S.Product(m, m, sr) for m, sr in zip(mats, srs)]
+    vb = BT.VAL_BYTES
+
+    def one_by_one():
+        for b, pr in enumerate(singles):
+            pr.symbolic(bp.c_ptr[bp.pool_off[b]:bp.pool_off[b + 1]])
+            nz = bp.c_nnz[b]
+            idx = bp.c_idx[bp.idx_off[b]:bp.idx_off[b] + nz]
+            raw = bp.c_val[bp.val_off[b]:bp.val_off[b] + nz * vb[srs[b]]]
+            pr.numeric(idx, raw.view(S.OUT_DTYPE[srs[b]]) if nz else None)
+    ms_s = timed(one_by_one, max(1, args.steps // 2), 1)
+    for pr in singles:
+        pr.close()
+    out = base_record(args, round(2.0 * flops / (ms_b * 1e-3) / 1e9, 2), "GFLOP/s", ms_b, "f64+int32",
+                      {"workload": f"{len(items)} uneven products: n log-uniform in [1K,64K], degree 4-32, "
+                                   "half Erdos-Renyi / half R-MAT, (+,x) float64 and (min,+) int32",
+                       "flops": flops, "nnz_C": int(sum(bp.c_nnz))})
+    out["batched_ms"] = round(ms_b, 3)
+    out["one_call_per_product_ms"] = round(ms_s, 3)
+    out["batched_speedup"] = round(ms_s / ms_b, 3)
+    bp.close()
+    return out
+
+
+def run_served(args):
+    """Resident R-MAT scale-22 adjacency (directed, pattern only); Poisson
+    streams of frontier requests F' = A^T F over (OR,AND) at three rates,
+    served with continuous batching and with one call per request."""
+    import numpy as np
+
+    import spgen
+    from paper_2106_14402_amd import serve as SV
+    t0 = time.time()
+    A = spgen.config_served_graph()
+    log(f"[bench] served graph n={A.nrows} nnz={A.nnz} in {time.time() - t0:.1f}s")
+    g = SV.ResidentGraph(A)
+    rng = spgen.rng_for(4, 7)
+    # one-at-a-time service rate mu1 (back-to-back requests, one call each)
+    probe = spgen.request_stream(A.nrows, 300, 1e9, rng)
+    single = SV.FrontierServer(g, workers=1, max_batch_requests=1)
+    res = single.serve(probe)
+    mu1 = SV.latency_summary(res)["req_per_s"]
+    log(f"[bench] one call per request: {mu1:.0f} req/s")
+    rates = {}
+    for frac in (0.3, 0.6, 0.9):
+        lam = frac * mu1
+        reqs = spgen.request_stream(A.nrows, args.requests, lam, spgen.rng_for(4, int(frac * 10)))
+        r_batch = SV.latency_summary(SV.FrontierServer(g, workers=3).serve(reqs))
+        r_single = SV.latency_summary(SV.FrontierServer(g, workers=1, max_batch_requests=1).serve(reqs))
+        rates[f"{frac:.1f}mu1"] = {"rate_req_s": round(lam, 1), "batched": r_batch, "one_call": r_single}
+        log(f"[bench] rate {lam:.0f}/s: batched p50 {r_batch['p50_ms']:.2f} p99 {r_batch['p99_ms']:.2f} | "
+            f"single p50 {r_single['p50_ms']:.2f} p99 {r_single['p99_ms']:.2f}")
+    top = rates["0.9mu1"]["batched"]
+    out = base_record(args, round(top["p99_ms"], 3), "ms (p99 at 0.9 mu1)", top["mean_ms"], "bool(pattern)",
+                      {"workload": "served frontier expansion on resident R-MAT scale 22 (edge factor 16, "
+                                   "directed), k log-uniform in [1,1024], 1-64 sources per column",
+                       "n": A.nrows, "nnz_A": A.nnz, "requests_per_rate": args.requests}, higher=False)
+    out["mu1_req_s"] = round(mu1, 1)
+    out["rates"] = rates
+    return out
+
+
+def cpu_baseline_generic(A, semiring, target_s):
+    """The oracle on a seeded slice sample of a square product."""
+    import oracle
+
+    nthreads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    fl = oracle.flops(A, A)
+    order = np.random.default_rng(7).permutation(fl.size)
+    probe = order[:256]
+    t = time.perf_counter()
+    oracle.spgemm(A, A, semiring, select=probe, nthreads=nthreads)
+    rate = fl[probe].sum() / max(time.perf_counter() - t, 1e-3)
+    nsel = int(np.searchsorted(np.cumsum(fl[order]), rate * target_s)) + 1
+    sel = np.sort(order[:nsel])
+    t = time.perf_counter()
+    oracle.spgemm(A, A, semiring, select=sel, nthreads=nthreads)
+    dt = time.perf_counter() - t
+    return {"value": round(2.0 * int(fl[sel].sum()) / dt / 1e9, 4), "unit": "GFLOP/s", "cores": nthreads,
+            "kind": "oracle", "sample": f"{sel.size} seeded random slices of {fl.size} ({dt:.1f} s)"}
 
 
 if __name__ == "__main__":

@@ -117,10 +117,11 @@ typedef struct spg_options {
                               plan's stream (read with spg_plan_timings) */
   int32_t split_panels;    /* numeric phase of rows that took the dense
                               symbolic path, when the value panels are
-                              narrower than C: 0 (default) splits each such
-                              row into one work item per column panel, binned
-                              by that panel's exact size; -1 processes the
-                              panels of a row in sequence in one workgroup */
+                              narrower than C: 1 splits each such row into
+                              column windows of at most hash_max_nnz entries
+                              (one work item each, LDS hash or one dense
+                              panel); 0 (default) or -1 processes the panels
+                              of a row in sequence in one workgroup */
   int32_t bitmap_mib;      /* pattern-only (OR,AND) products: MiB of workspace
                               in which the symbolic phase keeps the column
                               bitmaps of its heaviest rows, so the numeric

@@ -118,7 +118,7 @@ void resolve_options(const spg_options* in, spg_options* o) {
 
 spg_status check_options(const spg_options& o, int sr) {
   if (o.hash_max_flops > 16384 || o.hash_max_flops < 32) return SPG_E_INVALID;
-  if (o.hash_max_nnz < 32) return SPG_E_INVALID;
+  if (o.hash_max_nnz < 32 || o.hash_max_nnz > 4096) return SPG_E_INVALID;
   if (o.dense_threads % kWave != 0 || o.dense_threads > 1024) return SPG_E_INVALID;
   if (o.sym_panel_log2 < 7 || o.sym_panel_log2 > 20) return SPG_E_INVALID;
   // hash tables must fit in LDS
@@ -126,7 +126,7 @@ spg_status check_options(const spg_options& o, int sr) {
   if (hash_sym_lds(hash_table_size(csym), hash_threads(csym)) > static_cast<size_t>(max_lds_bytes()))
     return SPG_E_INVALID;
   const int cnum = hash_class(o.hash_max_nnz);
-  if (hash_num_lds(sr, hash_table_size(cnum), hash_threads(cnum)) > static_cast<size_t>(max_lds_bytes()))
+  if (hash_num_lds(sr, hash_table_size(cnum), hash_threads_num(cnum, sr)) > static_cast<size_t>(max_lds_bytes()))
     return SPG_E_INVALID;
   return SPG_OK;
 }
@@ -201,8 +201,6 @@ spg_status spg_plan_create(const spg_matrix* A, const spg_matrix* B, spg_semirin
   p->sr = (bool_sr && !A->val && !B->val) ? 7 : sr;
 
   resolve_options(opt_in, &p->opt);
-  if (!opt_in || opt_in->hash_max_nnz <= 0)  // a hash table of 16K slots fits LDS for 4-byte values
-    p->opt.hash_max_nnz = storage_bytes(p->sr == 7 ? 2 : p->sr) <= 4 ? 8192 : 4096;
   if ((st = check_options(p->opt, p->sr)) != SPG_OK) {
     delete p;
     return st;
@@ -232,7 +230,7 @@ spg_status spg_plan_create(const spg_matrix* A, const spg_matrix* B, spg_semirin
   const int64_t kk = std::max<int64_t>(1, p->op.k);
   p->sym_P = static_cast<int>((kk + (int64_t(1) << p->sym_wlog2) - 1) >> p->sym_wlog2);
   p->num_P = static_cast<int>((kk + (int64_t(1) << p->num_wlog2) - 1) >> p->num_wlog2);
-  p->split = p->opt.split_panels >= 0 && p->sr != 7 && p->num_P > 1 && p->sym_wlog2 >= p->num_wlog2 &&
+  p->split = p->opt.split_panels > 0 && p->sr != 7 && p->num_P > 1 && p->sym_wlog2 >= p->num_wlog2 &&
              static_cast<int64_t>(p->op.m) * p->num_P < (int64_t(1) << 31);
   p->bp.split_heavy = p->split ? 1 : 0;
 
@@ -569,7 +567,7 @@ spg_status spg_numeric(spg_plan* p, void* ws, int32_t* c_idx, void* c_val) {
     for (int c = 1; c < kExpandBin; ++c) {
       if (!p->num_counts[c]) continue;
       SPG_TRY_HIP(launch_hash_num(p->sr, op, rows_num + no.v[c], static_cast<int64_t>(p->num_counts[c]),
-                                  hash_table_size(c), hash_threads(c), p->opt.short_seg, p->c_ptr,
+                                  hash_table_size(c), hash_threads_num(c, p->sr), p->opt.short_seg, p->c_ptr,
                                   c_idx, c_val, s));
     }
     if (sub) {
@@ -578,12 +576,12 @@ spg_status spg_numeric(spg_plan* p, void* ws, int32_t* c_idx, void* c_val) {
         if (use_segs)
           SPG_TRY_HIP(launch_hash_num_seg(p->sr, op, rows_dense_sym, subitems + sbo.v[c],
                                           static_cast<int64_t>(p->sub_counts[c]), hash_table_size(c),
-                                          hash_threads(c), p->opt.short_seg, p->num_P, p->num_wlog2, segoff,
+                                          hash_threads_num(c, p->sr), p->opt.short_seg, p->num_P, p->num_wlog2, segoff,
                                           segs, subcnt, suboff, p->c_ptr, c_idx, c_val, s));
         else
           SPG_TRY_HIP(launch_hash_num_sub(p->sr, op, rows_dense_sym, subitems + sbo.v[c],
                                           static_cast<int64_t>(p->sub_counts[c]), hash_table_size(c),
-                                          hash_threads(c), p->opt.short_seg, p->num_P, p->num_wlog2, pnum,
+                                          hash_threads_num(c, p->sr), p->opt.short_seg, p->num_P, p->num_wlog2, pnum,
                                           subcnt, suboff, wend, p->c_ptr, c_idx, c_val, s));
       }
     }

@@ -261,7 +261,7 @@ spg_status enqueue_numeric(spg_batch_plan* p, unsigned char* w) {
     for (int c = 1; c < kDenseBinBase; ++c) {
       const int bin = c + kNumBins * sl;
       if (!p->num_counts[bin]) continue;
-      const int nt = hash_threads(c);
+      const int nt = hash_threads_num(c, sr);
       SPG_TRY_HIP(launch_hash_num_b(sr, d, row_off, p->nprod, items + no[bin],
                                     static_cast<int64_t>(p->num_counts[bin]), hash_table_size(c), nt,
                                     p->opt.short_seg, grid_cap(p, nt), s));
@@ -300,6 +300,7 @@ spg_status spg_batch_plan_create(int nprod, const spg_matrix* A, const spg_matri
   if (p->opt.sym_panel_log2 <= 0) p->opt.sym_panel_log2 = 20;
   if (p->opt.lds_budget <= 0) p->opt.lds_budget = 65536;
   if (p->opt.hash_max_flops > 16384 || p->opt.hash_max_flops < 32 || p->opt.hash_max_nnz < 32 ||
+      p->opt.hash_max_nnz > 4096 ||
       p->opt.dense_threads % kWave || p->opt.dense_threads > 1024 || p->opt.sym_panel_log2 < 7 ||
       p->opt.sym_panel_log2 > 20) {
     delete p;

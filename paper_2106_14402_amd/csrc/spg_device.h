@@ -289,6 +289,23 @@ struct RowSource {
   }
 };
 
+// A row of at most one entry per thread, walked panel after panel: every
+// thread keeps its A entry (value, B row start, panel-index row) in registers
+// and has the next panel's offset loaded one panel ahead.
+template <class SR>
+struct CachedRowSource {
+  int64_t deg;
+  int64_t bs;
+  typename SR::In a;
+  int32_t s_cur, s_nxt, s_nxt2;
+  __device__ int64_t count() const { return deg; }
+  __device__ void load(int64_t, int64_t& lo, int32_t& len, typename SR::In& av) const {
+    lo = bs + s_cur;
+    len = s_nxt - s_cur;
+    av = a;
+  }
+};
+
 // One non-empty segment of a (row, panel) piece: entries [bpos, bpos+len) of
 // B, multiplied by A entry a_lo + apos.
 struct SegDesc {
@@ -316,6 +333,9 @@ template <class SR, class Src, class Sink>
 __device__ void enumerate_src(const Operands& op, const Src& src, int32_t c0, int short_seg,
                               RowQueue<typename SR::In> q, Sink& sink) {
   using In = typename SR::In;
+  // 16 loads in flight per lane (8 for 8-byte values, to stay in registers)
+  constexpr int kPU = sizeof(In) > 4 ? kPieceUnroll / 2 : kPieceUnroll;
+  constexpr int kPc = kWave * kPU;
   const int tid = threadIdx.x;
   const int nt = blockDim.x;
   const int lane = tid & (kWave - 1);
@@ -356,7 +376,7 @@ __device__ void enumerate_src(const Operands& op, const Src& src, int32_t c0, in
     __syncthreads();
     const int nq = q.ctr[0];
     if (nq > 0) {
-      int pieces = tid < nq ? (q.len[tid] + kPiece - 1) / kPiece : 0;
+      int pieces = tid < nq ? (q.len[tid] + kPc - 1) / kPc : 0;
       int ptotal;
       const int off = block_exclusive_scan(pieces, q.ctr + 2, &ptotal);
       if (tid < nq) q.pfx[tid] = off;
@@ -378,13 +398,13 @@ __device__ void enumerate_src(const Operands& op, const Src& src, int32_t c0, in
         }
         const int e = lo_e;
         e_lo = e;
-        const int64_t s0 = q.lo[e] + static_cast<int64_t>(u - q.pfx[e]) * kPiece;
+        const int64_t s0 = q.lo[e] + static_cast<int64_t>(u - q.pfx[e]) * kPc;
         const int64_t s1 = q.lo[e] + q.len[e];
         const In ae = q.a[e];
-        int32_t cols[kPieceUnroll];
-        In bv[kPieceUnroll];
+        int32_t cols[kPU];
+        In bv[kPU];
 #pragma unroll
-        for (int r = 0; r < kPieceUnroll; ++r) {
+        for (int r = 0; r < kPU; ++r) {
           const int64_t qq = s0 + r * kWave + lane;
           if (qq < s1) {
             cols[r] = bidx[qq];
@@ -392,7 +412,7 @@ __device__ void enumerate_src(const Operands& op, const Src& src, int32_t c0, in
           }
         }
 #pragma unroll
-        for (int r = 0; r < kPieceUnroll; ++r) {
+        for (int r = 0; r < kPU; ++r) {
           const int64_t qq = s0 + r * kWave + lane;
           if (qq < s1) sink.add(cols[r] - c0, SR::mul(ae, bv[r]));
         }
@@ -413,6 +433,14 @@ __device__ void enumerate_row(const Operands& op, int64_t a_lo, int64_t a_hi, bo
                               int short_seg, RowQueue<typename SR::In> q, Sink& sink) {
   RowSource<SR> src{&op, a_lo, a_hi, paneled, pidx, P, p, p + 1};
   enumerate_src<SR>(op, src, c0, short_seg, q, sink);
+}
+
+// Wave-uniform values kept in scalar registers.
+__device__ __forceinline__ int32_t uniform(int32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ int64_t uniform64(int64_t x) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(x));
+  const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(static_cast<uint64_t>(x) >> 32));
+  return static_cast<int64_t>((static_cast<uint64_t>(hi) << 32) | lo);
 }
 
 __device__ __forceinline__ uint32_t hash_slot(int32_t key, uint32_t mask) {

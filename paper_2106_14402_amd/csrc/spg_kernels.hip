@@ -437,7 +437,7 @@ __global__ __launch_bounds__(1024) void k_hash_sym(Operands op, const int32_t* _
                                                    int64_t* __restrict__ c_ptr) {
   extern __shared__ __align__(16) unsigned char smem[];
   for (int64_t it = blockIdx.x; it < nrows; it += gridDim.x) {
-    const int32_t row = rows[it];
+    const int32_t row = uniform(rows[it]);
     const int64_t nz = hash_sym_row(op, row, T, short_seg, smem);
     if (threadIdx.x == 0) c_ptr[row + 1] = nz;
   }
@@ -451,7 +451,7 @@ __global__ __launch_bounds__(1024) void k_dense_sym(Operands op, const int32_t* 
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int slot_s;
   for (int64_t it = blockIdx.x; it < nrows; it += gridDim.x) {
-    const int32_t row = rows[it];
+    const int32_t row = uniform(rows[it]);
     uint32_t* keep = nullptr;
     if (kb.store) {
       // The heaviest rows come first; each takes a bitmap slot while any is left.
@@ -480,10 +480,10 @@ __global__ __launch_bounds__(1024) void k_hash_sym_b(const BatchDesc* __restrict
                                                      int T, int short_seg) {
   extern __shared__ __align__(16) unsigned char smem[];
   for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
-    const int64_t r = items[it];
-    const int b = batch_product(row_off, nprod, r);
-    const BatchDesc& d = descs[b];
-    const int32_t row = static_cast<int32_t>(r - row_off[b]);
+    const int64_t r = uniform(items[it]);
+    const int b = uniform(batch_product(row_off, nprod, r));
+    const BatchDesc d = descs[b];  // uniform: held in scalar registers
+    const int32_t row = uniform(static_cast<int32_t>(r - row_off[b]));
     const int64_t nz = hash_sym_row(d.op, row, T, short_seg, smem);
     if (threadIdx.x == 0) d.c_ptr[row + 1] = nz;
   }
@@ -495,10 +495,10 @@ __global__ __launch_bounds__(1024) void k_dense_sym_b(const BatchDesc* __restric
                                                       int short_seg) {
   extern __shared__ __align__(16) unsigned char smem[];
   for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
-    const int64_t r = items[it];
-    const int b = batch_product(row_off, nprod, r);
-    const BatchDesc& d = descs[b];
-    const int32_t row = static_cast<int32_t>(r - row_off[b]);
+    const int64_t r = uniform(items[it]);
+    const int b = uniform(batch_product(row_off, nprod, r));
+    const BatchDesc d = descs[b];  // uniform: held in scalar registers
+    const int32_t row = uniform(static_cast<int32_t>(r - row_off[b]));
     const int64_t nz = dense_sym_row(d.op, row, d.sym_wlog2, d.sym_P, d.psym, short_seg, smem);
     if (threadIdx.x == 0) d.c_ptr[row + 1] = nz;
     __syncthreads();
@@ -569,7 +569,7 @@ __global__ __launch_bounds__(1024) void k_expand_rows(const int32_t* __restrict_
   int* tmp = reinterpret_cast<int*>(smem);
   uint32_t* bits = reinterpret_cast<uint32_t*>(smem + 256);
   for (int64_t it = blockIdx.x; it < nrows; it += gridDim.x) {
-    const int32_t row = rows[it];
+    const int32_t row = uniform(rows[it]);
     const uint32_t* src = store + static_cast<int64_t>(row_slot[row]) * nwords;
     for (int t = threadIdx.x; t < nwords; t += blockDim.x) bits[t] = src[t];
     __syncthreads();
@@ -761,17 +761,20 @@ __device__ void hash_num_src(const Operands& op, const Src& src, int32_t c0, int
   __syncthreads();
   HashMapSink<SR> sink{keys, vals, static_cast<uint32_t>(T - 1)};
   enumerate_src<SR>(op, src, c0, short_seg, q, sink);
-  // Compact occupied slots to the front: every thread takes a contiguous
-  // block of T/nt slots into registers, then writes them at its scanned offset.
+  // Compact occupied slots to the front: every thread takes T/nt slots
+  // (strided by nt, so reads are free of bank conflicts) into registers, then
+  // writes them at its scanned offset.  The order does not matter: a sort
+  // follows.
+  constexpr int kMaxSlots = sizeof(S) > 4 ? kMaxSlotsPerThread / 2 : kMaxSlotsPerThread;
   const int per = T / nt;
-  int32_t kr[kMaxSlotsPerThread];
-  S vr[kMaxSlotsPerThread];
+  int32_t kr[kMaxSlots];
+  S vr[kMaxSlots];
   int cnt = 0;
 #pragma unroll
-  for (int r = 0; r < kMaxSlotsPerThread; ++r) {
+  for (int r = 0; r < kMaxSlots; ++r) {
     kr[r] = kEmpty;
     if (r < per) {
-      const int slot = tid * per + r;
+      const int slot = r * nt + tid;
       kr[r] = keys[slot];
       if constexpr (!SR::kPattern) vr[r] = vals[slot];
       cnt += kr[r] != kEmpty;
@@ -780,7 +783,7 @@ __device__ void hash_num_src(const Operands& op, const Src& src, int32_t c0, int
   int nnz;
   int o = block_exclusive_scan(cnt, q.ctr + 2, &nnz);
 #pragma unroll
-  for (int r = 0; r < kMaxSlotsPerThread; ++r) {
+  for (int r = 0; r < kMaxSlots; ++r) {
     if (r < per && kr[r] != kEmpty) {
       keys[o] = kr[r];
       if constexpr (!SR::kPattern) vals[o] = vr[r];
@@ -890,9 +893,33 @@ __device__ void dense_num_row(const Operands& op, int32_t row, int wlog2, int P,
                               typename SR::Out* __restrict__ c_val, unsigned char* smem,
                               int p_begin = 0, int p_end = -1) {
   const int64_t a_lo = op.a_ptr[row], a_hi = op.a_ptr[row + 1];
+  if (p_end < 0) p_end = P;
+  if (P > 1 && a_hi - a_lo <= blockDim.x && p_end - p_begin > 1) {
+    CachedRowSource<SR> cs{a_hi - a_lo, 0, typename SR::In(1), 0, 0, 0};
+    const int32_t* sp = nullptr;
+    const int tid = threadIdx.x;
+    if (tid < a_hi - a_lo) {
+      const int32_t kk = op.a_idx[a_lo + tid];
+      cs.a = load_val<SR>(op.a_val, a_lo + tid);
+      cs.bs = op.b_ptr[kk];
+      sp = pidx + static_cast<int64_t>(kk) * (P + 1);
+      cs.s_cur = sp[p_begin];
+      cs.s_nxt = sp[p_begin + 1];
+      cs.s_nxt2 = sp[min(p_begin + 2, P)];
+    }
+    auto make = [&](int p) {
+      if (p > p_begin) {
+        cs.s_cur = cs.s_nxt;
+        cs.s_nxt = cs.s_nxt2;
+        if (sp) cs.s_nxt2 = sp[min(p + 2, P)];  // consumed at the next panel
+      }
+      return cs;
+    };
+    dense_num_gen<SR>(op, wlog2, p_begin, p_end, short_seg, out, out_end, c_idx, c_val, smem, make);
+    return;
+  }
   auto make = [&](int p) { return RowSource<SR>{&op, a_lo, a_hi, P > 1, pidx, P, p, p + 1}; };
-  dense_num_gen<SR>(op, wlog2, p_begin, p_end < 0 ? P : p_end, short_seg, out, out_end, c_idx, c_val, smem,
-                    make);
+  dense_num_gen<SR>(op, wlog2, p_begin, p_end, short_seg, out, out_end, c_idx, c_val, smem, make);
 }
 
 template <class SR>
@@ -903,7 +930,7 @@ __global__ __launch_bounds__(1024) void k_hash_num(Operands op, const int32_t* _
                                                    typename SR::Out* __restrict__ c_val) {
   extern __shared__ __align__(16) unsigned char smem[];
   for (int64_t it = blockIdx.x; it < nrows; it += gridDim.x) {
-    const int32_t row = rows[it];
+    const int32_t row = uniform(rows[it]);
     hash_num_row<SR>(op, row, T, short_seg, c_ptr[row], c_ptr[row + 1], c_idx, c_val, smem);
   }
 }
@@ -917,7 +944,7 @@ __global__ __launch_bounds__(1024) void k_dense_num(Operands op, const int32_t* 
                                                     typename SR::Out* __restrict__ c_val) {
   extern __shared__ __align__(16) unsigned char smem[];
   for (int64_t it = blockIdx.x; it < nrows; it += gridDim.x) {
-    const int32_t row = rows[it];
+    const int32_t row = uniform(rows[it]);
     dense_num_row<SR>(op, row, wlog2, P, pidx, short_seg, c_ptr[row], c_ptr[row + 1], c_idx, c_val,
                       smem);
   }
@@ -1109,10 +1136,10 @@ __global__ __launch_bounds__(1024) void k_hash_num_b(const BatchDesc* __restrict
                                                      int T, int short_seg) {
   extern __shared__ __align__(16) unsigned char smem[];
   for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
-    const int64_t r = items[it];
-    const int b = batch_product(row_off, nprod, r);
-    const BatchDesc& d = descs[b];
-    const int32_t row = static_cast<int32_t>(r - row_off[b]);
+    const int64_t r = uniform(items[it]);
+    const int b = uniform(batch_product(row_off, nprod, r));
+    const BatchDesc d = descs[b];  // uniform: held in scalar registers
+    const int32_t row = uniform(static_cast<int32_t>(r - row_off[b]));
     hash_num_row<SR>(d.op, row, T, short_seg, d.c_ptr[row], d.c_ptr[row + 1], d.c_idx,
                      static_cast<typename SR::Out*>(d.c_val), smem);
   }
@@ -1125,10 +1152,10 @@ __global__ __launch_bounds__(1024) void k_dense_num_b(const BatchDesc* __restric
                                                       int short_seg) {
   extern __shared__ __align__(16) unsigned char smem[];
   for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
-    const int64_t r = items[it];
-    const int b = batch_product(row_off, nprod, r);
-    const BatchDesc& d = descs[b];
-    const int32_t row = static_cast<int32_t>(r - row_off[b]);
+    const int64_t r = uniform(items[it]);
+    const int b = uniform(batch_product(row_off, nprod, r));
+    const BatchDesc d = descs[b];  // uniform: held in scalar registers
+    const int32_t row = uniform(static_cast<int32_t>(r - row_off[b]));
     dense_num_row<SR>(d.op, row, d.num_wlog2, d.num_P, d.pnum, short_seg, d.c_ptr[row],
                       d.c_ptr[row + 1], d.c_idx, static_cast<typename SR::Out*>(d.c_val), smem);
   }
@@ -1323,6 +1350,12 @@ static size_t storage_bytes_t() {
   return SR::kPattern ? 0 : sizeof(typename SR::S);
 }
 size_t storage_bytes(int sr) { SPG_DISPATCH(sr, storage_bytes_t) }
+
+int hash_threads_num(int c, int sr) {
+  // the numeric compaction keeps 16 slots per thread (8 for 8-byte values)
+  int t = hash_table_size(c) / (storage_bytes(sr) > 4 ? 8 : 16);
+  return t < 64 ? 64 : (t > 1024 ? 1024 : t);
+}
 
 int max_lds_bytes() { return 160 * 1024; }
 

@@ -84,7 +84,7 @@ struct BatchDesc {
 // Hash table size and workgroup size of hash class c.
 inline int hash_table_size(int c) { return 64 << (c - 1); }
 inline int hash_threads(int c) {
-  int t = hash_table_size(c) / 16;
+  int t = hash_table_size(c) / 16;  // at most 16 slots per thread in the numeric compaction
   return t < 64 ? 64 : (t > 1024 ? 1024 : t);
 }
 
@@ -167,6 +167,7 @@ hipError_t launch_dense_num_seg(int sr, const Operands& op, const int32_t* rows,
                                 hipStream_t s);
 size_t seg_desc_bytes();
 size_t storage_bytes(int sr);  // bytes per LDS accumulator value (0 for pattern)
+int hash_threads_num(int c, int sr);  // workgroup size of numeric hash class c
 size_t hash_num_lds(int sr, int T, int nt);
 size_t dense_num_lds(int sr, int wlog2, int nt);
 size_t dense_sym_lds(int wlog2, int nt);

@@ -43,7 +43,7 @@ def test_skewed_rmat_default_bins(sr):
 
 @pytest.mark.parametrize("sr", ["plus_times_f64", "min_plus_i32", "or_and_bool", "max_times_f32"])
 @pytest.mark.parametrize("mode", ["all_dense", "many_panels", "many_panels_in_sequence",
-                                  "many_panels_rewalk", "all_hash_small_threads"])
+                                  "many_panels_rewalk", "windows", "all_hash_small_threads"])
 def test_forced_paths(sr, mode):
     """The same product through forced accumulators: every row dense; dense
     with many narrow panels (panel index in use), as (row, panel) pieces or
@@ -51,12 +51,13 @@ def test_forced_paths(sr, mode):
     A = with_semiring_values(_skewed(5000, 10, 4), sr, np.random.default_rng(5))
     o = {"all_dense": opts(hash_max_flops=32, hash_max_nnz=32),
          "many_panels": opts(hash_max_flops=32, hash_max_nnz=32, sym_panel_log2=8, lds_budget=1024,
-                             dense_threads=256),
+                             dense_threads=256, split_panels=1),
          "many_panels_in_sequence": opts(hash_max_flops=32, hash_max_nnz=32, sym_panel_log2=8,
                                          lds_budget=1024, dense_threads=256, split_panels=-1),
          # no room for segment lists: pieces re-walk their rows
          "many_panels_rewalk": opts(hash_max_flops=32, hash_max_nnz=32, sym_panel_log2=8, lds_budget=1024,
-                                    dense_threads=256, seg_mib=1),
+                                    dense_threads=256, seg_mib=1, split_panels=1),
+         "windows": opts(hash_max_flops=64, hash_max_nnz=512, lds_budget=4096, split_panels=1),
          "all_hash_small_threads": opts(short_seg=1, dense_threads=64)}[mode]
     got = run_gpu(A, A, sr, o)
     assert_parity(A, A, sr, got)
