@@ -56,6 +56,38 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def kernel_sources_digest():
+    """sha256 over the HIP sources of the library: counter figures taken on
+    other sources no longer describe the kernels."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2106_14402_amd", "csrc")
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".hip", ".h")):
+            with open(os.path.join(d, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of ``kernel`` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE runs, each scaled by the same counter's
+    reading on a plain copy of known size), or None when there is no summary
+    for it or the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("sources_sha256") != kernel_sources_digest():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    if not k:
+        return None
+    return int(round(k["fetch_kib"] * 1024 / rec["fetch_factor"] + k["write_kib"] * 1024 / rec["write_factor"]))
+
+
 def alg_bytes_dense(A, nnz_dense_rows_A, ndense_rows, nnz_c_dense, s_in, s_out, symbolic):
     """Algorithmic HBM bytes of one dense-accumulator launch: read the row
     list, the A rows it covers and B once; write C's entries (numeric) or the
@@ -156,14 +188,19 @@ def run_rmat(args):
         # flops per row from the host copy of the operand (bookkeeping only)
         fl = np.bincount(np.repeat(np.arange(H.nrows), deg), weights=deg[H.idx].astype(np.float64),
                          minlength=H.nrows)
-        num_dense_rows = rownnz > 4096
         sym_dense_rows = fl > 8192
+        ranked = phase_ms[sr].get("num_rank", 0.0) > 0
+        rank_rows = sym_dense_rows & (rownnz > 4096) if ranked else np.zeros_like(sym_dense_rows)
+        num_dense_rows = (rownnz > 4096) & ~rank_rows
+
+        def dense_bytes(rows):
+            return alg_bytes_dense(H, int(deg[rows].sum()), int(rows.sum()), int(rownnz[rows].sum()),
+                                   s_in[sr], s_out[sr], False)
         cands = {
             "k_expand_rows": (phase_ms[sr].get("num_expand", 0.0), 0),
-            "k_hash_num_seg": (phase_ms[sr].get("num_hash", 0.0), 0),
-            "k_dense_num": (phase_ms[sr]["num_dense"], alg_bytes_dense(
-                H, int(deg[num_dense_rows].sum()), int(num_dense_rows.sum()),
-                int(rownnz[num_dense_rows].sum()), s_in[sr], s_out[sr], False)),
+            "k_hash_num": (phase_ms[sr].get("num_hash", 0.0), 0),
+            "k_dense_num": (phase_ms[sr].get("num_dense", 0.0), dense_bytes(num_dense_rows)),
+            "k_rank_num": (phase_ms[sr].get("num_rank", 0.0), dense_bytes(rank_rows)),
             "k_dense_sym": (phase_ms[sr]["sym_dense"], alg_bytes_dense(
                 H, int(deg[sym_dense_rows].sum()), int(sym_dense_rows.sum()), 0, s_in[sr], 0, True)),
         }
@@ -172,7 +209,8 @@ def run_rmat(args):
                 dom = {"kernel": name, "semiring": sr, "ms": ms, "bytes": by}
     achieved = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(f"{dom['kernel']}<{dom['semiring']}>", f"rmat{args.scale}"),
                 "kernel": f"{dom['kernel']}<{dom['semiring']}>",
                 "kernel_ms": round(dom["ms"], 3), "alg_bytes": int(dom["bytes"])}
     # whole-step compulsory bytes (two-phase, B cached): per product

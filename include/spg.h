@@ -131,7 +131,16 @@ typedef struct spg_options {
                               (row, panel) pieces (default 16384); a product
                               that needs more falls back to re-walking each
                               row per piece */
-  int32_t reserved[5];
+  int32_t rank_panels;     /* numeric phase of heavy valued rows (more than
+                              hash_max_nnz entries, dense symbolic path) when
+                              the value panels are narrower than C: 0
+                              (default) or 1 = passes over runs of column
+                              chunks whose entries fit the LDS value slots,
+                              each entry stored at its column's rank; -1 =
+                              fixed-width panels in sequence */
+  int32_t rank_dense_div;  /* rows with nnz * rank_dense_div >= columns of C
+                              keep fixed-width panels (default 4) */
+  int32_t reserved[3];
 } spg_options;
 
 /* Phases reported by spg_plan_timings, in milliseconds. */
@@ -148,7 +157,8 @@ enum {
   SPG_PHASE_NUM_EXPAND = 9,  /* numeric, rows expanded from kept bitmaps */
   SPG_PHASE_SEG_COUNT = 10,  /* symbolic, segment counts of (row, panel) pieces */
   SPG_PHASE_SEG_WRITE = 11,  /* numeric, segment lists of (row, panel) pieces */
-  SPG_NUM_PHASES = 12
+  SPG_PHASE_NUM_RANK = 12,   /* numeric, heavy valued rows by rank-compressed panels */
+  SPG_NUM_PHASES = 13
 };
 
 typedef struct spg_plan spg_plan;

@@ -61,7 +61,9 @@ class spg_options(ctypes.Structure):
         ("split_panels", ctypes.c_int32),
         ("bitmap_mib", ctypes.c_int32),
         ("seg_mib", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 5),
+        ("rank_panels", ctypes.c_int32),
+        ("rank_dense_div", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 3),
     ]
 
 
@@ -212,7 +214,7 @@ def spg_plan_stats(plan):
 
 
 PHASES = ["validate", "flops_bin", "sym_hash", "sym_dense", "scan", "num_hash", "num_dense",
-          "sym_panels", "num_panels", "num_expand", "seg_count", "seg_write"]
+          "sym_panels", "num_panels", "num_expand", "seg_count", "seg_write", "num_rank"]
 
 
 def spg_plan_timings(plan) -> dict:

@@ -40,6 +40,9 @@ struct spg_plan {
   int64_t keep_nwords, keep_min_flops;
   unsigned int keep_cap;
   size_t off_segoff, off_segs;   // (row, panel) segment lists
+  bool rank;                     // heavy valued rows through rank-compressed panels
+  int rank_cw, rank_NC, rank_maxc;
+  size_t off_rcnt, off_pchunk;
   int64_t seg_cap, seg_total;
   bool pnum_ready;
   unsigned long long sub_counts[kNumBins];
@@ -114,6 +117,7 @@ void resolve_options(const spg_options* in, spg_options* o) {
   if (o->sym_panel_log2 <= 0) o->sym_panel_log2 = 20;
   if (o->lds_budget <= 0) o->lds_budget = 131072;
   if (o->seg_mib <= 0) o->seg_mib = 16384;
+  if (o->rank_dense_div <= 0) o->rank_dense_div = 4;
 }
 
 spg_status check_options(const spg_options& o, int sr) {
@@ -234,6 +238,31 @@ spg_status spg_plan_create(const spg_matrix* A, const spg_matrix* B, spg_semirin
              static_cast<int64_t>(p->op.m) * p->num_P < (int64_t(1) << 31);
   p->bp.split_heavy = p->split ? 1 : 0;
 
+  // Rank-compressed panels: 64 KiB of value slots (2^cw of them) per pass,
+  // chunks of 2^cw columns, a bitmap of up to 2^18 columns.
+  p->rank = false;
+  p->rank_cw = 0;
+  p->rank_NC = 0;
+  p->rank_maxc = 0;
+  if (p->opt.rank_panels >= 0 && sb > 0 && !p->split && p->num_P > 1) {
+    int cw = 5;
+    while ((static_cast<size_t>(1) << (cw + 1)) * sb <= 65536) ++cw;
+    cw = std::min(cw, p->num_wlog2);
+    int maxc = std::max(1, std::min(64, (1 << 18) >> cw));
+    while (maxc > 1 && rank_num_lds(p->sr, cw, maxc, p->num_wlog2, nt) > static_cast<size_t>(max_lds_bytes()))
+      maxc >>= 1;
+    const int64_t NC = (kk + (int64_t(1) << cw) - 1) >> cw;
+    if (cw >= 5 && cw <= p->sym_wlog2 &&
+        rank_num_lds(p->sr, cw, maxc, p->num_wlog2, nt) <= static_cast<size_t>(max_lds_bytes()) &&
+        static_cast<int64_t>(p->op.m) * NC < (int64_t(1) << 31) && NC < (int64_t(1) << 24)) {
+      p->rank = true;
+      p->rank_cw = cw;
+      p->rank_NC = static_cast<int>(NC);
+      p->rank_maxc = maxc;
+    }
+  }
+  p->bp.rank_heavy = p->rank ? 1 : 0;
+
   // Workspace layout.
   const int64_t m = p->op.m;
   const int64_t nB = p->op.n;
@@ -288,6 +317,10 @@ spg_status spg_plan_create(const spg_matrix* A, const spg_matrix* B, spg_semirin
     p->seg_cap = std::min(bound, budget);
     off = align_up(off + static_cast<size_t>(p->seg_cap) * seg_desc_bytes());
   }
+  p->off_rcnt = off;
+  if (p->rank) off = align_up(off + static_cast<size_t>(m) * p->rank_NC * sizeof(int32_t));
+  p->off_pchunk = off;
+  if (p->rank) off = align_up(off + static_cast<size_t>(nB) * (p->rank_NC + 1) * sizeof(int32_t));
   p->seg_total = 0;
   p->pnum_ready = false;
   p->ws_bytes = off;
@@ -467,8 +500,12 @@ spg_status spg_symbolic(spg_plan* p, void* ws, int64_t* c_ptr, int64_t* c_nnz) {
     }
     SPG_TRY_HIP(launch_dense_sym(op, rows_sym + so.v[kDenseBinBase], ndense, p->sym_wlog2, p->sym_P,
                                  psym, p->opt.dense_threads, p->opt.short_seg, c_ptr, s,
-                                 p->split ? p->num_wlog2 : 0, p->split ? p->num_P : 0,
-                                 p->split ? reinterpret_cast<int32_t*>(w + p->off_subcnt) : nullptr, kb));
+                                 p->split ? p->num_wlog2 : (p->rank ? p->rank_cw : 0),
+                                 p->split ? p->num_P : (p->rank ? p->rank_NC : 0),
+                                 p->split  ? reinterpret_cast<int32_t*>(w + p->off_subcnt)
+                                 : p->rank ? reinterpret_cast<int32_t*>(w + p->off_rcnt)
+                                           : nullptr,
+                                 kb));
   }
   int64_t total = 0;
   p->n_dense_sym = ndense;
@@ -535,7 +572,7 @@ spg_status spg_numeric(spg_plan* p, void* ws, int32_t* c_idx, void* c_val) {
   int64_t ndense = 0;
   for (int b = kDenseBinBase; b < kNumBins; ++b) ndense += static_cast<int64_t>(p->num_counts[b]);
   p->ran[SPG_PHASE_NUM_HASH] = p->ran[SPG_PHASE_NUM_DENSE] = p->ran[SPG_PHASE_NUM_PANELS] = false;
-  p->ran[SPG_PHASE_NUM_EXPAND] = false;
+  p->ran[SPG_PHASE_NUM_EXPAND] = p->ran[SPG_PHASE_NUM_RANK] = false;
   const bool sub = p->split && p->n_dense_sym > 0;
   const BinOffsets sbo = offsets_of(p->sub_counts);
   int64_t nsub_dense = 0;
@@ -608,6 +645,18 @@ spg_status spg_numeric(spg_plan* p, void* ws, int32_t* c_idx, void* c_val) {
       SPG_TRY_HIP(launch_dense_num_sub(p->sr, op, rows_dense_sym, subitems + sbo.v[kDenseBinBase], nsub_dense,
                                        p->opt.dense_threads, p->opt.short_seg, p->num_P, p->num_wlog2, pnum,
                                        subcnt, suboff, p->c_ptr, c_idx, c_val, s));
+  }
+  if (p->rank && p->n_dense_sym > 0) {
+    auto* pchunk = reinterpret_cast<int32_t*>(w + p->off_pchunk);
+    {
+      PhaseTimer tp(p, SPG_PHASE_NUM_PANELS);
+      SPG_TRY_HIP(launch_panel_index(op.b_ptr, op.b_idx, op.n, p->rank_cw, p->rank_NC, pchunk, s));
+    }
+    PhaseTimer t(p, SPG_PHASE_NUM_RANK);
+    SPG_TRY_HIP(launch_rank_num(p->sr, op, rows_dense_sym, p->n_dense_sym, p->rank_cw, p->rank_NC, p->rank_maxc,
+                                pchunk, reinterpret_cast<const int32_t*>(w + p->off_rcnt), p->bp.hash_max_nnz,
+                                p->opt.rank_dense_div, p->num_wlog2, p->num_P, p->opt.dense_threads,
+                                p->opt.short_seg, p->c_ptr, c_idx, c_val, s));
   }
   return SPG_OK;
 }

@@ -129,8 +129,9 @@ __global__ void k_count_num_bins(int32_t m, const int64_t* __restrict__ flops,
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + tid;
   if (i < m) {
     const bool split = bp.split_heavy && flops[i] > bp.hash_max_flops;
+    const bool ranked = bp.rank_heavy && flops[i] > bp.hash_max_flops && c_ptr[i + 1] > bp.hash_max_nnz;
     const bool kept = bp.row_slot && flops[i] > bp.hash_max_flops && bp.row_slot[i] >= 0;
-    atomicAdd(&lc[kept ? kExpandBin : (split ? 0 : num_bin(c_ptr[i + 1], flops[i], bp))], 1u);
+    atomicAdd(&lc[kept ? kExpandBin : ((split || ranked) ? 0 : num_bin(c_ptr[i + 1], flops[i], bp))], 1u);
   }
   __syncthreads();
   if (tid < kNumBins && lc[tid]) atomicAdd(&counts[tid], static_cast<unsigned long long>(lc[tid]));
@@ -163,8 +164,11 @@ __global__ void k_scatter(int mode, int32_t m, const int64_t* __restrict__ flops
       bin = sym_bin(flops[i], bp);
     else if (bp.row_slot && flops[i] > bp.hash_max_flops && bp.row_slot[i] >= 0)
       bin = kExpandBin;
-    else
-      bin = (bp.split_heavy && flops[i] > bp.hash_max_flops) ? 0 : num_bin(c_ptr[i + 1] - c_ptr[i], flops[i], bp);
+    else {
+      const int64_t nz = c_ptr[i + 1] - c_ptr[i];
+      const bool ranked = bp.rank_heavy && flops[i] > bp.hash_max_flops && nz > bp.hash_max_nnz;
+      bin = ((bp.split_heavy && flops[i] > bp.hash_max_flops) || ranked) ? 0 : num_bin(nz, flops[i], bp);
+    }
     if (bin > 0) local = atomicAdd(&lc[bin], 1u);
   }
   __syncthreads();
@@ -950,6 +954,165 @@ __global__ __launch_bounds__(1024) void k_dense_num(Operands op, const int32_t* 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Rank-compressed panels for heavy valued rows.
+//
+// A fixed-width value panel spends one LDS slot per column, so a row whose
+// entries are spread thinly over many columns needs a pass per panel even
+// when each panel holds few entries.  Here the symbolic phase has counted the
+// row's entries per chunk of 2^cw columns.  A pass takes the longest run of
+// chunks whose entries fit the 2^cw value slots (and whose columns fit the LDS
+// bitmap), marks the pattern of that column range in a bitmap, takes a prefix
+// count per bitmap word, and then combines every product into the slot given
+// by its column's rank in the range.  The slots are then in column order: the
+// values are written out as they stand, the column ids from the bitmap.
+// Rows dense enough that fixed panels need fewer passes use fixed panels over
+// the same chunk index.
+// ---------------------------------------------------------------------------
+template <class SR>
+struct RankSink {
+  using S = typename SR::S;
+  const uint32_t* bits;
+  const uint16_t* pre;
+  S* vals;
+  __device__ void add(int32_t c, S v) {
+    const int w = c >> 5;
+    const uint32_t below = bits[w] & ((1u << (c & 31)) - 1u);
+    SR::combine(&vals[pre[w] + __popc(below)], v);
+  }
+};
+
+template <class SR>
+__host__ __device__ inline size_t rank_queue_bytes(int nt) {
+  const size_t a = RowQueue<typename SR::In>::bytes(nt);
+  const size_t b = RowQueue<SrPattern::In>::bytes(nt);
+  return a > b ? a : b;
+}
+
+template <class SR>
+__host__ __device__ inline size_t rank_num_lds_bytes(int cw, int max_chunks, int nt) {
+  const size_t cols = static_cast<size_t>(max_chunks) << cw;
+  return rank_queue_bytes<SR>(nt) + (sizeof(typename SR::S) << cw) + cols / 8 + (cols / 32) * 2;
+}
+
+template <class SR>
+__device__ void rank_num_row(const Operands& op, int64_t a_lo, int64_t a_hi, int cw, int NC,
+                             int max_chunks, const int32_t* __restrict__ pchunk,
+                             const int32_t* __restrict__ cnt, int short_seg, int64_t out, int64_t out_end,
+                             int32_t* __restrict__ c_idx, typename SR::Out* __restrict__ c_val,
+                             unsigned char* smem, int* info) {
+  using S = typename SR::S;
+  const int nt = blockDim.x;
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int slots = 1 << cw;
+  auto q = RowQueue<typename SR::In>::carve(smem, nt);
+  auto pq = RowQueue<SrPattern::In>::carve(smem, nt);  // same LDS, used by the pattern walk
+  unsigned char* p0 = smem + rank_queue_bytes<SR>(nt);
+  S* vals = reinterpret_cast<S*>(p0);
+  uint32_t* bits = reinterpret_cast<uint32_t*>(p0 + (sizeof(S) << cw));
+  uint16_t* pre = reinterpret_cast<uint16_t*>(bits + (static_cast<size_t>(max_chunks) << (cw - 5)));
+  for (int c_lo = 0; c_lo < NC;) {
+    if (tid < kWave) {
+      // The pass: the longest run of at most max_chunks chunks from c_lo whose
+      // entries fit the slots (one chunk always fits: it has 2^cw columns).
+      const int c = c_lo + lane;
+      const bool in = lane < max_chunks && c < NC;
+      const int v = in ? cnt[c] : 0;
+      const int incl = wave_inclusive_scan(v);
+      const unsigned long long fit = __ballot(in && incl <= slots);
+      const int n = __popcll(fit);
+      const int tot = __shfl(incl, n - 1, kWave);
+      if (lane == 0) {
+        info[0] = n;
+        info[1] = tot;
+      }
+    }
+    __syncthreads();
+    const int n = info[0];
+    const int total = info[1];
+    __syncthreads();  // info is rewritten by the next pass
+    const int c_hi = c_lo + n;
+    if (total > 0) {
+      const int32_t C0 = c_lo << cw;
+      const int32_t wcols = min(n << cw, op.k - C0);
+      const int nwords = (wcols + 31) >> 5;
+      for (int t = tid; t < nwords; t += nt) bits[t] = 0u;
+      for (int t = tid; t < total; t += nt) vals[t] = SR::identity();
+      __syncthreads();
+      // 1. pattern of the column range
+      BitmapSink bs{bits};
+      RowSource<SrPattern> ps{&op, a_lo, a_hi, true, pchunk, NC, c_lo, c_hi};
+      enumerate_src<SrPattern>(op, ps, C0, short_seg, pq, bs);
+      // 2. rank of the first entry of every bitmap word (contiguous words per thread)
+      const int wpt = (nwords + nt - 1) / nt;
+      const int w0 = min(nwords, tid * wpt), w1 = min(nwords, w0 + wpt);
+      int local = 0;
+      for (int w = w0; w < w1; ++w) local += __popc(bits[w]);
+      int ptotal;
+      int run = block_exclusive_scan(local, q.ctr + 2, &ptotal);
+      for (int w = w0; w < w1; ++w) {
+        pre[w] = static_cast<uint16_t>(run);
+        run += __popc(bits[w]);
+      }
+      __syncthreads();
+      // 3. values, combined at their ranks
+      RankSink<SR> rs{bits, pre, vals};
+      RowSource<SR> vs{&op, a_lo, a_hi, true, pchunk, NC, c_lo, c_hi};
+      enumerate_src<SR>(op, vs, C0, short_seg, q, rs);
+      // 4. write the range out: values in slot order, ids from the bitmap
+      const int lim = static_cast<int>(min(static_cast<int64_t>(total), out_end - out));
+      for (int r = tid; r < lim; r += nt) c_val[out + r] = SR::out(vals[r]);
+      for (int w = tid; w < nwords; w += nt) {
+        uint32_t x = bits[w];
+        int64_t o = out + pre[w];
+        while (x) {
+          const int b = __ffs(x) - 1;
+          if (o < out_end) c_idx[o] = C0 + (w << 5) + b;
+          x &= x - 1;
+          ++o;
+        }
+      }
+      out += total;
+      __syncthreads();
+    }
+    c_lo = c_hi;
+  }
+}
+
+// Heavy valued rows of the dense symbolic list (slot order), those with more
+// than hash_max_nnz entries; the others went to the hash numeric bins.
+template <class SR>
+__global__ __launch_bounds__(1024) void k_rank_num(Operands op, const int32_t* __restrict__ rows,
+                                                   int64_t nrows, int cw, int NC, int max_chunks,
+                                                   const int32_t* __restrict__ pchunk,
+                                                   const int32_t* __restrict__ rcnt, int64_t hash_max_nnz,
+                                                   int dense_div, int wlog2, int P, int short_seg,
+                                                   const int64_t* __restrict__ c_ptr,
+                                                   int32_t* __restrict__ c_idx,
+                                                   typename SR::Out* __restrict__ c_val) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int info[2];
+  for (int64_t it = blockIdx.x; it < nrows; it += gridDim.x) {
+    const int32_t row = uniform(rows[it]);
+    const int64_t out = uniform64(c_ptr[row]), out_end = uniform64(c_ptr[row + 1]);
+    const int64_t nnz = out_end - out;
+    if (nnz <= hash_max_nnz) continue;
+    const int64_t a_lo = op.a_ptr[row], a_hi = op.a_ptr[row + 1];
+    if (nnz * dense_div >= op.k) {
+      // fixed panels of 2^wlog2 columns = 2^(wlog2-cw) chunks
+      const int r = 1 << (wlog2 - cw);
+      auto make = [&](int p) {
+        return RowSource<SR>{&op, a_lo, a_hi, true, pchunk, NC, p * r, min((p + 1) * r, NC)};
+      };
+      dense_num_gen<SR>(op, wlog2, 0, P, short_seg, out, out_end, c_idx, c_val, smem, make);
+    } else {
+      rank_num_row<SR>(op, a_lo, a_hi, cw, NC, max_chunks, pchunk, rcnt + it * NC, short_seg, out,
+                       out_end, c_idx, c_val, smem, info);
+    }
+  }
+}
+
 // (row, panel) pieces of heavy rows: one panel of one row per work item.
 template <class SR>
 __global__ __launch_bounds__(1024) void k_hash_num_sub(Operands op, const int32_t* __restrict__ rows,
@@ -1194,6 +1357,30 @@ static hipError_t dense_num_t(const Operands& op, const int32_t* rows, int64_t n
 }
 
 template <class SR>
+static size_t rank_num_lds_t(int cw, int max_chunks, int wlog2, int nt) {
+  const size_t a = rank_num_lds_bytes<SR>(cw, max_chunks, nt);
+  const size_t b = dense_num_lds_t<SR>(wlog2, nt);
+  return a > b ? a : b;
+}
+
+template <class SR>
+static hipError_t rank_num_t(const Operands& op, const int32_t* rows, int64_t nrows, int cw, int NC,
+                             int max_chunks, const int32_t* pchunk, const int32_t* rcnt, int64_t hash_max_nnz,
+                             int dense_div, int wlog2, int P, int nt, int short_seg, const int64_t* c_ptr,
+                             int32_t* c_idx, void* c_val, hipStream_t s) {
+  if (nrows <= 0) return hipSuccess;
+  if constexpr (SR::kPattern) {
+    return hipErrorInvalidValue;  // pattern-only rows use the bitmap paths
+  } else {
+    hipLaunchKernelGGL(k_rank_num<SR>, dim3(grid_for(nrows, 0)), dim3(nt),
+                       rank_num_lds_t<SR>(cw, max_chunks, wlog2, nt), s, op, rows, nrows, cw, NC, max_chunks,
+                       pchunk, rcnt, hash_max_nnz, dense_div, wlog2, P, short_seg, c_ptr, c_idx,
+                       static_cast<typename SR::Out*>(c_val));
+    return hipGetLastError();
+  }
+}
+
+template <class SR>
 static hipError_t hash_num_b_t(const BatchDesc* descs, const int64_t* row_off, int nprod,
                                const int32_t* items, int64_t nitems, int T, int nt, int short_seg,
                                int64_t grid_cap, hipStream_t s) {
@@ -1292,6 +1479,14 @@ hipError_t launch_dense_num(int sr, const Operands& op, const int32_t* rows, int
                s)
 }
 
+hipError_t launch_rank_num(int sr, const Operands& op, const int32_t* rows, int64_t nrows, int cw, int NC,
+                           int max_chunks, const int32_t* pchunk, const int32_t* rcnt, int64_t hash_max_nnz,
+                           int dense_div, int wlog2, int P, int nt, int short_seg, const int64_t* c_ptr,
+                           int32_t* c_idx, void* c_val, hipStream_t s) {
+  SPG_DISPATCH(sr, rank_num_t, op, rows, nrows, cw, NC, max_chunks, pchunk, rcnt, hash_max_nnz, dense_div,
+               wlog2, P, nt, short_seg, c_ptr, c_idx, c_val, s)
+}
+
 hipError_t launch_hash_num_b(int sr, const BatchDesc* descs, const int64_t* row_off, int nprod,
                              const int32_t* items, int64_t nitems, int T, int nt, int short_seg,
                              int64_t grid_cap, hipStream_t s) {
@@ -1344,6 +1539,9 @@ size_t seg_desc_bytes() { return sizeof(SegDesc); }
 
 size_t hash_num_lds(int sr, int T, int nt) { SPG_DISPATCH(sr, hash_num_lds_t, T, nt) }
 size_t dense_num_lds(int sr, int wlog2, int nt) { SPG_DISPATCH(sr, dense_num_lds_t, wlog2, nt) }
+size_t rank_num_lds(int sr, int cw, int max_chunks, int wlog2, int nt) {
+  SPG_DISPATCH(sr, rank_num_lds_t, cw, max_chunks, wlog2, nt)
+}
 
 template <class SR>
 static size_t storage_bytes_t() {

@@ -17,6 +17,8 @@ struct BinParams {
   int64_t hash_max_nnz;    // numeric: hash when nnz <= this
   int64_t split_heavy;     // numeric: rows past hash_max_flops go as (row, panel) pieces
   const int32_t* row_slot; // numeric: rows with a kept bitmap (slot >= 0) are expanded
+  int64_t rank_heavy;      // numeric: rows past hash_max_flops with more than
+                           // hash_max_nnz entries go to the rank-panel kernel
 };
 constexpr int kExpandBin = 15;  // numeric bin of rows whose bitmap was kept
 
@@ -137,6 +139,15 @@ hipError_t launch_hash_num(int sr, const Operands& op, const int32_t* rows, int6
 hipError_t launch_dense_num(int sr, const Operands& op, const int32_t* rows, int64_t nrows,
                             int wlog2, int P, const int32_t* pidx, int nt, int short_seg,
                             const int64_t* c_ptr, int32_t* c_idx, void* c_val, hipStream_t s);
+// Heavy valued rows (the dense symbolic list, slot order) through rank-compressed
+// panels: chunks of 2^cw columns, rcnt[slot*NC + c] entries per chunk, pchunk
+// the chunk index of B; rows with nnz*dense_div >= k use fixed panels of
+// 2^wlog2 columns (P of them) over the same index.
+hipError_t launch_rank_num(int sr, const Operands& op, const int32_t* rows, int64_t nrows, int cw, int NC,
+                           int max_chunks, const int32_t* pchunk, const int32_t* rcnt, int64_t hash_max_nnz,
+                           int dense_div, int wlog2, int P, int nt, int short_seg, const int64_t* c_ptr,
+                           int32_t* c_idx, void* c_val, hipStream_t s);
+size_t rank_num_lds(int sr, int cw, int max_chunks, int wlog2, int nt);
 hipError_t launch_hash_sym_b(const BatchDesc* descs, const int64_t* row_off, int nprod,
                              const int32_t* items, int64_t nitems, int T, int nt, int short_seg,
                              int64_t grid_cap, hipStream_t s);

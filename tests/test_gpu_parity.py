@@ -43,23 +43,46 @@ def test_skewed_rmat_default_bins(sr):
 
 @pytest.mark.parametrize("sr", ["plus_times_f64", "min_plus_i32", "or_and_bool", "max_times_f32"])
 @pytest.mark.parametrize("mode", ["all_dense", "many_panels", "many_panels_in_sequence",
-                                  "many_panels_rewalk", "windows", "all_hash_small_threads"])
+                                  "many_panels_rewalk", "windows", "all_hash_small_threads",
+                                  "rank_small_slots", "rank_all", "rank_fixed_via_chunks"])
 def test_forced_paths(sr, mode):
     """The same product through forced accumulators: every row dense; dense
     with many narrow panels (panel index in use), as (row, panel) pieces or
-    panel after panel in one workgroup; short segments split."""
+    panel after panel in one workgroup; short segments split; rank-compressed
+    passes with few value slots (rows over several passes, by slot count and
+    by bitmap width), and fixed panels taken over the chunk index."""
     A = with_semiring_values(_skewed(5000, 10, 4), sr, np.random.default_rng(5))
     o = {"all_dense": opts(hash_max_flops=32, hash_max_nnz=32),
          "many_panels": opts(hash_max_flops=32, hash_max_nnz=32, sym_panel_log2=8, lds_budget=1024,
                              dense_threads=256, split_panels=1),
          "many_panels_in_sequence": opts(hash_max_flops=32, hash_max_nnz=32, sym_panel_log2=8,
-                                         lds_budget=1024, dense_threads=256, split_panels=-1),
+                                         lds_budget=1024, dense_threads=256, split_panels=-1,
+                                         rank_panels=-1),
+         # 128 value slots per pass, chunks of 128 columns, bitmap of 64 chunks
+         "rank_small_slots": opts(hash_max_flops=32, hash_max_nnz=32, sym_panel_log2=8, lds_budget=1024,
+                                  dense_threads=256),
+         "rank_all": opts(hash_max_flops=64, hash_max_nnz=64, lds_budget=8192, rank_dense_div=1),
+         "rank_fixed_via_chunks": opts(hash_max_flops=32, hash_max_nnz=32, sym_panel_log2=8, lds_budget=1024,
+                                       rank_dense_div=100000),
          # no room for segment lists: pieces re-walk their rows
          "many_panels_rewalk": opts(hash_max_flops=32, hash_max_nnz=32, sym_panel_log2=8, lds_budget=1024,
                                     dense_threads=256, seg_mib=1, split_panels=1),
          "windows": opts(hash_max_flops=64, hash_max_nnz=512, lds_budget=4096, split_panels=1),
          "all_hash_small_threads": opts(short_seg=1, dense_threads=64)}[mode]
     got = run_gpu(A, A, sr, o)
+    assert_parity(A, A, sr, got)
+
+
+@pytest.mark.parametrize("sr", ["plus_times_f64", "plus_times_f32", "min_plus_i32", "max_times_f64",
+                                "or_and_bool"])
+@pytest.mark.parametrize("div", [4, 1, 100000])
+def test_rank_panels_default_widths(sr, div):
+    """More columns than one value panel holds (70,000), default slot and chunk
+    widths (2^14 columns for 4-byte accumulators, 2^13 for 8-byte; fixed
+    panels of two chunks): heavy rows by rank passes, by fixed panels, or a
+    mix split by density."""
+    A = with_semiring_values(_skewed(70000, 2, 21, symmetric=True), sr, np.random.default_rng(22))
+    got = run_gpu(A, A, sr, opts(rank_dense_div=div))
     assert_parity(A, A, sr, got)
 
 
