@@ -49,6 +49,8 @@ def parse():
                     help="extra option for the valued product, key=value (e.g. split_panels=-1)")
     ap.add_argument("--bitmap-mib", type=int, default=24576,
                     help="workspace for symbolic bitmaps kept for the pattern-only numeric phase")
+    ap.add_argument("--bitmap-mib-valued", type=int, default=28672,
+                    help="workspace for symbolic bitmaps kept for the rank passes of the (min,+) product")
     return ap.parse_args()
 
 
@@ -137,7 +139,7 @@ def run_rmat(args):
     s_in = {"or_and_bool": 0, "min_plus_i32": 4}
     s_out = {"or_and_bool": 0, "min_plus_i32": 4}
     opts = {"or_and_bool": B.make_options(timing=1, bitmap_mib=args.bitmap_mib),
-            "min_plus_i32": B.make_options(timing=1, seg_mib=20480,
+            "min_plus_i32": B.make_options(timing=1, bitmap_mib=args.bitmap_mib_valued,
                                            **{k: int(v) for k, v in (o.split("=") for o in args.opt)})}
     prods = {sr: S.Product(mats[sr], mats[sr], sr, opts[sr]) for sr in semirings}
     c_ptr = torch.empty(H.nrows + 1, dtype=torch.int64, device=dev)

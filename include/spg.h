@@ -122,11 +122,13 @@ typedef struct spg_options {
                               (one work item each, LDS hash or one dense
                               panel); 0 (default) or -1 processes the panels
                               of a row in sequence in one workgroup */
-  int32_t bitmap_mib;      /* pattern-only (OR,AND) products: MiB of workspace
-                              in which the symbolic phase keeps the column
-                              bitmaps of its heaviest rows, so the numeric
-                              phase expands them instead of recomputing
-                              (default 0: off) */
+  int32_t bitmap_mib;      /* MiB of workspace in which the symbolic phase
+                              keeps the column bitmaps of its heaviest rows
+                              (C no wider than the symbolic bitmap): a
+                              pattern-only (OR,AND) product expands them in
+                              its numeric phase instead of recomputing; rank
+                              passes read their pattern from them (default 0:
+                              off) */
   int32_t seg_mib;         /* MiB of workspace for the segment lists of
                               (row, panel) pieces (default 16384); a product
                               that needs more falls back to re-walking each

@@ -35,7 +35,7 @@ struct spg_plan {
   bool split;                    // heavy rows go to the numeric phase as (row, panel) pieces
   size_t off_subcnt, off_suboff, off_subitems, off_wend;
   int64_t n_dense_sym;
-  bool keep;                     // pattern-only: keep heavy rows' symbolic bitmaps
+  bool keep;                     // keep heavy rows' symbolic bitmaps for the numeric phase
   size_t off_rowslot, off_store;
   int64_t keep_nwords, keep_min_flops;
   unsigned int keep_cap;
@@ -285,9 +285,12 @@ spg_status spg_plan_create(const spg_matrix* A, const spg_matrix* B, spg_semirin
   if (p->sym_P > 1) off = align_up(off + static_cast<size_t>(nB) * (p->sym_P + 1) * sizeof(int32_t));
   p->off_pnum = off;
   if (p->num_P > 1) off = align_up(off + static_cast<size_t>(nB) * (p->num_P + 1) * sizeof(int32_t));
-  p->keep = p->sr == 7 && p->sym_P == 1 && p->opt.bitmap_mib > 0 && p->op.k > 0;
+  // Kept bitmaps.  Pattern-only rows are expanded from them (worth it past
+  // 4 products per bitmap word); rank-panel rows read their pattern from them
+  // instead of walking B's column ids once more (worth it past one).
+  p->keep = (p->sr == 7 || p->rank) && p->sym_P == 1 && p->opt.bitmap_mib > 0 && p->op.k > 0;
   p->keep_nwords = (static_cast<int64_t>(p->op.k) + 31) / 32;
-  p->keep_min_flops = 4 * p->keep_nwords;
+  p->keep_min_flops = (p->sr == 7 ? 4 : 1) * p->keep_nwords;
   p->keep_cap = 0;
   if (p->keep) {
     const int64_t cap = (static_cast<int64_t>(p->opt.bitmap_mib) << 20) / (p->keep_nwords * 4);
@@ -509,7 +512,8 @@ spg_status spg_symbolic(spg_plan* p, void* ws, int64_t* c_ptr, int64_t* c_nnz) {
   }
   int64_t total = 0;
   p->n_dense_sym = ndense;
-  p->bp.row_slot = (p->keep && ndense > 0) ? reinterpret_cast<const int32_t*>(w + p->off_rowslot) : nullptr;
+  p->bp.row_slot =
+      (p->keep && p->sr == 7 && ndense > 0) ? reinterpret_cast<const int32_t*>(w + p->off_rowslot) : nullptr;
   {
     PhaseTimer t(p, SPG_PHASE_SCAN);
     SPG_TRY_HIP(launch_count_num_bins(m, flops, c_ptr, p->bp, ctr + kCtrNum, s));
@@ -656,7 +660,10 @@ spg_status spg_numeric(spg_plan* p, void* ws, int32_t* c_idx, void* c_val) {
     SPG_TRY_HIP(launch_rank_num(p->sr, op, rows_dense_sym, p->n_dense_sym, p->rank_cw, p->rank_NC, p->rank_maxc,
                                 pchunk, reinterpret_cast<const int32_t*>(w + p->off_rcnt), p->bp.hash_max_nnz,
                                 p->opt.rank_dense_div, p->num_wlog2, p->num_P, p->opt.dense_threads,
-                                p->opt.short_seg, p->c_ptr, c_idx, c_val, s));
+                                p->opt.short_seg,
+                                p->keep ? reinterpret_cast<const uint32_t*>(w + p->off_store) : nullptr,
+                                p->keep ? reinterpret_cast<const int32_t*>(w + p->off_rowslot) : nullptr,
+                                p->keep_nwords, p->c_ptr, c_idx, c_val, s));
   }
   return SPG_OK;
 }

@@ -998,7 +998,8 @@ __host__ __device__ inline size_t rank_num_lds_bytes(int cw, int max_chunks, int
 template <class SR>
 __device__ void rank_num_row(const Operands& op, int64_t a_lo, int64_t a_hi, int cw, int NC,
                              int max_chunks, const int32_t* __restrict__ pchunk,
-                             const int32_t* __restrict__ cnt, int short_seg, int64_t out, int64_t out_end,
+                             const int32_t* __restrict__ cnt, const uint32_t* __restrict__ keep,
+                             int short_seg, int64_t out, int64_t out_end,
                              int32_t* __restrict__ c_idx, typename SR::Out* __restrict__ c_val,
                              unsigned char* smem, int* info) {
   using S = typename SR::S;
@@ -1037,13 +1038,20 @@ __device__ void rank_num_row(const Operands& op, int64_t a_lo, int64_t a_hi, int
       const int32_t C0 = c_lo << cw;
       const int32_t wcols = min(n << cw, op.k - C0);
       const int nwords = (wcols + 31) >> 5;
-      for (int t = tid; t < nwords; t += nt) bits[t] = 0u;
       for (int t = tid; t < total; t += nt) vals[t] = SR::identity();
-      __syncthreads();
-      // 1. pattern of the column range
-      BitmapSink bs{bits};
-      RowSource<SrPattern> ps{&op, a_lo, a_hi, true, pchunk, NC, c_lo, c_hi};
-      enumerate_src<SrPattern>(op, ps, C0, short_seg, pq, bs);
+      // 1. pattern of the column range: from the kept bitmap, or by a walk
+      //    over B's column ids
+      if (keep) {
+        const uint32_t* src = keep + (C0 >> 5);
+        for (int t = tid; t < nwords; t += nt) bits[t] = src[t];
+        __syncthreads();
+      } else {
+        for (int t = tid; t < nwords; t += nt) bits[t] = 0u;
+        __syncthreads();
+        BitmapSink bs{bits};
+        RowSource<SrPattern> ps{&op, a_lo, a_hi, true, pchunk, NC, c_lo, c_hi};
+        enumerate_src<SrPattern>(op, ps, C0, short_seg, pq, bs);
+      }
       // 2. rank of the first entry of every bitmap word (contiguous words per thread)
       const int wpt = (nwords + nt - 1) / nt;
       const int w0 = min(nwords, tid * wpt), w1 = min(nwords, w0 + wpt);
@@ -1088,6 +1096,8 @@ __global__ __launch_bounds__(1024) void k_rank_num(Operands op, const int32_t* _
                                                    const int32_t* __restrict__ pchunk,
                                                    const int32_t* __restrict__ rcnt, int64_t hash_max_nnz,
                                                    int dense_div, int wlog2, int P, int short_seg,
+                                                   const uint32_t* __restrict__ keep_store,
+                                                   const int32_t* __restrict__ keep_slot, int64_t keep_nwords,
                                                    const int64_t* __restrict__ c_ptr,
                                                    int32_t* __restrict__ c_idx,
                                                    typename SR::Out* __restrict__ c_val) {
@@ -1107,7 +1117,9 @@ __global__ __launch_bounds__(1024) void k_rank_num(Operands op, const int32_t* _
       };
       dense_num_gen<SR>(op, wlog2, 0, P, short_seg, out, out_end, c_idx, c_val, smem, make);
     } else {
-      rank_num_row<SR>(op, a_lo, a_hi, cw, NC, max_chunks, pchunk, rcnt + it * NC, short_seg, out,
+      const int32_t slot = keep_slot ? uniform(keep_slot[row]) : -1;
+      const uint32_t* keep = slot >= 0 ? keep_store + static_cast<int64_t>(slot) * keep_nwords : nullptr;
+      rank_num_row<SR>(op, a_lo, a_hi, cw, NC, max_chunks, pchunk, rcnt + it * NC, keep, short_seg, out,
                        out_end, c_idx, c_val, smem, info);
     }
   }
@@ -1366,7 +1378,8 @@ static size_t rank_num_lds_t(int cw, int max_chunks, int wlog2, int nt) {
 template <class SR>
 static hipError_t rank_num_t(const Operands& op, const int32_t* rows, int64_t nrows, int cw, int NC,
                              int max_chunks, const int32_t* pchunk, const int32_t* rcnt, int64_t hash_max_nnz,
-                             int dense_div, int wlog2, int P, int nt, int short_seg, const int64_t* c_ptr,
+                             int dense_div, int wlog2, int P, int nt, int short_seg, const uint32_t* keep_store,
+                             const int32_t* keep_slot, int64_t keep_nwords, const int64_t* c_ptr,
                              int32_t* c_idx, void* c_val, hipStream_t s) {
   if (nrows <= 0) return hipSuccess;
   if constexpr (SR::kPattern) {
@@ -1374,8 +1387,8 @@ static hipError_t rank_num_t(const Operands& op, const int32_t* rows, int64_t nr
   } else {
     hipLaunchKernelGGL(k_rank_num<SR>, dim3(grid_for(nrows, 0)), dim3(nt),
                        rank_num_lds_t<SR>(cw, max_chunks, wlog2, nt), s, op, rows, nrows, cw, NC, max_chunks,
-                       pchunk, rcnt, hash_max_nnz, dense_div, wlog2, P, short_seg, c_ptr, c_idx,
-                       static_cast<typename SR::Out*>(c_val));
+                       pchunk, rcnt, hash_max_nnz, dense_div, wlog2, P, short_seg, keep_store, keep_slot,
+                       keep_nwords, c_ptr, c_idx, static_cast<typename SR::Out*>(c_val));
     return hipGetLastError();
   }
 }
@@ -1481,10 +1494,11 @@ hipError_t launch_dense_num(int sr, const Operands& op, const int32_t* rows, int
 
 hipError_t launch_rank_num(int sr, const Operands& op, const int32_t* rows, int64_t nrows, int cw, int NC,
                            int max_chunks, const int32_t* pchunk, const int32_t* rcnt, int64_t hash_max_nnz,
-                           int dense_div, int wlog2, int P, int nt, int short_seg, const int64_t* c_ptr,
+                           int dense_div, int wlog2, int P, int nt, int short_seg, const uint32_t* keep_store,
+                           const int32_t* keep_slot, int64_t keep_nwords, const int64_t* c_ptr,
                            int32_t* c_idx, void* c_val, hipStream_t s) {
   SPG_DISPATCH(sr, rank_num_t, op, rows, nrows, cw, NC, max_chunks, pchunk, rcnt, hash_max_nnz, dense_div,
-               wlog2, P, nt, short_seg, c_ptr, c_idx, c_val, s)
+               wlog2, P, nt, short_seg, keep_store, keep_slot, keep_nwords, c_ptr, c_idx, c_val, s)
 }
 
 hipError_t launch_hash_num_b(int sr, const BatchDesc* descs, const int64_t* row_off, int nprod,

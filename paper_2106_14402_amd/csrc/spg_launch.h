@@ -142,10 +142,13 @@ hipError_t launch_dense_num(int sr, const Operands& op, const int32_t* rows, int
 // Heavy valued rows (the dense symbolic list, slot order) through rank-compressed
 // panels: chunks of 2^cw columns, rcnt[slot*NC + c] entries per chunk, pchunk
 // the chunk index of B; rows with nnz*dense_div >= k use fixed panels of
-// 2^wlog2 columns (P of them) over the same index.
+// 2^wlog2 columns (P of them) over the same index.  Rows with a kept symbolic
+// bitmap (keep_slot[row] >= 0, keep_nwords words each in keep_store) read
+// their pattern from it.
 hipError_t launch_rank_num(int sr, const Operands& op, const int32_t* rows, int64_t nrows, int cw, int NC,
                            int max_chunks, const int32_t* pchunk, const int32_t* rcnt, int64_t hash_max_nnz,
-                           int dense_div, int wlog2, int P, int nt, int short_seg, const int64_t* c_ptr,
+                           int dense_div, int wlog2, int P, int nt, int short_seg, const uint32_t* keep_store,
+                           const int32_t* keep_slot, int64_t keep_nwords, const int64_t* c_ptr,
                            int32_t* c_idx, void* c_val, hipStream_t s);
 size_t rank_num_lds(int sr, int cw, int max_chunks, int wlog2, int nt);
 hipError_t launch_hash_sym_b(const BatchDesc* descs, const int64_t* row_off, int nprod,

@@ -107,8 +107,8 @@ def test_rmat20_bool_and_min_plus(rmat20):
     assert_parity(Hpat, Hpat, "or_and_bool", got, select=rows,
                   want=oracle.spgemm(Hpat, Hpat, "or_and_bool", select=rows, nthreads=NTHREADS))
 
-    # (min,+) int32 with the benchmarked segment-list budget
-    p = S.Product(dA, dA, "min_plus_i32", B.make_options(seg_mib=20480))
+    # (min,+) int32 with the benchmarked kept-bitmap budget for its rank passes
+    p = S.Product(dA, dA, "min_plus_i32", B.make_options(bitmap_mib=28672))
     nnz_m = p.symbolic()
     C = p.numeric()
     assert nnz_m == nnz_b

@@ -44,7 +44,8 @@ def test_skewed_rmat_default_bins(sr):
 @pytest.mark.parametrize("sr", ["plus_times_f64", "min_plus_i32", "or_and_bool", "max_times_f32"])
 @pytest.mark.parametrize("mode", ["all_dense", "many_panels", "many_panels_in_sequence",
                                   "many_panels_rewalk", "windows", "all_hash_small_threads",
-                                  "rank_small_slots", "rank_all", "rank_fixed_via_chunks"])
+                                  "rank_small_slots", "rank_all", "rank_kept_bitmaps",
+                                  "rank_fixed_via_chunks"])
 def test_forced_paths(sr, mode):
     """The same product through forced accumulators: every row dense; dense
     with many narrow panels (panel index in use), as (row, panel) pieces or
@@ -62,6 +63,8 @@ def test_forced_paths(sr, mode):
          "rank_small_slots": opts(hash_max_flops=32, hash_max_nnz=32, sym_panel_log2=8, lds_budget=1024,
                                   dense_threads=256),
          "rank_all": opts(hash_max_flops=64, hash_max_nnz=64, lds_budget=8192, rank_dense_div=1),
+         "rank_kept_bitmaps": opts(hash_max_flops=32, hash_max_nnz=32, lds_budget=1024, dense_threads=256,
+                                   bitmap_mib=1),
          "rank_fixed_via_chunks": opts(hash_max_flops=32, hash_max_nnz=32, sym_panel_log2=8, lds_budget=1024,
                                        rank_dense_div=100000),
          # no room for segment lists: pieces re-walk their rows
@@ -75,14 +78,15 @@ def test_forced_paths(sr, mode):
 
 @pytest.mark.parametrize("sr", ["plus_times_f64", "plus_times_f32", "min_plus_i32", "max_times_f64",
                                 "or_and_bool"])
-@pytest.mark.parametrize("div", [4, 1, 100000])
-def test_rank_panels_default_widths(sr, div):
+@pytest.mark.parametrize("div,mib", [(4, 0), (1, 0), (100000, 0), (4, 1), (1, 64)])
+def test_rank_panels_default_widths(sr, div, mib):
     """More columns than one value panel holds (70,000), default slot and chunk
     widths (2^14 columns for 4-byte accumulators, 2^13 for 8-byte; fixed
     panels of two chunks): heavy rows by rank passes, by fixed panels, or a
-    mix split by density."""
+    mix split by density; pattern walked again or read from kept symbolic
+    bitmaps (room for some rows, or for all)."""
     A = with_semiring_values(_skewed(70000, 2, 21, symmetric=True), sr, np.random.default_rng(22))
-    got = run_gpu(A, A, sr, opts(rank_dense_div=div))
+    got = run_gpu(A, A, sr, opts(rank_dense_div=div, bitmap_mib=mib))
     assert_parity(A, A, sr, got)
 
 
