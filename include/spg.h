@@ -104,7 +104,10 @@ typedef struct spg_options {
   int32_t hash_max_flops;  /* symbolic: rows with more products than this use
                               the dense bitmap accumulator (default 8192) */
   int32_t hash_max_nnz;    /* numeric: rows with more output entries than this
-                              use the dense panel accumulator (default 4096) */
+                              use the dense panel accumulator (at most 8192,
+                              and only where a table of twice that fits in
+                              LDS; default 8192 for 4-byte accumulators,
+                              4096 for 8-byte ones and the pattern) */
   int32_t short_seg;       /* B-row segments up to this length are walked by
                               one lane; longer ones are split across the
                               waves of a workgroup (default 32) */
@@ -289,7 +292,8 @@ spg_status spg_batch_numeric(spg_batch_plan* plan, void* ws, int32_t* c_idx, voi
 
 /* Captures the numeric phase (same arguments) into a hipGraph held by the
  * plan, without running it; spg_batch_graph_launch replays it on the plan's
- * stream.  The capture stays valid while the inputs, workspace and pools do. */
+ * stream.  The capture stays valid while the inputs, workspace and pools do,
+ * until the next spg_batch_symbolic call, which drops it. */
 spg_status spg_batch_graph_capture(spg_batch_plan* plan, void* ws, int32_t* c_idx, void* c_val,
                                    const int64_t* val_off);
 spg_status spg_batch_graph_launch(spg_batch_plan* plan);

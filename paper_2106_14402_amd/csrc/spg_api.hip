@@ -107,11 +107,20 @@ spg_status check_matrix(const spg_matrix* M) {
 
 int ilog2_ceil(int64_t x) { return ceil_log2_u64(static_cast<uint64_t>(x < 1 ? 1 : x)); }
 
-void resolve_options(const spg_options* in, spg_options* o) {
+void resolve_options(const spg_options* in, spg_options* o, int sr) {
   std::memset(o, 0, sizeof(*o));
   if (in) *o = *in;
   if (o->hash_max_flops <= 0) o->hash_max_flops = 8192;
-  if (o->hash_max_nnz <= 0) o->hash_max_nnz = 4096;
+  if (o->hash_max_nnz <= 0) {
+    // Valued rows: as many output entries as a hash table of twice the size
+    // holds in LDS.  Pattern-only rows: 4096 (a bitmap panel is cheaper than
+    // the largest table for them).
+    const int c = hash_class(8192);
+    o->hash_max_nnz = sr != 7 && hash_num_lds(sr, hash_table_size(c), hash_threads_num(c, sr)) <=
+                                     static_cast<size_t>(max_lds_bytes())
+                          ? 8192
+                          : 4096;
+  }
   if (o->short_seg <= 0) o->short_seg = 32;
   if (o->dense_threads <= 0) o->dense_threads = 1024;
   if (o->sym_panel_log2 <= 0) o->sym_panel_log2 = 20;
@@ -122,7 +131,7 @@ void resolve_options(const spg_options* in, spg_options* o) {
 
 spg_status check_options(const spg_options& o, int sr) {
   if (o.hash_max_flops > 16384 || o.hash_max_flops < 32) return SPG_E_INVALID;
-  if (o.hash_max_nnz < 32 || o.hash_max_nnz > 4096) return SPG_E_INVALID;
+  if (o.hash_max_nnz < 32 || o.hash_max_nnz > 8192) return SPG_E_INVALID;
   if (o.dense_threads % kWave != 0 || o.dense_threads > 1024) return SPG_E_INVALID;
   if (o.sym_panel_log2 < 7 || o.sym_panel_log2 > 20) return SPG_E_INVALID;
   // hash tables must fit in LDS
@@ -204,7 +213,7 @@ spg_status spg_plan_create(const spg_matrix* A, const spg_matrix* B, spg_semirin
   p->op.k = p->csc ? A->nrows : B->ncols;
   p->sr = (bool_sr && !A->val && !B->val) ? 7 : sr;
 
-  resolve_options(opt_in, &p->opt);
+  resolve_options(opt_in, &p->opt, p->sr);
   if ((st = check_options(p->opt, p->sr)) != SPG_OK) {
     delete p;
     return st;

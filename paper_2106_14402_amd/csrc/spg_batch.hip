@@ -466,7 +466,12 @@ spg_status spg_batch_symbolic(spg_batch_plan* p, void* ws, int64_t* c_ptr_pool, 
   auto* bases = reinterpret_cast<int64_t*>(w + p->off_bases);
   auto* offs = reinterpret_cast<int64_t*>(w + p->off_offs);
   const int nprod = p->nprod;
-  p->has_graph = false;
+  if (p->has_graph) {
+    // a new symbolic pass may change the launch shapes: the capture is dropped
+    (void)hipGraphExecDestroy(p->graph_exec);
+    (void)hipGraphDestroy(p->graph);
+    p->has_graph = false;
+  }
   for (int b = 0; b < nprod; ++b) {
     p->desc[b].c_ptr = c_ptr_pool + p->pool_off[b];
     p->desc[b].c_idx = nullptr;
