@@ -192,8 +192,11 @@ def run_rmat(args):
                          minlength=H.nrows)
         sym_dense_rows = fl > 8192
         ranked = phase_ms[sr].get("num_rank", 0.0) > 0
-        rank_rows = sym_dense_rows & (rownnz > 4096) if ranked else np.zeros_like(sym_dense_rows)
-        num_dense_rows = (rownnz > 4096) & ~rank_rows
+        hmn = p.hash_max_nnz()
+        heavy = sym_dense_rows & (rownnz > hmn)
+        fixed_rows = heavy & (rownnz * p.rank_dense_div() >= H.ncols)
+        rank_rows = heavy & ~fixed_rows if ranked else np.zeros_like(sym_dense_rows)
+        num_dense_rows = (rownnz > hmn) & ~rank_rows
 
         def dense_bytes(rows):
             return alg_bytes_dense(H, int(deg[rows].sum()), int(rows.sum()), int(rownnz[rows].sum()),

@@ -219,6 +219,10 @@ spg_status spg_plan_bins(const spg_plan* plan, int64_t* sym, int64_t* num);
 
 spg_status spg_plan_destroy(spg_plan* plan);
 
+/* The options the plan runs with, defaults filled in (host, after plan
+ * creation).  Errors: SPG_E_INVALID for a NULL argument. */
+spg_status spg_plan_options(const spg_plan* plan, spg_options* out);
+
 const char* spg_status_str(spg_status s);
 
 /* Column panels.  A dense row accumulator covers 2^wlog2 columns of C at a

@@ -102,6 +102,8 @@ def load(path: str = LIB_PATH):
     pint = ctypes.POINTER(ctypes.c_int)
     L.spg_plan_panels.restype = st
     L.spg_plan_panels.argtypes = [vp, pint, pint, pint, pint]
+    L.spg_plan_options.restype = st
+    L.spg_plan_options.argtypes = [vp, ctypes.POINTER(spg_options)]
     L.spg_panel_index_size.restype = st
     L.spg_panel_index_size.argtypes = [pm, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]
     L.spg_panel_index_build.restype = st
@@ -233,6 +235,13 @@ def spg_plan_bins(plan):
 def spg_plan_destroy(plan) -> None:
     if plan:
         load().spg_plan_destroy(plan)
+
+
+def spg_plan_options(plan) -> spg_options:
+    """The options the plan runs with, defaults filled in."""
+    o = spg_options()
+    _check(load().spg_plan_options(plan, ctypes.byref(o)), "spg_plan_options")
+    return o
 
 
 def spg_plan_panels(plan):

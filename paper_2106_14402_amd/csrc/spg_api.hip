@@ -37,7 +37,7 @@ struct spg_plan {
   int64_t n_dense_sym;
   bool keep;                     // keep heavy rows' symbolic bitmaps for the numeric phase
   size_t off_rowslot, off_store;
-  int64_t keep_nwords, keep_min_flops;
+  int64_t keep_nwords, keep_stride, keep_min_flops;  // words per bitmap; slot stride (multiple of 4)
   unsigned int keep_cap;
   size_t off_segoff, off_segs;   // (row, panel) segment lists
   bool rank;                     // heavy valued rows through rank-compressed panels
@@ -299,17 +299,18 @@ spg_status spg_plan_create(const spg_matrix* A, const spg_matrix* B, spg_semirin
   // instead of walking B's column ids once more (worth it past one).
   p->keep = (p->sr == 7 || p->rank) && p->sym_P == 1 && p->opt.bitmap_mib > 0 && p->op.k > 0;
   p->keep_nwords = (static_cast<int64_t>(p->op.k) + 31) / 32;
+  p->keep_stride = (p->keep_nwords + 3) & ~int64_t(3);
   p->keep_min_flops = (p->sr == 7 ? 4 : 1) * p->keep_nwords;
   p->keep_cap = 0;
   if (p->keep) {
-    const int64_t cap = (static_cast<int64_t>(p->opt.bitmap_mib) << 20) / (p->keep_nwords * 4);
+    const int64_t cap = (static_cast<int64_t>(p->opt.bitmap_mib) << 20) / (p->keep_stride * 4);
     p->keep_cap = static_cast<unsigned int>(std::min<int64_t>(cap, std::max<int64_t>(m, 1)));
     if (p->keep_cap == 0) p->keep = false;
   }
   p->off_rowslot = off;
   if (p->keep) off = align_up(off + static_cast<size_t>(m) * sizeof(int32_t));
   p->off_store = off;
-  if (p->keep) off = align_up(off + static_cast<size_t>(p->keep_cap) * p->keep_nwords * 4);
+  if (p->keep) off = align_up(off + static_cast<size_t>(p->keep_cap) * p->keep_stride * 4);
   const size_t nsub = p->split ? static_cast<size_t>(m) * p->num_P : 0;
   p->off_subcnt = off;
   off = align_up(off + nsub * sizeof(int32_t));
@@ -387,6 +388,12 @@ spg_status spg_plan_bins(const spg_plan* p, int64_t* sym, int64_t* num) {
     if (sym) sym[b] = static_cast<int64_t>(p->sym_counts[b]);
     if (num) num[b] = static_cast<int64_t>(p->num_counts[b]);
   }
+  return SPG_OK;
+}
+
+spg_status spg_plan_options(const spg_plan* p, spg_options* out) {
+  if (!p || !out) return SPG_E_INVALID;
+  *out = p->opt;
   return SPG_OK;
 }
 
@@ -507,7 +514,7 @@ spg_status spg_symbolic(spg_plan* p, void* ws, int64_t* c_ptr, int64_t* c_nnz) {
       kb.counter = reinterpret_cast<unsigned int*>(ctr + kCtrMisc + 2);
       kb.flops = flops;
       kb.min_flops = p->keep_min_flops;
-      kb.nwords = p->keep_nwords;
+      kb.nwords = p->keep_stride;
       kb.capacity = p->keep_cap;
     }
     SPG_TRY_HIP(launch_dense_sym(op, rows_sym + so.v[kDenseBinBase], ndense, p->sym_wlog2, p->sym_P,
@@ -639,12 +646,27 @@ spg_status spg_numeric(spg_plan* p, void* ws, int32_t* c_idx, void* c_val) {
   if (p->num_counts[kExpandBin]) {
     PhaseTimer t(p, SPG_PHASE_NUM_EXPAND);
     SPG_TRY_HIP(launch_expand_rows(rows_num + no.v[kExpandBin], static_cast<int64_t>(p->num_counts[kExpandBin]),
-                                   static_cast<int>(p->keep_nwords),
+                                   static_cast<int>(p->keep_nwords), p->keep_stride,
                                    reinterpret_cast<const uint32_t*>(w + p->off_store),
                                    reinterpret_cast<const int32_t*>(w + p->off_rowslot), p->c_ptr, c_idx,
                                    1024, s));
   }
-  if (ndense > 0 || nsub_dense > 0) {
+  const bool ranked = p->rank && p->n_dense_sym > 0;
+  auto* pchunk = reinterpret_cast<int32_t*>(w + p->off_pchunk);
+  if (ranked) {
+    PhaseTimer tp(p, SPG_PHASE_NUM_PANELS);
+    SPG_TRY_HIP(launch_panel_index(op.b_ptr, op.b_idx, op.n, p->rank_cw, p->rank_NC, pchunk, s));
+  }
+  const uint32_t* kstore = p->keep ? reinterpret_cast<const uint32_t*>(w + p->off_store) : nullptr;
+  const int32_t* kslot = p->keep ? reinterpret_cast<const int32_t*>(w + p->off_rowslot) : nullptr;
+  const int32_t* rcnt = reinterpret_cast<const int32_t*>(w + p->off_rcnt);
+  auto rank_launch = [&](bool fixed) {
+    return launch_rank_num(p->sr, fixed, op, rows_dense_sym, p->n_dense_sym, p->rank_cw, p->rank_NC,
+                           p->rank_maxc, pchunk, rcnt, p->bp.hash_max_nnz, p->opt.rank_dense_div, p->num_wlog2,
+                           p->num_P, p->opt.dense_threads, p->opt.short_seg, kstore, kslot, p->keep_stride,
+                           p->c_ptr, c_idx, c_val, s);
+  };
+  if (ndense > 0 || nsub_dense > 0 || ranked) {
     PhaseTimer t(p, SPG_PHASE_NUM_DENSE);
     if (ndense > 0)
       SPG_TRY_HIP(launch_dense_num(p->sr, op, rows_num + no.v[kDenseBinBase], ndense, p->num_wlog2,
@@ -658,21 +680,12 @@ spg_status spg_numeric(spg_plan* p, void* ws, int32_t* c_idx, void* c_val) {
       SPG_TRY_HIP(launch_dense_num_sub(p->sr, op, rows_dense_sym, subitems + sbo.v[kDenseBinBase], nsub_dense,
                                        p->opt.dense_threads, p->opt.short_seg, p->num_P, p->num_wlog2, pnum,
                                        subcnt, suboff, p->c_ptr, c_idx, c_val, s));
+    // heavy rows dense enough for fixed panels
+    if (ranked) SPG_TRY_HIP(rank_launch(true));
   }
-  if (p->rank && p->n_dense_sym > 0) {
-    auto* pchunk = reinterpret_cast<int32_t*>(w + p->off_pchunk);
-    {
-      PhaseTimer tp(p, SPG_PHASE_NUM_PANELS);
-      SPG_TRY_HIP(launch_panel_index(op.b_ptr, op.b_idx, op.n, p->rank_cw, p->rank_NC, pchunk, s));
-    }
+  if (ranked) {
     PhaseTimer t(p, SPG_PHASE_NUM_RANK);
-    SPG_TRY_HIP(launch_rank_num(p->sr, op, rows_dense_sym, p->n_dense_sym, p->rank_cw, p->rank_NC, p->rank_maxc,
-                                pchunk, reinterpret_cast<const int32_t*>(w + p->off_rcnt), p->bp.hash_max_nnz,
-                                p->opt.rank_dense_div, p->num_wlog2, p->num_P, p->opt.dense_threads,
-                                p->opt.short_seg,
-                                p->keep ? reinterpret_cast<const uint32_t*>(w + p->off_store) : nullptr,
-                                p->keep ? reinterpret_cast<const int32_t*>(w + p->off_rowslot) : nullptr,
-                                p->keep_nwords, p->c_ptr, c_idx, c_val, s));
+    SPG_TRY_HIP(rank_launch(false));
   }
   return SPG_OK;
 }

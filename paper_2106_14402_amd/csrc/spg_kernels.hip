@@ -530,65 +530,105 @@ hipError_t launch_dense_sym(const Operands& op, const int32_t* rows, int64_t nro
   return hipGetLastError();
 }
 
-// Numeric phase of a pattern-only row whose bitmap the symbolic phase kept:
-// load it into LDS and emit its set bits in column order.
-__device__ void emit_bitmap(const uint32_t* bits, int nwords, int64_t out, int64_t out_end,
-                            int32_t* __restrict__ c_idx, int* tmp) {
-  const int nt = blockDim.x;
+// n words from global memory (16-byte aligned) into LDS, with up to U
+// 16-byte loads in flight per thread before any of them is stored.
+template <int U>
+__device__ __forceinline__ void load_words_lds(uint32_t* __restrict__ dst, const uint32_t* __restrict__ src,
+                                               int n) {
+  const int nt = blockDim.x, tid = threadIdx.x;
+  const int n4 = n >> 2;
+  const uint4* s4 = reinterpret_cast<const uint4*>(src);
+  uint4* d4 = reinterpret_cast<uint4*>(dst);
+  for (int base = 0; base < n4; base += U * nt) {
+    uint4 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = base + u * nt + tid;
+      if (i < n4) v[u] = s4[i];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = base + u * nt + tid;
+      if (i < n4) d4[i] = v[u];
+    }
+  }
+  for (int i = (n4 << 2) + tid; i < n; i += nt) dst[i] = src[i];
+}
+
+// Orders the LDS accesses of one wave: writes by some lanes before the
+// barrier are seen by reads of other lanes after it.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Numeric phase of a pattern-only row whose bitmap the symbolic phase kept.
+// Each wave owns a contiguous range of words, read straight from the kept
+// bitmap.  One block scan of the wave totals places the ranges.  Then, 64
+// words at a time, the lanes put the column ids of their words in order into
+// the wave's LDS staging area and the wave writes the staged ids out with
+// consecutive lanes on consecutive slots.
+constexpr int kExpandThreads = 1024;
+
+__global__ __launch_bounds__(kExpandThreads) void k_expand_rows(const int32_t* __restrict__ rows, int64_t nrows,
+                                                                int nwords, int64_t stride,
+                                                                const uint32_t* __restrict__ store,
+                                                                const int32_t* __restrict__ row_slot,
+                                                                const int64_t* __restrict__ c_ptr,
+                                                                int32_t* __restrict__ c_idx) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  int* tmp = reinterpret_cast<int*>(smem);
   const int lane = threadIdx.x & (kWave - 1);
   const int wid = threadIdx.x >> 6;
-  const int nw = nt >> 6;
+  const int nw = blockDim.x >> 6;
+  int32_t* stage = reinterpret_cast<int32_t*>(smem + 256) + wid * (kWave * 32);
   const int wpw = (((nwords + nw - 1) / nw) + kWave - 1) & ~(kWave - 1);
   const int w_begin = min(nwords, wid * wpw);
   const int w_end = min(nwords, w_begin + wpw);
-  int cnt = 0;
-  for (int w = w_begin + lane; w < w_end; w += kWave) cnt += __popc(bits[w]);
-  cnt = wave_sum(cnt);
-  int ptotal;
-  const int woff = __shfl(block_exclusive_scan(lane == 0 ? cnt : 0, tmp, &ptotal), 0, kWave);
-  int64_t o_base = out + woff;
-  for (int w0 = w_begin; w0 < w_end; w0 += kWave) {
-    const int w = w0 + lane;
-    const uint32_t word = w < w_end ? bits[w] : 0u;
-    const int c = __popc(word);
-    const int incl = wave_inclusive_scan(c);
-    int64_t o = o_base + (incl - c);
-    uint32_t x = word;
-    while (x) {
-      const int b = __ffs(x) - 1;
-      if (o < out_end) c_idx[o] = (w << 5) + b;
-      x &= x - 1;
-      ++o;
-    }
-    o_base += __shfl(incl, kWave - 1, kWave);
-  }
-}
-
-__global__ __launch_bounds__(1024) void k_expand_rows(const int32_t* __restrict__ rows, int64_t nrows,
-                                                      int nwords, const uint32_t* __restrict__ store,
-                                                      const int32_t* __restrict__ row_slot,
-                                                      const int64_t* __restrict__ c_ptr,
-                                                      int32_t* __restrict__ c_idx) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  int* tmp = reinterpret_cast<int*>(smem);
-  uint32_t* bits = reinterpret_cast<uint32_t*>(smem + 256);
   for (int64_t it = blockIdx.x; it < nrows; it += gridDim.x) {
     const int32_t row = uniform(rows[it]);
-    const uint32_t* src = store + static_cast<int64_t>(row_slot[row]) * nwords;
-    for (int t = threadIdx.x; t < nwords; t += blockDim.x) bits[t] = src[t];
-    __syncthreads();
-    emit_bitmap(bits, nwords, c_ptr[row], c_ptr[row + 1], c_idx, tmp);
-    __syncthreads();
+    const uint32_t* src = store + static_cast<int64_t>(row_slot[row]) * stride;
+    int cnt = 0;
+#pragma unroll 8
+    for (int w = w_begin + lane; w < w_end; w += kWave) cnt += __popc(src[w]);
+    cnt = wave_sum(cnt);
+    int ptotal;
+    const int woff = __shfl(block_exclusive_scan(lane == 0 ? cnt : 0, tmp, &ptotal), 0, kWave);
+    const int64_t out_end = c_ptr[row + 1];
+    int64_t o = c_ptr[row] + woff;
+    uint32_t nxt = w_begin + lane < w_end ? src[w_begin + lane] : 0u;
+    for (int w0 = w_begin; w0 < w_end; w0 += kWave) {
+      const uint32_t word = nxt;  // this round's word; the next one is loaded meanwhile
+      nxt = w0 + kWave + lane < w_end ? src[w0 + kWave + lane] : 0u;
+      const int c = __popc(word);
+      const int incl = wave_inclusive_scan(c);
+      const int T = __shfl(incl, kWave - 1, kWave);
+      int q = incl - c;
+      uint32_t x = word;
+      const int col0 = (w0 + lane) << 5;
+      while (x) {
+        stage[q++] = col0 + __ffs(x) - 1;
+        x &= x - 1;
+      }
+      wave_sync();
+      for (int t = lane; t < T; t += kWave)
+        if (o + t < out_end) c_idx[o + t] = stage[t];
+      wave_sync();
+      o += T;
+    }
+    __syncthreads();  // tmp is reused by the next row's scan
   }
 }
 
-hipError_t launch_expand_rows(const int32_t* rows, int64_t nrows, int nwords, const uint32_t* store,
+hipError_t launch_expand_rows(const int32_t* rows, int64_t nrows, int nwords, int64_t stride, const uint32_t* store,
                               const int32_t* row_slot, const int64_t* c_ptr, int32_t* c_idx, int nt,
                               hipStream_t s) {
   if (nrows <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_expand_rows, dim3(grid_for(nrows, 0)), dim3(nt),
-                     256 + static_cast<size_t>(nwords) * 4, s, rows, nrows, nwords, store, row_slot, c_ptr,
-                     c_idx);
+  (void)nt;
+  const size_t lds = 256 + static_cast<size_t>(kExpandThreads / kWave) * kWave * 32 * sizeof(int32_t);
+  hipLaunchKernelGGL(k_expand_rows, dim3(grid_for(nrows, 0)), dim3(kExpandThreads), lds, s, rows, nrows, nwords,
+                     stride, store, row_slot, c_ptr, c_idx);
   return hipGetLastError();
 }
 
@@ -1042,8 +1082,7 @@ __device__ void rank_num_row(const Operands& op, int64_t a_lo, int64_t a_hi, int
       // 1. pattern of the column range: from the kept bitmap, or by a walk
       //    over B's column ids
       if (keep) {
-        const uint32_t* src = keep + (C0 >> 5);
-        for (int t = tid; t < nwords; t += nt) bits[t] = src[t];
+        load_words_lds<1>(bits, keep + (C0 >> 5), nwords);
         __syncthreads();
       } else {
         for (int t = tid; t < nwords; t += nt) bits[t] = 0u;
@@ -1068,19 +1107,25 @@ __device__ void rank_num_row(const Operands& op, int64_t a_lo, int64_t a_hi, int
       RankSink<SR> rs{bits, pre, vals};
       RowSource<SR> vs{&op, a_lo, a_hi, true, pchunk, NC, c_lo, c_hi};
       enumerate_src<SR>(op, vs, C0, short_seg, q, rs);
-      // 4. write the range out: values in slot order, ids from the bitmap
+      // 4. write the range out: the values in slot order; then the column
+      //    ids, placed at their ranks in LDS (over the value slots, 4 bytes
+      //    each at most as wide as a slot) and written in order
+      static_assert(sizeof(S) >= sizeof(int32_t), "ids are staged over the value slots");
       const int lim = static_cast<int>(min(static_cast<int64_t>(total), out_end - out));
       for (int r = tid; r < lim; r += nt) c_val[out + r] = SR::out(vals[r]);
+      __syncthreads();
+      int32_t* ids = reinterpret_cast<int32_t*>(vals);
       for (int w = tid; w < nwords; w += nt) {
         uint32_t x = bits[w];
-        int64_t o = out + pre[w];
+        int q = pre[w];
+        const int32_t col0 = C0 + (w << 5);
         while (x) {
-          const int b = __ffs(x) - 1;
-          if (o < out_end) c_idx[o] = C0 + (w << 5) + b;
+          ids[q++] = col0 + __ffs(x) - 1;
           x &= x - 1;
-          ++o;
         }
       }
+      __syncthreads();
+      for (int r = tid; r < lim; r += nt) c_idx[out + r] = ids[r];
       out += total;
       __syncthreads();
     }
@@ -1090,7 +1135,7 @@ __device__ void rank_num_row(const Operands& op, int64_t a_lo, int64_t a_hi, int
 
 // Heavy valued rows of the dense symbolic list (slot order), those with more
 // than hash_max_nnz entries; the others went to the hash numeric bins.
-template <class SR>
+template <class SR, bool kFixed>
 __global__ __launch_bounds__(1024) void k_rank_num(Operands op, const int32_t* __restrict__ rows,
                                                    int64_t nrows, int cw, int NC, int max_chunks,
                                                    const int32_t* __restrict__ pchunk,
@@ -1109,7 +1154,8 @@ __global__ __launch_bounds__(1024) void k_rank_num(Operands op, const int32_t* _
     const int64_t nnz = out_end - out;
     if (nnz <= hash_max_nnz) continue;
     const int64_t a_lo = op.a_ptr[row], a_hi = op.a_ptr[row + 1];
-    if (nnz * dense_div >= op.k) {
+    if ((nnz * dense_div >= op.k) != kFixed) continue;  // the other launch takes this row
+    if constexpr (kFixed) {
       // fixed panels of 2^wlog2 columns = 2^(wlog2-cw) chunks
       const int r = 1 << (wlog2 - cw);
       auto make = [&](int p) {
@@ -1376,7 +1422,7 @@ static size_t rank_num_lds_t(int cw, int max_chunks, int wlog2, int nt) {
 }
 
 template <class SR>
-static hipError_t rank_num_t(const Operands& op, const int32_t* rows, int64_t nrows, int cw, int NC,
+static hipError_t rank_num_t(bool fixed, const Operands& op, const int32_t* rows, int64_t nrows, int cw, int NC,
                              int max_chunks, const int32_t* pchunk, const int32_t* rcnt, int64_t hash_max_nnz,
                              int dense_div, int wlog2, int P, int nt, int short_seg, const uint32_t* keep_store,
                              const int32_t* keep_slot, int64_t keep_nwords, const int64_t* c_ptr,
@@ -1385,8 +1431,14 @@ static hipError_t rank_num_t(const Operands& op, const int32_t* rows, int64_t nr
   if constexpr (SR::kPattern) {
     return hipErrorInvalidValue;  // pattern-only rows use the bitmap paths
   } else {
-    hipLaunchKernelGGL(k_rank_num<SR>, dim3(grid_for(nrows, 0)), dim3(nt),
-                       rank_num_lds_t<SR>(cw, max_chunks, wlog2, nt), s, op, rows, nrows, cw, NC, max_chunks,
+    if (fixed)
+      hipLaunchKernelGGL((k_rank_num<SR, true>), dim3(grid_for(nrows, 0)), dim3(nt),
+                         dense_num_lds_t<SR>(wlog2, nt), s, op, rows, nrows, cw, NC, max_chunks,
+                         pchunk, rcnt, hash_max_nnz, dense_div, wlog2, P, short_seg, keep_store, keep_slot,
+                         keep_nwords, c_ptr, c_idx, static_cast<typename SR::Out*>(c_val));
+    else
+      hipLaunchKernelGGL((k_rank_num<SR, false>), dim3(grid_for(nrows, 0)), dim3(nt),
+                       rank_num_lds_bytes<SR>(cw, max_chunks, nt), s, op, rows, nrows, cw, NC, max_chunks,
                        pchunk, rcnt, hash_max_nnz, dense_div, wlog2, P, short_seg, keep_store, keep_slot,
                        keep_nwords, c_ptr, c_idx, static_cast<typename SR::Out*>(c_val));
     return hipGetLastError();
@@ -1492,12 +1544,12 @@ hipError_t launch_dense_num(int sr, const Operands& op, const int32_t* rows, int
                s)
 }
 
-hipError_t launch_rank_num(int sr, const Operands& op, const int32_t* rows, int64_t nrows, int cw, int NC,
+hipError_t launch_rank_num(int sr, bool fixed, const Operands& op, const int32_t* rows, int64_t nrows, int cw, int NC,
                            int max_chunks, const int32_t* pchunk, const int32_t* rcnt, int64_t hash_max_nnz,
                            int dense_div, int wlog2, int P, int nt, int short_seg, const uint32_t* keep_store,
                            const int32_t* keep_slot, int64_t keep_nwords, const int64_t* c_ptr,
                            int32_t* c_idx, void* c_val, hipStream_t s) {
-  SPG_DISPATCH(sr, rank_num_t, op, rows, nrows, cw, NC, max_chunks, pchunk, rcnt, hash_max_nnz, dense_div,
+  SPG_DISPATCH(sr, rank_num_t, fixed, op, rows, nrows, cw, NC, max_chunks, pchunk, rcnt, hash_max_nnz, dense_div,
                wlog2, P, nt, short_seg, keep_store, keep_slot, keep_nwords, c_ptr, c_idx, c_val, s)
 }
 

@@ -29,7 +29,7 @@ struct KeepBitmaps {
   unsigned int* counter;     // next free slot (zeroed before the launch)
   const int64_t* flops;      // per row products
   int64_t min_flops;         // rows with fewer products are recomputed instead
-  int64_t nwords;
+  int64_t nwords;            // slot stride in words (a multiple of 4)
   unsigned int capacity;
 };
 
@@ -114,7 +114,7 @@ hipError_t launch_dense_sym(const Operands& op, const int32_t* rows, int64_t nro
                             const int32_t* pidx, int nt, int short_seg, int64_t* c_ptr,
                             hipStream_t s, int sub_wlog2 = 0, int subP = 0, int32_t* sub_cnt = nullptr,
                             KeepBitmaps kb = KeepBitmaps{});
-hipError_t launch_expand_rows(const int32_t* rows, int64_t nrows, int nwords, const uint32_t* store,
+hipError_t launch_expand_rows(const int32_t* rows, int64_t nrows, int nwords, int64_t stride, const uint32_t* store,
                               const int32_t* row_slot, const int64_t* c_ptr, int32_t* c_idx, int nt,
                               hipStream_t s);
 // (row, panel) pieces: offsets within rows + bin counts, then the item lists.
@@ -141,11 +141,12 @@ hipError_t launch_dense_num(int sr, const Operands& op, const int32_t* rows, int
                             const int64_t* c_ptr, int32_t* c_idx, void* c_val, hipStream_t s);
 // Heavy valued rows (the dense symbolic list, slot order) through rank-compressed
 // panels: chunks of 2^cw columns, rcnt[slot*NC + c] entries per chunk, pchunk
-// the chunk index of B; rows with nnz*dense_div >= k use fixed panels of
-// 2^wlog2 columns (P of them) over the same index.  Rows with a kept symbolic
-// bitmap (keep_slot[row] >= 0, keep_nwords words each in keep_store) read
+// the chunk index of B.  fixed: only the rows with nnz*dense_div >= k, by
+// fixed panels of 2^wlog2 columns (P of them) over the same index; otherwise
+// only the other rows.  Rows with a kept symbolic
+// bitmap (keep_slot[row] >= 0, slots of keep_nwords words in keep_store) read
 // their pattern from it.
-hipError_t launch_rank_num(int sr, const Operands& op, const int32_t* rows, int64_t nrows, int cw, int NC,
+hipError_t launch_rank_num(int sr, bool fixed, const Operands& op, const int32_t* rows, int64_t nrows, int cw, int NC,
                            int max_chunks, const int32_t* pchunk, const int32_t* rcnt, int64_t hash_max_nnz,
                            int dense_div, int wlog2, int P, int nt, int short_seg, const uint32_t* keep_store,
                            const int32_t* keep_slot, int64_t keep_nwords, const int64_t* c_ptr,

@@ -92,6 +92,16 @@ class Product:
     def stats(self):
         return B_.spg_plan_stats(self.plan)
 
+    def options(self):
+        """The options the plan runs with (defaults filled in)."""
+        return B_.spg_plan_options(self.plan)
+
+    def hash_max_nnz(self) -> int:
+        return int(self.options().hash_max_nnz)
+
+    def rank_dense_div(self) -> int:
+        return int(self.options().rank_dense_div)
+
     def timings(self) -> dict:
         return B_.spg_plan_timings(self.plan)
 
