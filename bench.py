@@ -47,7 +47,7 @@ def parse():
     ap.add_argument("--requests", type=int, default=2000, help="served: requests per arrival rate")
     ap.add_argument("--opt", action="append", default=[],
                     help="extra option for the valued product, key=value (e.g. split_panels=-1)")
-    ap.add_argument("--bitmap-mib", type=int, default=24576,
+    ap.add_argument("--bitmap-mib", type=int, default=28672,
                     help="workspace for symbolic bitmaps kept for the pattern-only numeric phase")
     ap.add_argument("--bitmap-mib-valued", type=int, default=28672,
                     help="workspace for symbolic bitmaps kept for the rank passes of the (min,+) product")

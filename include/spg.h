@@ -144,7 +144,8 @@ typedef struct spg_options {
                               each entry stored at its column's rank; -1 =
                               fixed-width panels in sequence */
   int32_t rank_dense_div;  /* rows with nnz * rank_dense_div >= columns of C
-                              keep fixed-width panels (default 4) */
+                              keep fixed-width panels (default 1: only full
+                              rows) */
   int32_t reserved[3];
 } spg_options;
 

@@ -126,7 +126,7 @@ void resolve_options(const spg_options* in, spg_options* o, int sr) {
   if (o->sym_panel_log2 <= 0) o->sym_panel_log2 = 20;
   if (o->lds_budget <= 0) o->lds_budget = 131072;
   if (o->seg_mib <= 0) o->seg_mib = 16384;
-  if (o->rank_dense_div <= 0) o->rank_dense_div = 4;
+  if (o->rank_dense_div <= 0) o->rank_dense_div = 1;
 }
 
 spg_status check_options(const spg_options& o, int sr) {
@@ -247,17 +247,19 @@ spg_status spg_plan_create(const spg_matrix* A, const spg_matrix* B, spg_semirin
              static_cast<int64_t>(p->op.m) * p->num_P < (int64_t(1) << 31);
   p->bp.split_heavy = p->split ? 1 : 0;
 
-  // Rank-compressed panels: 64 KiB of value slots (2^cw of them) per pass,
-  // chunks of 2^cw columns, a bitmap of up to 2^18 columns.
+  // Rank-compressed panels: half the LDS budget, at most 64 KiB, of value
+  // slots (2^cw of them) per pass, chunks of 2^cw columns, a bitmap of up to
+  // four columns per value byte (2^18 columns for 64 KiB).
   p->rank = false;
   p->rank_cw = 0;
   p->rank_NC = 0;
   p->rank_maxc = 0;
   if (p->opt.rank_panels >= 0 && sb > 0 && !p->split && p->num_P > 1) {
+    const size_t vbytes = std::max<size_t>(1024, std::min<size_t>(65536, p->opt.lds_budget / 2));
     int cw = 5;
-    while ((static_cast<size_t>(1) << (cw + 1)) * sb <= 65536) ++cw;
+    while ((static_cast<size_t>(1) << (cw + 1)) * sb <= vbytes) ++cw;
     cw = std::min(cw, p->num_wlog2);
-    int maxc = std::max(1, std::min(64, (1 << 18) >> cw));
+    int maxc = std::max(1, std::min(64, static_cast<int>((4 * vbytes) >> cw)));
     while (maxc > 1 && rank_num_lds(p->sr, cw, maxc, p->num_wlog2, nt) > static_cast<size_t>(max_lds_bytes()))
       maxc >>= 1;
     const int64_t NC = (kk + (int64_t(1) << cw) - 1) >> cw;
@@ -294,13 +296,13 @@ spg_status spg_plan_create(const spg_matrix* A, const spg_matrix* B, spg_semirin
   if (p->sym_P > 1) off = align_up(off + static_cast<size_t>(nB) * (p->sym_P + 1) * sizeof(int32_t));
   p->off_pnum = off;
   if (p->num_P > 1) off = align_up(off + static_cast<size_t>(nB) * (p->num_P + 1) * sizeof(int32_t));
-  // Kept bitmaps.  Pattern-only rows are expanded from them (worth it past
-  // 4 products per bitmap word); rank-panel rows read their pattern from them
-  // instead of walking B's column ids once more (worth it past one).
+  // Kept bitmaps: pattern-only rows are expanded from them, rank-panel rows
+  // read their pattern from them, instead of walking B's column ids once
+  // more; worth it for rows with at least one product per bitmap word.
   p->keep = (p->sr == 7 || p->rank) && p->sym_P == 1 && p->opt.bitmap_mib > 0 && p->op.k > 0;
   p->keep_nwords = (static_cast<int64_t>(p->op.k) + 31) / 32;
   p->keep_stride = (p->keep_nwords + 3) & ~int64_t(3);
-  p->keep_min_flops = (p->sr == 7 ? 4 : 1) * p->keep_nwords;
+  p->keep_min_flops = p->keep_nwords;
   p->keep_cap = 0;
   if (p->keep) {
     const int64_t cap = (static_cast<int64_t>(p->opt.bitmap_mib) << 20) / (p->keep_stride * 4);

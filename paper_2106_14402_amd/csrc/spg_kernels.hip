@@ -762,10 +762,22 @@ hipError_t launch_dense_sym_b(const BatchDesc* descs, const int64_t* row_off, in
 // ---------------------------------------------------------------------------
 template <class S>
 __device__ void bitonic_sort(int32_t* keys, S* vals, int N, bool with_vals) {
+  // Wave w takes the M pairs [w*M, (w+1)*M) of every stage (M a power of two,
+  // at least a wave's width).  A stage with distance j <= M then pairs
+  // elements inside the wave's own 2M elements, so only stages with j > M,
+  // and the stages next to them, need a workgroup barrier; the others are
+  // ordered within the wave.
+  const int lane = threadIdx.x & (kWave - 1);
+  const int nw = blockDim.x >> 6;
+  const int half = N >> 1;
+  int M = kWave;
+  while (M * nw < half) M <<= 1;
+  const int p0 = (threadIdx.x >> 6) * M;
+  const int p1 = min(p0 + M, half);
   for (int k = 2; k <= N; k <<= 1) {
     for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int t = threadIdx.x; t < (N >> 1); t += blockDim.x) {
-        const int i = 2 * t - (t & (j - 1));
+      for (int p = p0 + lane; p < p1; p += kWave) {
+        const int i = 2 * p - (p & (j - 1));
         const int l = i + j;
         const bool up = (i & k) == 0;
         const int32_t ki = keys[i], kl = keys[l];
@@ -779,9 +791,14 @@ __device__ void bitonic_sort(int32_t* keys, S* vals, int N, bool with_vals) {
           }
         }
       }
-      __syncthreads();
+      const int next_j = j > 1 ? j >> 1 : k;  // first distance of the next stage
+      if (j > M || (next_j > M && k < N))
+        __syncthreads();
+      else
+        wave_sync();
     }
   }
+  __syncthreads();
 }
 
 constexpr int kMaxSlotsPerThread = 16;

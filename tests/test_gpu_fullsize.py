@@ -94,7 +94,7 @@ def test_rmat20_bool_and_min_plus(rmat20):
     Hpat = A.with_values(None)
 
     # (OR,AND), pattern only, with kept bitmaps as benchmarked
-    p = S.Product(Apat, Apat, "or_and_bool", B.make_options(bitmap_mib=24576))
+    p = S.Product(Apat, Apat, "or_and_bool", B.make_options(bitmap_mib=28672))
     nnz_b = p.symbolic()
     C = p.numeric()
     assert p.stats()[0] == int(fl.sum())
