@@ -45,6 +45,8 @@ def parse():
                          "remaining configurations, printed in the same JSON form")
     ap.add_argument("--nprod", type=int, default=512, help="batched: number of products")
     ap.add_argument("--requests", type=int, default=2000, help="served: requests per arrival rate")
+    ap.add_argument("--autotune-cache", default=None,
+                    help="batched: autotuner cache file (default gpurun_out/autotune.json under the repo)")
     ap.add_argument("--opt", action="append", default=[],
                     help="extra option for the valued product, key=value (e.g. split_panels=-1)")
     ap.add_argument("--bitmap-mib", type=int, default=28672,
@@ -392,7 +394,11 @@ def run_batched(args):
     mats = [S.to_device(it.A) for it in items]
     srs = [it.semiring for it in items]
     log(f"[bench] {len(items)} products generated in {time.time() - t0:.1f}s")
-    bp = BT.BatchProduct(mats, mats, srs)
+    from paper_2106_14402_amd import autotune as AT
+    cache = os.path.join(ROOT, "gpurun_out", "autotune.json") if args.autotune_cache is None else args.autotune_cache
+    tuning = AT.tune_batch(mats, mats, srs, cache, log=log)
+    log(f"[bench] autotuned {tuning}")
+    bp = BT.BatchProduct(mats, mats, srs, AT.make_options(tuning["knobs"]))
     bp.symbolic()
     bp.allocate()
     flops = bp.stats()[0]
@@ -432,6 +438,8 @@ def run_batched(args):
     out["batched"] = {"full_step_ms": round(ms_b, 3), "numeric_graph_replay_ms": round(ms_br, 3)}
     out["one_call_per_product"] = {"full_step_ms": round(ms_s, 3), "numeric_ms": round(ms_sn, 3)}
     out["speedup"] = {"full_step": round(ms_s / ms_b, 3), "numeric": round(ms_sn / ms_br, 3)}
+    out["autotune"] = {"knobs": tuning["knobs"], "tuned_ms": tuning["ms"], "default_ms": tuning["default_ms"],
+                       "from_cache": tuning["from_cache"]}
     bp.close()
     return out
 

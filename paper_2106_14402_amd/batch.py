@@ -19,9 +19,21 @@ VAL_BYTES = {"plus_times_f64": 8, "plus_times_f32": 4, "min_plus_i32": 4, "min_p
 
 
 class BatchProduct:
+    """options: None (library defaults), an spg_options, or "auto": knob
+    values from the autotuner (timed on this batch the first time a batch of
+    its shape is seen on this device, then read from autotune_cache)."""
+
     def __init__(self, As: Sequence[DeviceMatrix], Bs: Sequence[DeviceMatrix], semirings: Sequence[str],
-                 options: Optional[B_.spg_options] = None, stream=None):
+                 options=None, stream=None, autotune_cache: Optional[str] = None):
         assert len(As) == len(Bs) == len(semirings)
+        self.tuning = None
+        if isinstance(options, str):
+            if options != "auto":
+                raise ValueError(f"options must be None, spg_options or 'auto', not {options!r}")
+            from . import autotune
+            self.tuning = autotune.tune_batch(As, Bs, semirings,
+                                              autotune_cache if autotune_cache else autotune.DEFAULT_CACHE)
+            options = autotune.make_options(self.tuning["knobs"])
         self.As, self.Bs, self.semirings = list(As), list(Bs), list(semirings)
         self.n = len(As)
         self.device = As[0].ptr.device if As else torch.device("cuda")

@@ -115,3 +115,24 @@ def test_empty_and_degenerate_products_in_batch():
     for j, (A, Bm, sr) in enumerate(extra):
         assert_parity(A, Bm, sr, _host(bp.result(j)))
     bp.close()
+
+
+def test_autotuned_batch_matches_oracle_and_uses_cache(tmp_path):
+    """Knobs picked by timing change launch shapes only: every product still
+    matches the oracle; a second batch of the same shape reads the cache."""
+    from paper_2106_14402_amd import autotune as AT
+    from paper_2106_14402_amd import batch as BT
+    from paper_2106_14402_amd import spgemm as S
+    items = _batch(16, n_hi=3000)
+    mats = [S.to_device(it.A) for it in items]
+    srs = [it.semiring for it in items]
+    cache = str(tmp_path / "tune.json")
+    rec = AT.tune_batch(mats, mats, srs, cache, reps=1)
+    assert not rec["from_cache"] and rec["ms"] is not None and rec["ms"] <= rec["default_ms"]
+    bp = BT.BatchProduct(mats, mats, srs, "auto", autotune_cache=cache)
+    assert bp.tuning["from_cache"] and bp.tuning["knobs"] == rec["knobs"]
+    bp.symbolic()
+    bp.numeric()
+    for b, it in enumerate(items):
+        assert_parity(it.A, it.A, it.semiring, _host(bp.result(b)))
+    bp.close()
