@@ -564,11 +564,14 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 // Numeric phase of a pattern-only row whose bitmap the symbolic phase kept.
-// Each wave owns a contiguous range of words, read straight from the kept
-// bitmap.  One block scan of the wave totals places the ranges.  Then, 64
-// words at a time, the lanes put the column ids of their words in order into
-// the wave's LDS staging area and the wave writes the staged ids out with
-// consecutive lanes on consecutive slots.
+// The row is taken in slabs of nw * 64 * kExpandWords words.  In a slab each
+// wave owns a contiguous range of at most 64 * kExpandWords words, read once
+// into registers (lane l has words l, l+64, ...); one block scan of the wave
+// totals places the ranges.  Then, 64 words at a time, the lanes put the
+// column ids of their words in order into the wave's LDS staging area and
+// the wave writes the staged ids out with consecutive lanes on consecutive
+// slots.
+constexpr int kExpandWords = 16;
 constexpr int kExpandThreads = 1024;
 
 __global__ __launch_bounds__(kExpandThreads) void k_expand_rows(const int32_t* __restrict__ rows, int64_t nrows,
@@ -583,41 +586,53 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand_rows(const int32_t* _
   const int wid = threadIdx.x >> 6;
   const int nw = blockDim.x >> 6;
   int32_t* stage = reinterpret_cast<int32_t*>(smem + 256) + wid * (kWave * 32);
-  const int wpw = (((nwords + nw - 1) / nw) + kWave - 1) & ~(kWave - 1);
-  const int w_begin = min(nwords, wid * wpw);
-  const int w_end = min(nwords, w_begin + wpw);
+  const int slab = nw * kWave * kExpandWords;
   for (int64_t it = blockIdx.x; it < nrows; it += gridDim.x) {
     const int32_t row = uniform(rows[it]);
     const uint32_t* src = store + static_cast<int64_t>(row_slot[row]) * stride;
-    int cnt = 0;
-#pragma unroll 8
-    for (int w = w_begin + lane; w < w_end; w += kWave) cnt += __popc(src[w]);
-    cnt = wave_sum(cnt);
-    int ptotal;
-    const int woff = __shfl(block_exclusive_scan(lane == 0 ? cnt : 0, tmp, &ptotal), 0, kWave);
     const int64_t out_end = c_ptr[row + 1];
-    int64_t o = c_ptr[row] + woff;
-    uint32_t nxt = w_begin + lane < w_end ? src[w_begin + lane] : 0u;
-    for (int w0 = w_begin; w0 < w_end; w0 += kWave) {
-      const uint32_t word = nxt;  // this round's word; the next one is loaded meanwhile
-      nxt = w0 + kWave + lane < w_end ? src[w0 + kWave + lane] : 0u;
-      const int c = __popc(word);
-      const int incl = wave_inclusive_scan(c);
-      const int T = __shfl(incl, kWave - 1, kWave);
-      int q = incl - c;
-      uint32_t x = word;
-      const int col0 = (w0 + lane) << 5;
-      while (x) {
-        stage[q++] = col0 + __ffs(x) - 1;
-        x &= x - 1;
+    int64_t o_slab = c_ptr[row];
+    for (int s0 = 0; s0 < nwords; s0 += slab) {
+      const int s1 = min(nwords, s0 + slab);
+      const int wpw = (((s1 - s0 + nw - 1) / nw) + kWave - 1) & ~(kWave - 1);
+      const int w_begin = min(s1, s0 + wid * wpw);
+      const int w_end = min(s1, w_begin + wpw);
+      uint32_t wr[kExpandWords];
+      int cnt = 0;
+#pragma unroll
+      for (int j = 0; j < kExpandWords; ++j) {
+        const int w = w_begin + j * kWave + lane;
+        wr[j] = w < w_end ? src[w] : 0u;
+        cnt += __popc(wr[j]);
       }
-      wave_sync();
-      for (int t = lane; t < T; t += kWave)
-        if (o + t < out_end) c_idx[o + t] = stage[t];
-      wave_sync();
-      o += T;
+      cnt = wave_sum(cnt);
+      int ptotal;
+      const int woff = __shfl(block_exclusive_scan(lane == 0 ? cnt : 0, tmp, &ptotal), 0, kWave);
+      int64_t o = o_slab + woff;
+#pragma unroll
+      for (int j = 0; j < kExpandWords; ++j) {
+        if (w_begin + j * kWave < w_end) {  // wave-uniform
+          const uint32_t word = wr[j];
+          const int c = __popc(word);
+          const int incl = wave_inclusive_scan(c);
+          const int T = __shfl(incl, kWave - 1, kWave);
+          int q = incl - c;
+          uint32_t x = word;
+          const int col0 = (w_begin + j * kWave + lane) << 5;
+          while (x) {
+            stage[q++] = col0 + __ffs(x) - 1;
+            x &= x - 1;
+          }
+          wave_sync();
+          for (int t = lane; t < T; t += kWave)
+            if (o + t < out_end) c_idx[o + t] = stage[t];
+          wave_sync();
+          o += T;
+        }
+      }
+      o_slab += ptotal;
+      __syncthreads();  // tmp is reused by the next scan
     }
-    __syncthreads();  // tmp is reused by the next row's scan
   }
 }
 
