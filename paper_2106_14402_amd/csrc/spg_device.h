@@ -329,12 +329,27 @@ struct SegSource {
   }
 };
 
-template <class SR, class Src, class Sink>
+// One piece of a queued segment held in registers: products [s0, s1) of B
+// (this lane's share), their column ids and values, and the A value.
+template <class In, int U>
+struct PieceBuf {
+  int64_t s0, s1;
+  In ae;
+  int32_t cols[U];
+  In bv[U];
+};
+
+// kBufs = 1: a wave loads a whole piece, then combines it.  kBufs = 2: pieces
+// are half as long and a wave keeps two in flight, issuing the next piece's
+// loads before combining the current one (more registers).
+template <class SR, int kBufs = 1, class Src, class Sink>
 __device__ void enumerate_src(const Operands& op, const Src& src, int32_t c0, int short_seg,
                               RowQueue<typename SR::In> q, Sink& sink) {
   using In = typename SR::In;
-  // 16 loads in flight per lane (8 for 8-byte values, to stay in registers)
-  constexpr int kPU = sizeof(In) > 4 ? kPieceUnroll / 2 : kPieceUnroll;
+  static_assert(kBufs == 1 || kBufs == 2, "one or two piece buffers");
+  // Loads per lane per piece buffer: 16 in flight per lane (8 for 8-byte
+  // values, to stay in registers).
+  constexpr int kPU = (sizeof(In) > 4 ? kPieceUnroll / 2 : kPieceUnroll) / kBufs;
   constexpr int kPc = kWave * kPU;
   const int tid = threadIdx.x;
   const int nt = blockDim.x;
@@ -382,12 +397,16 @@ __device__ void enumerate_src(const Operands& op, const Src& src, int32_t c0, in
       if (tid < nq) q.pfx[tid] = off;
       if (tid == 0) q.pfx[nq] = ptotal;
       __syncthreads();
-      int e_lo = 0;  // pieces are taken in increasing order by each wave
-      for (;;) {
+      // Each wave takes pieces in increasing order and keeps two in flight:
+      // the loads of the next piece are issued before the products of the
+      // current one are combined.
+      int e_lo = 0;
+      auto take = [&]() {
         int u = 0;
         if (lane == 0) u = atomicAdd(&q.ctr[1], 1);
-        u = __shfl(u, 0, kWave);
-        if (u >= ptotal) break;
+        return __shfl(u, 0, kWave);
+      };
+      auto fetch = [&](int u, PieceBuf<In, kPU>& b) {
         int lo_e = e_lo, hi_e = nq;  // pfx[lo_e] <= u < pfx[hi_e]
         while (hi_e - lo_e > 1) {
           const int mid = (lo_e + hi_e) >> 1;
@@ -396,25 +415,71 @@ __device__ void enumerate_src(const Operands& op, const Src& src, int32_t c0, in
           else
             hi_e = mid;
         }
-        const int e = lo_e;
-        e_lo = e;
-        const int64_t s0 = q.lo[e] + static_cast<int64_t>(u - q.pfx[e]) * kPc;
-        const int64_t s1 = q.lo[e] + q.len[e];
-        const In ae = q.a[e];
-        int32_t cols[kPU];
-        In bv[kPU];
+        e_lo = lo_e;
+        b.s0 = q.lo[lo_e] + static_cast<int64_t>(u - q.pfx[lo_e]) * kPc;
+        b.s1 = q.lo[lo_e] + q.len[lo_e];
+        b.ae = q.a[lo_e];
 #pragma unroll
         for (int r = 0; r < kPU; ++r) {
-          const int64_t qq = s0 + r * kWave + lane;
-          if (qq < s1) {
-            cols[r] = bidx[qq];
-            bv[r] = load_val<SR>(op.b_val, qq);
+          const int64_t qq = b.s0 + r * kWave + lane;
+          if (qq < b.s1) {
+            b.cols[r] = bidx[qq];
+            b.bv[r] = load_val<SR>(op.b_val, qq);
           }
         }
+      };
+      auto consume = [&](const PieceBuf<In, kPU>& b) {
 #pragma unroll
         for (int r = 0; r < kPU; ++r) {
-          const int64_t qq = s0 + r * kWave + lane;
-          if (qq < s1) sink.add(cols[r] - c0, SR::mul(ae, bv[r]));
+          const int64_t qq = b.s0 + r * kWave + lane;
+          if (qq < b.s1) sink.add(b.cols[r] - c0, SR::mul(b.ae, b.bv[r]));
+        }
+      };
+      if constexpr (kBufs == 1) {
+        for (;;) {
+          const int u = take();
+          if (u >= ptotal) break;
+          int lo_e = e_lo, hi_e = nq;  // pfx[lo_e] <= u < pfx[hi_e]
+          while (hi_e - lo_e > 1) {
+            const int mid = (lo_e + hi_e) >> 1;
+            if (q.pfx[mid] <= u)
+              lo_e = mid;
+            else
+              hi_e = mid;
+          }
+          const int e = lo_e;
+          e_lo = e;
+          const int64_t s0 = q.lo[e] + static_cast<int64_t>(u - q.pfx[e]) * kPc;
+          const int64_t s1 = q.lo[e] + q.len[e];
+          const In ae = q.a[e];
+          int32_t cols[kPU];
+          In bv[kPU];
+#pragma unroll
+          for (int r = 0; r < kPU; ++r) {
+            const int64_t qq = s0 + r * kWave + lane;
+            if (qq < s1) {
+              cols[r] = bidx[qq];
+              bv[r] = load_val<SR>(op.b_val, qq);
+            }
+          }
+#pragma unroll
+          for (int r = 0; r < kPU; ++r) {
+            const int64_t qq = s0 + r * kWave + lane;
+            if (qq < s1) sink.add(cols[r] - c0, SR::mul(ae, bv[r]));
+          }
+        }
+      } else if (const int u0 = take(); u0 < ptotal) {
+        PieceBuf<In, kPU> b0, b1;
+        fetch(u0, b0);
+        for (;;) {
+          const int u1 = take();
+          if (u1 < ptotal) fetch(u1, b1);
+          consume(b0);
+          if (u1 >= ptotal) break;
+          const int u2 = take();
+          if (u2 < ptotal) fetch(u2, b0);
+          consume(b1);
+          if (u2 >= ptotal) break;
         }
       }
     }
@@ -427,12 +492,12 @@ __device__ void enumerate_src(const Operands& op, const Src& src, int32_t c0, in
   }
 }
 
-template <class SR, class Sink>
+template <class SR, int kBufs = 1, class Sink>
 __device__ void enumerate_row(const Operands& op, int64_t a_lo, int64_t a_hi, bool paneled,
                               const int32_t* __restrict__ pidx, int P, int p, int32_t c0,
                               int short_seg, RowQueue<typename SR::In> q, Sink& sink) {
   RowSource<SR> src{&op, a_lo, a_hi, paneled, pidx, P, p, p + 1};
-  enumerate_src<SR>(op, src, c0, short_seg, q, sink);
+  enumerate_src<SR, kBufs>(op, src, c0, short_seg, q, sink);
 }
 
 // Wave-uniform values kept in scalar registers.

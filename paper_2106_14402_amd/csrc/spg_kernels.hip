@@ -555,6 +555,13 @@ __device__ __forceinline__ void load_words_lds(uint32_t* __restrict__ dst, const
   for (int i = (n4 << 2) + tid; i < n; i += nt) dst[i] = src[i];
 }
 
+// Output entries are written once and not read again by the product:
+// streaming stores keep them from displacing the operands in the caches.
+template <class T>
+__device__ __forceinline__ void st_stream(T* p, T v) {
+  __builtin_nontemporal_store(v, p);
+}
+
 // Orders the LDS accesses of one wave: writes by some lanes before the
 // barrier are seen by reads of other lanes after it.
 __device__ __forceinline__ void wave_sync() {
@@ -625,7 +632,7 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand_rows(const int32_t* _
           }
           wave_sync();
           for (int t = lane; t < T; t += kWave)
-            if (o + t < out_end) c_idx[o + t] = stage[t];
+            if (o + t < out_end) st_stream(&c_idx[o + t], stage[t]);
           wave_sync();
           o += T;
         }
@@ -875,8 +882,8 @@ __device__ void hash_num_src(const Operands& op, const Src& src, int32_t c0, int
   // row's range of C regardless.
   const int lim = static_cast<int>(min(static_cast<int64_t>(nnz), out_end - out));
   for (int e = tid; e < lim; e += nt) {
-    c_idx[out + e] = keys[e] + c0;
-    if constexpr (!SR::kPattern) c_val[out + e] = SR::out(vals[e]);
+    st_stream(&c_idx[out + e], keys[e] + c0);
+    if constexpr (!SR::kPattern) st_stream(&c_val[out + e], SR::out(vals[e]));
   }
   __syncthreads();
 }
@@ -893,7 +900,7 @@ __device__ void hash_num_row(const Operands& op, int32_t row, int T, int short_s
 
 // Dense LDS panel accumulator for one row: presence bits plus one value per
 // column of the panel, emitted in column order into [out, out_end).
-template <class SR, class MakeSrc>
+template <class SR, int kBufs = 1, class MakeSrc>
 __device__ void dense_num_gen(const Operands& op, int wlog2, int p_begin, int p_end, int short_seg,
                               int64_t out, int64_t out_end, int32_t* __restrict__ c_idx,
                               typename SR::Out* __restrict__ c_val, unsigned char* smem,
@@ -921,7 +928,7 @@ __device__ void dense_num_gen(const Operands& op, int wlog2, int p_begin, int p_
     const int32_t wcols = min(W, op.k - c0);
     const int nwords = (wcols + 31) >> 5;
     DenseSink<SR> sink{bits, vals};
-    enumerate_src<SR>(op, make(p), c0, short_seg, q, sink);
+    enumerate_src<SR, kBufs>(op, make(p), c0, short_seg, q, sink);
     // Emit the panel in column order.  Wave w owns a contiguous range of
     // words; one block scan of the wave totals places the ranges, then each
     // wave walks its range 64 words at a time with no further barriers.
@@ -947,8 +954,8 @@ __device__ void dense_num_gen(const Operands& op, int wlog2, int p_begin, int p_
         const int b = __ffs(x) - 1;
         const int col = (w << 5) + b;
         if (o < out_end) {
-          c_idx[o] = c0 + col;
-          if constexpr (!SR::kPattern) c_val[o] = SR::out(vals[col]);
+          st_stream(&c_idx[o], c0 + col);
+          if constexpr (!SR::kPattern) st_stream(&c_val[o], SR::out(vals[col]));
         }
         if constexpr (!SR::kPattern) vals[col] = SR::identity();
         x &= x - 1;
@@ -962,7 +969,7 @@ __device__ void dense_num_gen(const Operands& op, int wlog2, int p_begin, int p_
   }
 }
 
-template <class SR>
+template <class SR, int kBufs = 1>
 __device__ void dense_num_row(const Operands& op, int32_t row, int wlog2, int P,
                               const int32_t* __restrict__ pidx, int short_seg, int64_t out,
                               int64_t out_end, int32_t* __restrict__ c_idx,
@@ -991,11 +998,11 @@ __device__ void dense_num_row(const Operands& op, int32_t row, int wlog2, int P,
       }
       return cs;
     };
-    dense_num_gen<SR>(op, wlog2, p_begin, p_end, short_seg, out, out_end, c_idx, c_val, smem, make);
+    dense_num_gen<SR, kBufs>(op, wlog2, p_begin, p_end, short_seg, out, out_end, c_idx, c_val, smem, make);
     return;
   }
   auto make = [&](int p) { return RowSource<SR>{&op, a_lo, a_hi, P > 1, pidx, P, p, p + 1}; };
-  dense_num_gen<SR>(op, wlog2, p_begin, p_end, short_seg, out, out_end, c_idx, c_val, smem, make);
+  dense_num_gen<SR, kBufs>(op, wlog2, p_begin, p_end, short_seg, out, out_end, c_idx, c_val, smem, make);
 }
 
 template <class SR>
@@ -1021,7 +1028,7 @@ __global__ __launch_bounds__(1024) void k_dense_num(Operands op, const int32_t* 
   extern __shared__ __align__(16) unsigned char smem[];
   for (int64_t it = blockIdx.x; it < nrows; it += gridDim.x) {
     const int32_t row = uniform(rows[it]);
-    dense_num_row<SR>(op, row, wlog2, P, pidx, short_seg, c_ptr[row], c_ptr[row + 1], c_idx, c_val,
+    dense_num_row<SR, 2>(op, row, wlog2, P, pidx, short_seg, c_ptr[row], c_ptr[row + 1], c_idx, c_val,
                       smem);
   }
 }
@@ -1121,7 +1128,7 @@ __device__ void rank_num_row(const Operands& op, int64_t a_lo, int64_t a_hi, int
         __syncthreads();
         BitmapSink bs{bits};
         RowSource<SrPattern> ps{&op, a_lo, a_hi, true, pchunk, NC, c_lo, c_hi};
-        enumerate_src<SrPattern>(op, ps, C0, short_seg, pq, bs);
+        enumerate_src<SrPattern, 2>(op, ps, C0, short_seg, pq, bs);
       }
       // 2. rank of the first entry of every bitmap word (contiguous words per thread)
       const int wpt = (nwords + nt - 1) / nt;
@@ -1138,13 +1145,13 @@ __device__ void rank_num_row(const Operands& op, int64_t a_lo, int64_t a_hi, int
       // 3. values, combined at their ranks
       RankSink<SR> rs{bits, pre, vals};
       RowSource<SR> vs{&op, a_lo, a_hi, true, pchunk, NC, c_lo, c_hi};
-      enumerate_src<SR>(op, vs, C0, short_seg, q, rs);
+      enumerate_src<SR, 2>(op, vs, C0, short_seg, q, rs);
       // 4. write the range out: the values in slot order; then the column
       //    ids, placed at their ranks in LDS (over the value slots, 4 bytes
       //    each at most as wide as a slot) and written in order
       static_assert(sizeof(S) >= sizeof(int32_t), "ids are staged over the value slots");
       const int lim = static_cast<int>(min(static_cast<int64_t>(total), out_end - out));
-      for (int r = tid; r < lim; r += nt) c_val[out + r] = SR::out(vals[r]);
+      for (int r = tid; r < lim; r += nt) st_stream(&c_val[out + r], SR::out(vals[r]));
       __syncthreads();
       int32_t* ids = reinterpret_cast<int32_t*>(vals);
       for (int w = tid; w < nwords; w += nt) {
@@ -1157,7 +1164,7 @@ __device__ void rank_num_row(const Operands& op, int64_t a_lo, int64_t a_hi, int
         }
       }
       __syncthreads();
-      for (int r = tid; r < lim; r += nt) c_idx[out + r] = ids[r];
+      for (int r = tid; r < lim; r += nt) st_stream(&c_idx[out + r], ids[r]);
       out += total;
       __syncthreads();
     }
@@ -1193,7 +1200,7 @@ __global__ __launch_bounds__(1024) void k_rank_num(Operands op, const int32_t* _
       auto make = [&](int p) {
         return RowSource<SR>{&op, a_lo, a_hi, true, pchunk, NC, p * r, min((p + 1) * r, NC)};
       };
-      dense_num_gen<SR>(op, wlog2, 0, P, short_seg, out, out_end, c_idx, c_val, smem, make);
+      dense_num_gen<SR, 2>(op, wlog2, 0, P, short_seg, out, out_end, c_idx, c_val, smem, make);
     } else {
       const int32_t slot = keep_slot ? uniform(keep_slot[row]) : -1;
       const uint32_t* keep = slot >= 0 ? keep_store + static_cast<int64_t>(slot) * keep_nwords : nullptr;
