@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--autotune-cache", default=None,
                     help="batched: autotuner cache file (default gpurun_out/autotune.json under the repo)")
     ap.add_argument("--opt", action="append", default=[],
-                    help="extra option for the valued product, key=value (e.g. split_panels=-1)")
+                    help="extra option for both products, key=value (e.g. short_seg=16)")
     ap.add_argument("--bitmap-mib", type=int, default=28672,
                     help="workspace for symbolic bitmaps kept for the pattern-only numeric phase")
     ap.add_argument("--bitmap-mib-valued", type=int, default=28672,
@@ -140,9 +140,9 @@ def run_rmat(args):
     mats = {"or_and_bool": Apat, "min_plus_i32": Ad}
     s_in = {"or_and_bool": 0, "min_plus_i32": 4}
     s_out = {"or_and_bool": 0, "min_plus_i32": 4}
-    opts = {"or_and_bool": B.make_options(timing=1, bitmap_mib=args.bitmap_mib),
-            "min_plus_i32": B.make_options(timing=1, bitmap_mib=args.bitmap_mib_valued,
-                                           **{k: int(v) for k, v in (o.split("=") for o in args.opt)})}
+    extra = {k: int(v) for k, v in (o.split("=") for o in args.opt)}
+    opts = {"or_and_bool": B.make_options(timing=1, bitmap_mib=args.bitmap_mib, **extra),
+            "min_plus_i32": B.make_options(timing=1, bitmap_mib=args.bitmap_mib_valued, **extra)}
     prods = {sr: S.Product(mats[sr], mats[sr], sr, opts[sr]) for sr in semirings}
     c_ptr = torch.empty(H.nrows + 1, dtype=torch.int64, device=dev)
 

@@ -77,6 +77,10 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with paper_2106_14402_amd.build.build()")
+    # The HIP runtime torch ships must be the one this library binds to: with
+    # the library loaded first, torch would bring a second runtime and the
+    # streams it hands over would not be valid here.
+    import torch  # noqa: F401
     L = ctypes.CDLL(path)
     vp, i64, st = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
     pm = ctypes.POINTER(spg_matrix)

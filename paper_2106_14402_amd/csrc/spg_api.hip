@@ -43,6 +43,8 @@ struct spg_plan {
   bool rank;                     // heavy valued rows through rank-compressed panels
   int rank_cw, rank_NC, rank_maxc;
   size_t off_rcnt, off_pchunk;
+  bool pair;                     // rank passes read B through (column, value) pairs
+  size_t off_bpair;
   int64_t seg_cap, seg_total;
   bool pnum_ready;
   unsigned long long sub_counts[kNumBins];
@@ -336,6 +338,12 @@ spg_status spg_plan_create(const spg_matrix* A, const spg_matrix* B, spg_semirin
   if (p->rank) off = align_up(off + static_cast<size_t>(m) * p->rank_NC * sizeof(int32_t));
   p->off_pchunk = off;
   if (p->rank) off = align_up(off + static_cast<size_t>(nB) * (p->rank_NC + 1) * sizeof(int32_t));
+  // 4-byte input values (float32, int32): the rank passes load each product's
+  // column id and value with one 8-byte load from a paired copy of B
+  p->pair = p->rank && (p->sr == SPG_PLUS_TIMES_F32 || p->sr == SPG_MIN_PLUS_I32 || p->sr == SPG_MIN_PLUS_F32 ||
+                        p->sr == SPG_MAX_TIMES_F32);
+  p->off_bpair = off;
+  if (p->pair) off = align_up(off + static_cast<size_t>(p->b_nnz) * sizeof(int2));
   p->seg_total = 0;
   p->pnum_ready = false;
   p->ws_bytes = off;
@@ -655,15 +663,21 @@ spg_status spg_numeric(spg_plan* p, void* ws, int32_t* c_idx, void* c_val) {
   }
   const bool ranked = p->rank && p->n_dense_sym > 0;
   auto* pchunk = reinterpret_cast<int32_t*>(w + p->off_pchunk);
+  Operands opr = op;  // the rank passes' view of the operands
   if (ranked) {
     PhaseTimer tp(p, SPG_PHASE_NUM_PANELS);
     SPG_TRY_HIP(launch_panel_index(op.b_ptr, op.b_idx, op.n, p->rank_cw, p->rank_NC, pchunk, s));
+    if (p->pair) {
+      auto* bp = reinterpret_cast<int2*>(w + p->off_bpair);
+      SPG_TRY_HIP(launch_interleave_b(op, p->b_nnz, bp, s));
+      opr.b_pair = bp;
+    }
   }
   const uint32_t* kstore = p->keep ? reinterpret_cast<const uint32_t*>(w + p->off_store) : nullptr;
   const int32_t* kslot = p->keep ? reinterpret_cast<const int32_t*>(w + p->off_rowslot) : nullptr;
   const int32_t* rcnt = reinterpret_cast<const int32_t*>(w + p->off_rcnt);
   auto rank_launch = [&](bool fixed) {
-    return launch_rank_num(p->sr, fixed, op, rows_dense_sym, p->n_dense_sym, p->rank_cw, p->rank_NC,
+    return launch_rank_num(p->sr, fixed, opr, rows_dense_sym, p->n_dense_sym, p->rank_cw, p->rank_NC,
                            p->rank_maxc, pchunk, rcnt, p->bp.hash_max_nnz, p->opt.rank_dense_div, p->num_wlog2,
                            p->num_P, p->opt.dense_threads, p->opt.short_seg, kstore, kslot, p->keep_stride,
                            p->c_ptr, c_idx, c_val, s);

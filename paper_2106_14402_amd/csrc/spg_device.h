@@ -146,6 +146,9 @@ struct Operands {
   const int32_t* b_idx;
   const void* b_val;
   int32_t m, n, k;
+  // Optional copy of B with (column id, value bits) side by side, for
+  // 4-byte values: one load per product instead of two.  NULL: unused.
+  const int2* b_pair;
 };
 
 // ---------------------------------------------------------------------------
@@ -329,6 +332,34 @@ struct SegSource {
   }
 };
 
+// A semiring whose kernels read B through Operands::b_pair (4-byte values).
+template <class SR>
+struct PairedB : SR {
+  static_assert(!SR::kPattern && sizeof(typename SR::In) == 4, "pairs hold 4-byte values");
+  static constexpr bool kPairedB = true;
+};
+template <class SR, class = void>
+struct IsPairedB {
+  static constexpr bool value = false;
+};
+template <class SR>
+struct IsPairedB<SR, decltype(void(SR::kPairedB))> {
+  static constexpr bool value = SR::kPairedB;
+};
+
+// Column id and value of B entry q.
+template <class SR>
+__device__ __forceinline__ void load_b(const Operands& op, int64_t q, int32_t& col, typename SR::In& v) {
+  if constexpr (IsPairedB<SR>::value) {
+    const int2 pr = op.b_pair[q];
+    col = pr.x;
+    v = __builtin_bit_cast(typename SR::In, pr.y);
+  } else {
+    col = op.b_idx[q];
+    v = load_val<SR>(op.b_val, q);
+  }
+}
+
 // One piece of a queued segment held in registers: products [s0, s1) of B
 // (this lane's share), their column ids and values, and the A value.
 template <class In, int U>
@@ -354,7 +385,6 @@ __device__ void enumerate_src(const Operands& op, const Src& src, int32_t c0, in
   const int tid = threadIdx.x;
   const int nt = blockDim.x;
   const int lane = tid & (kWave - 1);
-  const int32_t* __restrict__ bidx = op.b_idx;
   if (tid == 0) {
     q.ctr[0] = 0;
     q.ctr[1] = 0;
@@ -379,8 +409,7 @@ __device__ void enumerate_src(const Operands& op, const Src& src, int32_t c0, in
 #pragma unroll
         for (int u = 0; u < kShortUnroll; ++u) {
           if (t + u < len) {
-            cols[u] = bidx[lo + t + u];
-            bv[u] = load_val<SR>(op.b_val, lo + t + u);
+            load_b<SR>(op, lo + t + u, cols[u], bv[u]);
           }
         }
 #pragma unroll
@@ -423,8 +452,7 @@ __device__ void enumerate_src(const Operands& op, const Src& src, int32_t c0, in
         for (int r = 0; r < kPU; ++r) {
           const int64_t qq = b.s0 + r * kWave + lane;
           if (qq < b.s1) {
-            b.cols[r] = bidx[qq];
-            b.bv[r] = load_val<SR>(op.b_val, qq);
+            load_b<SR>(op, qq, b.cols[r], b.bv[r]);
           }
         }
       };
@@ -458,8 +486,7 @@ __device__ void enumerate_src(const Operands& op, const Src& src, int32_t c0, in
           for (int r = 0; r < kPU; ++r) {
             const int64_t qq = s0 + r * kWave + lane;
             if (qq < s1) {
-              cols[r] = bidx[qq];
-              bv[r] = load_val<SR>(op.b_val, qq);
+              load_b<SR>(op, qq, cols[r], bv[r]);
             }
           }
 #pragma unroll

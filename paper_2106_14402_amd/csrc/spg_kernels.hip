@@ -188,6 +188,22 @@ hipError_t launch_scatter(int mode, int32_t m, const int64_t* flops, const int64
   return hipGetLastError();
 }
 
+// B's column ids and 4-byte values side by side (see Operands::b_pair).
+__global__ void k_interleave_b(const int32_t* __restrict__ idx, const uint32_t* __restrict__ val, int64_t n,
+                               int2* __restrict__ out) {
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    out[i] = make_int2(idx[i], static_cast<int32_t>(val[i]));
+}
+
+hipError_t launch_interleave_b(const Operands& op, int64_t nnz, int2* out, hipStream_t s) {
+  if (nnz <= 0) return hipSuccess;
+  const int64_t nb = std::min<int64_t>((nnz + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_interleave_b, dim3(static_cast<unsigned>(nb)), dim3(256), 0, s, op.b_idx,
+                     static_cast<const uint32_t*>(op.b_val), nnz, out);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Panel index: for B row k and panel p (columns [p*W, (p+1)*W)),
 // pidx[k*(P+1) + p] = number of entries of B(k,:) with column < p*W.  Rows
@@ -1461,6 +1477,25 @@ static size_t rank_num_lds_t(int cw, int max_chunks, int wlog2, int nt) {
 }
 
 template <class SR>
+static hipError_t rank_num_launch(bool fixed, const Operands& op, const int32_t* rows, int64_t nrows, int cw,
+                                  int NC, int max_chunks, const int32_t* pchunk, const int32_t* rcnt,
+                                  int64_t hash_max_nnz, int dense_div, int wlog2, int P, int nt, int short_seg,
+                                  const uint32_t* keep_store, const int32_t* keep_slot, int64_t keep_nwords,
+                                  const int64_t* c_ptr, int32_t* c_idx, void* c_val, hipStream_t s) {
+  if (fixed)
+    hipLaunchKernelGGL((k_rank_num<SR, true>), dim3(grid_for(nrows, 0)), dim3(nt), dense_num_lds_t<SR>(wlog2, nt),
+                       s, op, rows, nrows, cw, NC, max_chunks, pchunk, rcnt, hash_max_nnz, dense_div, wlog2, P,
+                       short_seg, keep_store, keep_slot, keep_nwords, c_ptr, c_idx,
+                       static_cast<typename SR::Out*>(c_val));
+  else
+    hipLaunchKernelGGL((k_rank_num<SR, false>), dim3(grid_for(nrows, 0)), dim3(nt),
+                       rank_num_lds_bytes<SR>(cw, max_chunks, nt), s, op, rows, nrows, cw, NC, max_chunks, pchunk,
+                       rcnt, hash_max_nnz, dense_div, wlog2, P, short_seg, keep_store, keep_slot, keep_nwords, c_ptr,
+                       c_idx, static_cast<typename SR::Out*>(c_val));
+  return hipGetLastError();
+}
+
+template <class SR>
 static hipError_t rank_num_t(bool fixed, const Operands& op, const int32_t* rows, int64_t nrows, int cw, int NC,
                              int max_chunks, const int32_t* pchunk, const int32_t* rcnt, int64_t hash_max_nnz,
                              int dense_div, int wlog2, int P, int nt, int short_seg, const uint32_t* keep_store,
@@ -1469,18 +1504,18 @@ static hipError_t rank_num_t(bool fixed, const Operands& op, const int32_t* rows
   if (nrows <= 0) return hipSuccess;
   if constexpr (SR::kPattern) {
     return hipErrorInvalidValue;  // pattern-only rows use the bitmap paths
+  } else if constexpr (sizeof(typename SR::In) == 4 && !IsPairedB<SR>::value) {
+    if (op.b_pair)  // B is read through its (column id, value) pairs
+      return rank_num_t<PairedB<SR>>(fixed, op, rows, nrows, cw, NC, max_chunks, pchunk, rcnt, hash_max_nnz,
+                                     dense_div, wlog2, P, nt, short_seg, keep_store, keep_slot, keep_nwords,
+                                     c_ptr, c_idx, c_val, s);
+    return rank_num_launch<SR>(fixed, op, rows, nrows, cw, NC, max_chunks, pchunk, rcnt, hash_max_nnz,
+                               dense_div, wlog2, P, nt, short_seg, keep_store, keep_slot, keep_nwords, c_ptr,
+                               c_idx, c_val, s);
   } else {
-    if (fixed)
-      hipLaunchKernelGGL((k_rank_num<SR, true>), dim3(grid_for(nrows, 0)), dim3(nt),
-                         dense_num_lds_t<SR>(wlog2, nt), s, op, rows, nrows, cw, NC, max_chunks,
-                         pchunk, rcnt, hash_max_nnz, dense_div, wlog2, P, short_seg, keep_store, keep_slot,
-                         keep_nwords, c_ptr, c_idx, static_cast<typename SR::Out*>(c_val));
-    else
-      hipLaunchKernelGGL((k_rank_num<SR, false>), dim3(grid_for(nrows, 0)), dim3(nt),
-                       rank_num_lds_bytes<SR>(cw, max_chunks, nt), s, op, rows, nrows, cw, NC, max_chunks,
-                       pchunk, rcnt, hash_max_nnz, dense_div, wlog2, P, short_seg, keep_store, keep_slot,
-                       keep_nwords, c_ptr, c_idx, static_cast<typename SR::Out*>(c_val));
-    return hipGetLastError();
+    return rank_num_launch<SR>(fixed, op, rows, nrows, cw, NC, max_chunks, pchunk, rcnt, hash_max_nnz,
+                               dense_div, wlog2, P, nt, short_seg, keep_store, keep_slot, keep_nwords, c_ptr,
+                               c_idx, c_val, s);
   }
 }
 
