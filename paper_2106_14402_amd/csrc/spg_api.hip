@@ -250,8 +250,8 @@ spg_status spg_plan_create(const spg_matrix* A, const spg_matrix* B, spg_semirin
   p->bp.split_heavy = p->split ? 1 : 0;
 
   // Rank-compressed panels: half the LDS budget, at most 64 KiB, of value
-  // slots (2^cw of them) per pass, chunks of 2^cw columns, a bitmap of up to
-  // four columns per value byte (2^18 columns for 64 KiB).
+  // slots (2^cw of them) per pass, chunks of 2^cw columns, and a bitmap of
+  // as many chunks as the rest of the LDS holds.
   p->rank = false;
   p->rank_cw = 0;
   p->rank_NC = 0;
@@ -261,9 +261,10 @@ spg_status spg_plan_create(const spg_matrix* A, const spg_matrix* B, spg_semirin
     int cw = 5;
     while ((static_cast<size_t>(1) << (cw + 1)) * sb <= vbytes) ++cw;
     cw = std::min(cw, p->num_wlog2);
-    int maxc = std::max(1, std::min(64, static_cast<int>((4 * vbytes) >> cw)));
-    while (maxc > 1 && rank_num_lds(p->sr, cw, maxc, p->num_wlog2, nt) > static_cast<size_t>(max_lds_bytes()))
-      maxc >>= 1;
+    // the bitmap (and its per-word ranks) takes the rest of the LDS, up to
+    // 64 chunks, leaving 1 KiB for the kernel's own shared variables
+    int maxc = 64;
+    while (maxc > 1 && rank_pass_lds(p->sr, cw, maxc, nt) + 1024 > static_cast<size_t>(max_lds_bytes())) --maxc;
     const int64_t NC = (kk + (int64_t(1) << cw) - 1) >> cw;
     if (cw >= 5 && cw <= p->sym_wlog2 &&
         rank_num_lds(p->sr, cw, maxc, p->num_wlog2, nt) <= static_cast<size_t>(max_lds_bytes()) &&

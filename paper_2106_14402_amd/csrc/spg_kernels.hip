@@ -1679,6 +1679,13 @@ size_t seg_desc_bytes() { return sizeof(SegDesc); }
 
 size_t hash_num_lds(int sr, int T, int nt) { SPG_DISPATCH(sr, hash_num_lds_t, T, nt) }
 size_t dense_num_lds(int sr, int wlog2, int nt) { SPG_DISPATCH(sr, dense_num_lds_t, wlog2, nt) }
+template <class SR>
+static size_t rank_pass_lds_t(int cw, int max_chunks, int nt) {
+  return rank_num_lds_bytes<SR>(cw, max_chunks, nt);
+}
+size_t rank_pass_lds(int sr, int cw, int max_chunks, int nt) {
+  SPG_DISPATCH(sr, rank_pass_lds_t, cw, max_chunks, nt)
+}
 size_t rank_num_lds(int sr, int cw, int max_chunks, int wlog2, int nt) {
   SPG_DISPATCH(sr, rank_num_lds_t, cw, max_chunks, wlog2, nt)
 }

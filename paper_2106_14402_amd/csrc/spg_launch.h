@@ -154,6 +154,7 @@ hipError_t launch_rank_num(int sr, bool fixed, const Operands& op, const int32_t
                            const int32_t* keep_slot, int64_t keep_nwords, const int64_t* c_ptr,
                            int32_t* c_idx, void* c_val, hipStream_t s);
 size_t rank_num_lds(int sr, int cw, int max_chunks, int wlog2, int nt);
+size_t rank_pass_lds(int sr, int cw, int max_chunks, int nt);  // the rank passes alone
 hipError_t launch_hash_sym_b(const BatchDesc* descs, const int64_t* row_off, int nprod,
                              const int32_t* items, int64_t nitems, int T, int nt, int short_seg,
                              int64_t grid_cap, hipStream_t s);
