@@ -218,7 +218,7 @@ __device__ T block_sum(T v, T* tmp) {
 // ---------------------------------------------------------------------------
 template <class In>
 struct RowQueue {
-  int* ctr;       // [0] queued entries, [1] next piece, [2..17] scan scratch
+  int* ctr;       // [0] queued entries, [1] next piece, [2..33] scan scratch (16 ints or 16 int64)
   int64_t* lo;    // segment start in B
   In* a;          // A value of the entry
   int32_t* len;   // segment length
@@ -229,14 +229,14 @@ struct RowQueue {
   }
   // LDS bytes for nt threads, rounded up to 16.
   __host__ __device__ static size_t bytes(int nt) {
-    size_t b = 32 * sizeof(int) + static_cast<size_t>(nt) * sizeof(int64_t) + a_bytes(nt) +
+    size_t b = 48 * sizeof(int) + static_cast<size_t>(nt) * sizeof(int64_t) + a_bytes(nt) +
                static_cast<size_t>(nt) * sizeof(int32_t) + static_cast<size_t>(nt + 1) * sizeof(int32_t);
     return (b + 15) & ~static_cast<size_t>(15);
   }
   __device__ static RowQueue carve(unsigned char* base, int nt) {
     RowQueue q;
     q.ctr = reinterpret_cast<int*>(base);
-    unsigned char* p = base + 32 * sizeof(int);
+    unsigned char* p = base + 48 * sizeof(int);
     q.lo = reinterpret_cast<int64_t*>(p);
     p += static_cast<size_t>(nt) * sizeof(int64_t);
     q.a = reinterpret_cast<In*>(p);
@@ -373,14 +373,20 @@ struct PieceBuf {
 // kBufs = 1: a wave loads a whole piece, then combines it.  kBufs = 2: pieces
 // are half as long and a wave keeps two in flight, issuing the next piece's
 // loads before combining the current one (more registers).
-template <class SR, int kBufs = 1, class Src, class Sink>
+// kFlat: when a round of A entries has at most a few products per thread,
+// the products of all its segments are dealt to the threads directly
+// (product j to thread j mod blockDim.x, its segment found by a binary
+// search over the segments' prefix), so every product of the round is
+// loaded in one or a few waves of independent loads.
+template <class SR, int kBufs = 1, bool kFlat = false, class Src, class Sink>
 __device__ void enumerate_src(const Operands& op, const Src& src, int32_t c0, int short_seg,
                               RowQueue<typename SR::In> q, Sink& sink) {
   using In = typename SR::In;
   static_assert(kBufs == 1 || kBufs == 2, "one or two piece buffers");
   // Loads per lane per piece buffer: 16 in flight per lane (8 for 8-byte
   // values, to stay in registers).
-  constexpr int kPU = (sizeof(In) > 4 ? kPieceUnroll / 2 : kPieceUnroll) / kBufs;
+  // (half as many with kFlat, whose products mostly take the flat path).
+  constexpr int kPU = (sizeof(In) > 4 ? kPieceUnroll / 2 : kPieceUnroll) / kBufs / (kFlat ? 2 : 1);
   constexpr int kPc = kWave * kPU;
   const int tid = threadIdx.x;
   const int nt = blockDim.x;
@@ -396,6 +402,57 @@ __device__ void enumerate_src(const Operands& op, const Src& src, int32_t c0, in
     int32_t len = 0;
     In a = In(1);
     if (base + tid < total) src.load(base + tid, lo, len, a);
+    if constexpr (kFlat) {
+      constexpr int kFU = sizeof(In) > 4 ? 2 : 4;  // products per thread per batch
+      // one scan gives each entry's product offset and, in the high bits,
+      // the number of segments longer than short_seg
+      long long tot;
+      const long long packed = block_exclusive_scan(
+          static_cast<long long>(len) + (static_cast<long long>(len > short_seg) << 40),
+          reinterpret_cast<long long*>(q.ctr + 2), &tot);
+      const int off = static_cast<int>(packed & ((1ll << 40) - 1));
+      const int E = static_cast<int>(tot & ((1ll << 40) - 1));
+      const int nlong = static_cast<int>(tot >> 40);
+      // Flat when the long segments would otherwise take several piece
+      // rounds per wave and the products fit a few batches.
+      if (nlong > (nt >> 6) && E <= 8 * kFU * nt) {  // uniform
+        q.lo[tid] = lo;
+        q.a[tid] = a;
+        q.pfx[tid] = off;  // threads past the row's entries have len 0: off == E
+        if (tid == 0) q.pfx[nt] = E;
+        __syncthreads();
+        for (int j0 = 0; j0 < E; j0 += kFU * nt) {
+          int es[kFU];  // segment of each product of this batch, or -1
+#pragma unroll
+          for (int u = 0; u < kFU; ++u) {
+            const int j = j0 + u * nt + tid;
+            int e_lo = -1;
+            if (j < E) {
+              e_lo = 0;
+              int e_hi = nt;  // the last entry with pfx <= j has len > 0
+              while (e_hi - e_lo > 1) {
+                const int mid = (e_lo + e_hi) >> 1;
+                if (q.pfx[mid] <= j)
+                  e_lo = mid;
+                else
+                  e_hi = mid;
+              }
+            }
+            es[u] = e_lo;
+          }
+          int32_t cols[kFU];
+          In bv[kFU];
+#pragma unroll
+          for (int u = 0; u < kFU; ++u)
+            if (es[u] >= 0) load_b<SR>(op, q.lo[es[u]] + (j0 + u * nt + tid - q.pfx[es[u]]), cols[u], bv[u]);
+#pragma unroll
+          for (int u = 0; u < kFU; ++u)
+            if (es[u] >= 0) sink.add(cols[u] - c0, SR::mul(q.a[es[u]], bv[u]));
+        }
+        __syncthreads();  // the queue arrays are rewritten by the next round
+        continue;
+      }
+    }
     if (len > short_seg) {
       const int slot = atomicAdd(&q.ctr[0], 1);
       q.lo[slot] = lo;
@@ -519,12 +576,12 @@ __device__ void enumerate_src(const Operands& op, const Src& src, int32_t c0, in
   }
 }
 
-template <class SR, int kBufs = 1, class Sink>
+template <class SR, int kBufs = 1, bool kFlat = false, class Sink>
 __device__ void enumerate_row(const Operands& op, int64_t a_lo, int64_t a_hi, bool paneled,
                               const int32_t* __restrict__ pidx, int P, int p, int32_t c0,
                               int short_seg, RowQueue<typename SR::In> q, Sink& sink) {
   RowSource<SR> src{&op, a_lo, a_hi, paneled, pidx, P, p, p + 1};
-  enumerate_src<SR, kBufs>(op, src, c0, short_seg, q, sink);
+  enumerate_src<SR, kBufs, kFlat>(op, src, c0, short_seg, q, sink);
 }
 
 // Wave-uniform values kept in scalar registers.

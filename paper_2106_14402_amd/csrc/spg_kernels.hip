@@ -381,6 +381,7 @@ size_t dense_sym_lds(int wlog2, int nt) {
   return PatQueue::bytes(nt) + (static_cast<size_t>(1) << wlog2) / 8;
 }
 
+template <bool kFlat>
 __device__ int64_t hash_sym_row(const Operands& op, int32_t row, int T, int short_seg,
                                 unsigned char* smem) {
   const int nt = blockDim.x;
@@ -389,7 +390,7 @@ __device__ int64_t hash_sym_row(const Operands& op, int32_t row, int T, int shor
   for (int t = threadIdx.x; t < T; t += nt) keys[t] = kEmpty;
   __syncthreads();
   HashSetSink sink{keys, static_cast<uint32_t>(T - 1), 0};
-  enumerate_row<SrPattern>(op, op.a_ptr[row], op.a_ptr[row + 1], false, nullptr, 1, 0, 0, short_seg,
+  enumerate_row<SrPattern, 1, kFlat>(op, op.a_ptr[row], op.a_ptr[row + 1], false, nullptr, 1, 0, 0, short_seg,
                            q, sink);
   return block_sum(sink.count, q.ctr + 2);
 }
@@ -458,7 +459,7 @@ __global__ __launch_bounds__(1024) void k_hash_sym(Operands op, const int32_t* _
   extern __shared__ __align__(16) unsigned char smem[];
   for (int64_t it = blockIdx.x; it < nrows; it += gridDim.x) {
     const int32_t row = uniform(rows[it]);
-    const int64_t nz = hash_sym_row(op, row, T, short_seg, smem);
+    const int64_t nz = hash_sym_row<true>(op, row, T, short_seg, smem);
     if (threadIdx.x == 0) c_ptr[row + 1] = nz;
   }
 }
@@ -504,7 +505,7 @@ __global__ __launch_bounds__(1024) void k_hash_sym_b(const BatchDesc* __restrict
     const int b = uniform(batch_product(row_off, nprod, r));
     const BatchDesc d = descs[b];  // uniform: held in scalar registers
     const int32_t row = uniform(static_cast<int32_t>(r - row_off[b]));
-    const int64_t nz = hash_sym_row(d.op, row, T, short_seg, smem);
+    const int64_t nz = hash_sym_row<false>(d.op, row, T, short_seg, smem);
     if (threadIdx.x == 0) d.c_ptr[row + 1] = nz;
   }
 }
@@ -573,6 +574,8 @@ __device__ __forceinline__ void load_words_lds(uint32_t* __restrict__ dst, const
 
 // Output entries are written once and not read again by the product:
 // streaming stores keep them from displacing the operands in the caches.
+// Used where a workgroup writes long contiguous runs (whole cache lines);
+// short or scattered runs keep ordinary stores, which the L2 merges.
 template <class T>
 __device__ __forceinline__ void st_stream(T* p, T v) {
   __builtin_nontemporal_store(v, p);
@@ -843,7 +846,7 @@ constexpr int kMaxSlotsPerThread = 16;
 
 // LDS hash accumulator for one row, then compaction, bitonic sort and
 // coalesced stores of the row's entries into [out, out_end).
-template <class SR, class Src>
+template <class SR, bool kFlat = false, class Src>
 __device__ void hash_num_src(const Operands& op, const Src& src, int32_t c0, int T, int short_seg,
                              int64_t out, int64_t out_end, int32_t* __restrict__ c_idx,
                              typename SR::Out* __restrict__ c_val, unsigned char* smem) {
@@ -859,7 +862,7 @@ __device__ void hash_num_src(const Operands& op, const Src& src, int32_t c0, int
   }
   __syncthreads();
   HashMapSink<SR> sink{keys, vals, static_cast<uint32_t>(T - 1)};
-  enumerate_src<SR>(op, src, c0, short_seg, q, sink);
+  enumerate_src<SR, 1, kFlat>(op, src, c0, short_seg, q, sink);
   // Compact occupied slots to the front: every thread takes T/nt slots
   // (strided by nt, so reads are free of bank conflicts) into registers, then
   // writes them at its scanned offset.  The order does not matter: a sort
@@ -898,20 +901,20 @@ __device__ void hash_num_src(const Operands& op, const Src& src, int32_t c0, int
   // row's range of C regardless.
   const int lim = static_cast<int>(min(static_cast<int64_t>(nnz), out_end - out));
   for (int e = tid; e < lim; e += nt) {
-    st_stream(&c_idx[out + e], keys[e] + c0);
-    if constexpr (!SR::kPattern) st_stream(&c_val[out + e], SR::out(vals[e]));
+    c_idx[out + e] = keys[e] + c0;
+    if constexpr (!SR::kPattern) c_val[out + e] = SR::out(vals[e]);
   }
   __syncthreads();
 }
 
-template <class SR>
+template <class SR, bool kFlat = false>
 __device__ void hash_num_row(const Operands& op, int32_t row, int T, int short_seg, int64_t out,
                              int64_t out_end, int32_t* __restrict__ c_idx,
                              typename SR::Out* __restrict__ c_val, unsigned char* smem,
                              bool paneled = false, const int32_t* __restrict__ pidx = nullptr, int P = 1,
                              int p = 0, int32_t c0 = 0, int p_hi = 0) {
   RowSource<SR> src{&op, op.a_ptr[row], op.a_ptr[row + 1], paneled, pidx, P, p, p_hi};
-  hash_num_src<SR>(op, src, c0, T, short_seg, out, out_end, c_idx, c_val, smem);
+  hash_num_src<SR, kFlat>(op, src, c0, T, short_seg, out, out_end, c_idx, c_val, smem);
 }
 
 // Dense LDS panel accumulator for one row: presence bits plus one value per
@@ -970,8 +973,8 @@ __device__ void dense_num_gen(const Operands& op, int wlog2, int p_begin, int p_
         const int b = __ffs(x) - 1;
         const int col = (w << 5) + b;
         if (o < out_end) {
-          st_stream(&c_idx[o], c0 + col);
-          if constexpr (!SR::kPattern) st_stream(&c_val[o], SR::out(vals[col]));
+          c_idx[o] = c0 + col;
+          if constexpr (!SR::kPattern) c_val[o] = SR::out(vals[col]);
         }
         if constexpr (!SR::kPattern) vals[col] = SR::identity();
         x &= x - 1;
@@ -1030,7 +1033,7 @@ __global__ __launch_bounds__(1024) void k_hash_num(Operands op, const int32_t* _
   extern __shared__ __align__(16) unsigned char smem[];
   for (int64_t it = blockIdx.x; it < nrows; it += gridDim.x) {
     const int32_t row = uniform(rows[it]);
-    hash_num_row<SR>(op, row, T, short_seg, c_ptr[row], c_ptr[row + 1], c_idx, c_val, smem);
+    hash_num_row<SR, true>(op, row, T, short_seg, c_ptr[row], c_ptr[row + 1], c_idx, c_val, smem);
   }
 }
 
