@@ -651,7 +651,7 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand_rows(const int32_t* _
           }
           wave_sync();
           for (int t = lane; t < T; t += kWave)
-            if (o + t < out_end) st_stream(&c_idx[o + t], stage[t]);
+            if (o + t < out_end) c_idx[o + t] = stage[t];
           wave_sync();
           o += T;
         }
