@@ -178,6 +178,24 @@ typedef struct spg_plan spg_plan;
 spg_status spg_plan_create(const spg_matrix* A, const spg_matrix* B, spg_semiring sr,
                            const spg_options* opt, void* stream, spg_plan** out);
 
+/* Semiring sum of k matrices of one shape, C(i,j) = (+)_t P_t(i,j) over the
+ * parts that hold (i,j): the merge of the partial products that the stages
+ * of Sparse SUMMA produce (paper Sec. 3.2: each process accumulates the
+ * local products of every stage), and elementwise semiring addition (k = 2).
+ * The parts come stacked in one matrix P in either layout: with m slices
+ * per part, slice i of part t is slice t*m + i of P (so P has k*m rows in
+ * CSR, k*m columns in CSC), each sorted strictly ascending.  C has m slices
+ * in P's layout.  The plan is used like a product plan: spg_workspace_size,
+ * spg_symbolic, spg_numeric, spg_plan_destroy.  It runs as C = S P with S
+ * the m x (k m) selector whose slice i holds the (x)-identity at t*m + i,
+ * built in the workspace by spg_symbolic, so a sum entry is combined with
+ * the semiring's own (+) and no value changes on the way (x (x) one = x).
+ * P must stay valid until the plan is destroyed.
+ * Errors: SPG_E_INVALID (k < 1, bad descriptor), SPG_E_SHAPE (slices not a
+ * multiple of k), SPG_E_SEMIRING (bad code or missing values). */
+spg_status spg_sum_plan_create(int k, const spg_matrix* P, spg_semiring sr, const spg_options* opt,
+                               void* stream, spg_plan** out);
+
 /* Bytes of device workspace the plan needs (256-byte aligned base).  The same
  * workspace must be passed, untouched, to spg_symbolic and spg_numeric. */
 spg_status spg_workspace_size(const spg_plan* plan, size_t* bytes);

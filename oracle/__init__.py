@@ -55,6 +55,8 @@ def load(path: str):
     vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
     L.orc_spgemm.restype = vp
     L.orc_spgemm.argtypes = [i32, i32, i64, vp, vp, vp, vp, vp, vp, vp, i32]
+    L.orc_sum.restype = vp
+    L.orc_sum.argtypes = [i32, i64, i32, vp, vp, vp, i32]
     L.orc_nnz.restype = i64
     L.orc_nnz.argtypes = [vp]
     L.orc_elem_bytes.restype = i32
@@ -126,6 +128,40 @@ def spgemm(A, B, semiring, select: Optional[Sequence[int]] = None,
     try:
         nnz = L.orc_nnz(h)
         ptr = np.empty(nsel + 1, np.int64)
+        idx = np.empty(nnz, np.int32)
+        val = np.empty(nnz, OUT_DTYPE[code])
+        L.orc_copy(h, _p(ptr), _p(idx), _p(val))
+    finally:
+        L.orc_free(h)
+    return ptr, idx, val
+
+
+def sum_parts(parts, semiring, nthreads: int = 0, _lib=None) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """(+)_t parts[t] over the semiring, entry by entry (parts: SparseMatrix
+    of one shape and layout).  Returns (ptr, idx, val) of the result's slices
+    (rows for CSR, columns for CSC)."""
+    code = _code(semiring)
+    P0 = parts[0]
+    if any(p.layout != P0.layout or p.nrows != P0.nrows or p.ncols != P0.ncols for p in parts):
+        raise ValueError("parts must share shape and layout")
+    m = P0.nrows if P0.layout == "csr" else P0.ncols
+    ptrs, idxs, vals, base = [np.zeros(1, np.int64)], [], [], 0
+    for p in parts:
+        pp, pi, pv = _arrays(p, code, "P")
+        ptrs.append(pp[1:] + base)
+        idxs.append(pi)
+        vals.append(pv)
+        base += int(pp[-1])
+    Pp = np.ascontiguousarray(np.concatenate(ptrs))
+    Pi = np.ascontiguousarray(np.concatenate(idxs) if idxs else np.zeros(0, np.int32))
+    Pv = None if vals[0] is None else np.ascontiguousarray(np.concatenate(vals))
+    L = _lib or lib()
+    h = L.orc_sum(code, m, len(parts), _p(Pp), _p(Pi), _p(Pv), int(nthreads))
+    if not h:
+        raise ValueError(f"unknown semiring {semiring}")
+    try:
+        nnz = L.orc_nnz(h)
+        ptr = np.empty(m + 1, np.int64)
         idx = np.empty(nnz, np.int32)
         val = np.empty(nnz, OUT_DTYPE[code])
         L.orc_copy(h, _p(ptr), _p(idx), _p(val))

@@ -192,9 +192,72 @@ ResultBase* run(bool csc, int64_t nsel, const int64_t* sel, const int64_t* Ap, c
   return r;
 }
 
+// One slice of a semiring sum of k parts stacked slice-wise (slice s of
+// part t is slice t*m + s): every stored entry of the k slices, merged by
+// key with (+).
+template <class S>
+void sum_slice(int64_t s, int64_t m, int k, const int64_t* Pp, const int32_t* Pi, const void* Pv,
+               std::vector<int32_t>& keys, std::vector<typename S::T>& vals) {
+  std::map<int32_t, typename S::T> acc;
+  for (int t = 0; t < k; ++t) {
+    const int64_t r = t * m + s;
+    for (int64_t q = Pp[r]; q < Pp[r + 1]; ++q) {
+      const auto v = static_cast<typename S::T>(value_at<S>(Pv, q));
+      auto it = acc.find(Pi[q]);
+      if (it == acc.end())
+        acc.emplace(Pi[q], v);
+      else
+        it->second = S::add(it->second, v);
+    }
+  }
+  keys.clear();
+  vals.clear();
+  for (const auto& kv : acc) {
+    keys.push_back(kv.first);
+    vals.push_back(kv.second);
+  }
+}
+
+template <class S>
+ResultBase* run_sum(int64_t m, int k, const int64_t* Pp, const int32_t* Pi, const void* Pv, int nthreads) {
+  auto* r = new Result<S>();
+  r->elem = sizeof(typename S::T);
+  r->keys.resize(m);
+  r->vals.resize(m);
+  r->counts.resize(m);
+  if (nthreads <= 0) nthreads = omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 64) num_threads(nthreads)
+  for (int64_t s = 0; s < m; ++s) {
+    sum_slice<S>(s, m, k, Pp, Pi, Pv, r->keys[s], r->vals[s]);
+    r->counts[s] = static_cast<int64_t>(r->keys[s].size());
+  }
+  int64_t nnz = 0;
+  for (auto c : r->counts) nnz += c;
+  r->nnz = nnz;
+  return r;
+}
+
 }  // namespace
 
 extern "C" {
+
+// Semiring sum of k parts of m slices each, stacked slice-wise in (Pp, Pi,
+// Pv): slice s of the result is the (+) of slices s, m+s, ..., (k-1)m+s,
+// entry by entry (the layout does not matter: slices are rows or columns
+// alike).  Same result handle as orc_spgemm.
+void* orc_sum(int semiring, int64_t m, int k, const int64_t* Pp, const int32_t* Pi, const void* Pv,
+              int nthreads) {
+  switch (semiring) {
+    case 0: return run_sum<PlusTimesF64>(m, k, Pp, Pi, Pv, nthreads);
+    case 1: return run_sum<PlusTimesF32in64>(m, k, Pp, Pi, Pv, nthreads);
+    case 2: return run_sum<MinPlusI32>(m, k, Pp, Pi, Pv, nthreads);
+    case 3: return run_sum<MinPlusF32>(m, k, Pp, Pi, Pv, nthreads);
+    case 4: return run_sum<OrAndBool>(m, k, Pp, Pi, Pv, nthreads);
+    case 5: return run_sum<MaxTimesF64>(m, k, Pp, Pi, Pv, nthreads);
+    case 6: return run_sum<MaxTimesF32>(m, k, Pp, Pi, Pv, nthreads);
+    default: return nullptr;
+  }
+}
 
 // Computes the selected output slices of C = A (x).(+) B.
 //   layout 0: CSR.  A is m x n with row pointers Ap (m+1) and column ids Ai;

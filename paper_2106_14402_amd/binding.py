@@ -106,6 +106,8 @@ def load(path: str = LIB_PATH):
     pint = ctypes.POINTER(ctypes.c_int)
     L.spg_plan_panels.restype = st
     L.spg_plan_panels.argtypes = [vp, pint, pint, pint, pint]
+    L.spg_sum_plan_create.restype = st
+    L.spg_sum_plan_create.argtypes = [ctypes.c_int, pm, ctypes.c_int, po, vp, ctypes.POINTER(vp)]
     L.spg_plan_options.restype = st
     L.spg_plan_options.argtypes = [vp, ctypes.POINTER(spg_options)]
     L.spg_panel_index_size.restype = st
@@ -194,6 +196,16 @@ def spg_plan_create(A: spg_matrix, B: spg_matrix, semiring, options: Optional[sp
     _check(load().spg_plan_create(ctypes.byref(A), ctypes.byref(B), code,
                                   ctypes.byref(options) if options is not None else None,
                                   _stream(stream), ctypes.byref(plan)), "spg_plan_create")
+    return plan
+
+
+def spg_sum_plan_create(k: int, P: spg_matrix, semiring, options: Optional[spg_options] = None,
+                        stream=None) -> ctypes.c_void_p:
+    code = SEMIRINGS[semiring] if isinstance(semiring, str) else int(semiring)
+    plan = ctypes.c_void_p()
+    _check(load().spg_sum_plan_create(int(k), ctypes.byref(P), code,
+                                      ctypes.byref(options) if options is not None else None,
+                                      _stream(stream), ctypes.byref(plan)), "spg_sum_plan_create")
     return plan
 
 

@@ -45,6 +45,8 @@ struct spg_plan {
   size_t off_rcnt, off_pchunk;
   bool pair;                     // rank passes read B through (column, value) pairs
   size_t off_bpair;
+  int sum_k;                     // > 0: a semiring sum of sum_k stacked parts; A is the selector
+  size_t off_sel, off_sel_idx, off_sel_val;  // built in the workspace by spg_symbolic
   int64_t seg_cap, seg_total;
   bool pnum_ready;
   unsigned long long sub_counts[kNumBins];
@@ -160,66 +162,12 @@ BinOffsets offsets_of(const unsigned long long* counts) {
 
 }  // namespace
 
-extern "C" {
-
-const char* spg_status_str(spg_status s) {
-  switch (s) {
-    case SPG_OK: return "ok";
-    case SPG_E_INVALID: return "invalid argument or malformed matrix";
-    case SPG_E_SHAPE: return "shape mismatch";
-    case SPG_E_LAYOUT: return "bad or mixed layout";
-    case SPG_E_SEMIRING: return "unknown semiring or missing values";
-    case SPG_E_NOMEM: return "workspace too small or over budget";
-    case SPG_E_OVERFLOW: return "integer overflow";
-    case SPG_E_DEVICE: return "HIP device error";
-    case SPG_E_STATE: return "call out of order";
-  }
-  return "unknown status";
-}
-
-spg_status spg_plan_create(const spg_matrix* A, const spg_matrix* B, spg_semiring sr_in,
-                           const spg_options* opt_in, void* stream, spg_plan** out) {
-  if (!out) return SPG_E_INVALID;
-  *out = nullptr;
+// Options, panel widths, workspace layout and timing events of a plan whose
+// oriented operands (p->op, a_nnz, b_nnz, sr, csc, stream) are set.
+static spg_status plan_init(spg_plan* p, const spg_options* opt_in) {
   spg_status st;
-  if ((st = check_matrix(A)) != SPG_OK) return st;
-  if ((st = check_matrix(B)) != SPG_OK) return st;
-  const int sr = static_cast<int>(sr_in);
-  if (!valid_semiring(sr)) return SPG_E_SEMIRING;
-  if (A->layout != B->layout) return SPG_E_LAYOUT;
-  if (A->ncols != B->nrows) return SPG_E_SHAPE;
-  const bool bool_sr = sr == SPG_OR_AND_BOOL;
-  if (!bool_sr && ((A->nnz > 0 && !A->val) || (B->nnz > 0 && !B->val))) return SPG_E_SEMIRING;
-
-  auto* p = new (std::nothrow) spg_plan();
-  if (!p) return SPG_E_NOMEM;
-  p->user_sr = sr;
-  p->csc = A->layout == SPG_CSC;
-  p->stream = static_cast<hipStream_t>(stream);
-  // Orientation.  CSR: C = A B row by row.  CSC: the arrays of a CSC matrix
-  // are the CSR arrays of its transpose, and C^T = B^T A^T, so the CSR kernel
-  // runs on (B^T, A^T).  Every listed multiplication is commutative, so the
-  // operand swap needs no change to (x).
-  const spg_matrix* L = p->csc ? B : A;
-  const spg_matrix* R = p->csc ? A : B;
-  p->op.a_ptr = L->ptr;
-  p->op.a_idx = L->idx;
-  p->op.a_val = L->val;
-  p->op.b_ptr = R->ptr;
-  p->op.b_idx = R->idx;
-  p->op.b_val = R->val;
-  p->a_nnz = L->nnz;
-  p->b_nnz = R->nnz;
-  p->op.m = p->csc ? B->ncols : A->nrows;
-  p->op.n = A->ncols;
-  p->op.k = p->csc ? A->nrows : B->ncols;
-  p->sr = (bool_sr && !A->val && !B->val) ? 7 : sr;
-
   resolve_options(opt_in, &p->opt, p->sr);
-  if ((st = check_options(p->opt, p->sr)) != SPG_OK) {
-    delete p;
-    return st;
-  }
+  if ((st = check_options(p->opt, p->sr)) != SPG_OK) return st;
   p->bp.hash_max_flops = p->opt.hash_max_flops;
   p->bp.hash_max_nnz = p->opt.hash_max_nnz;
   p->bp.split_heavy = 0;
@@ -345,6 +293,16 @@ spg_status spg_plan_create(const spg_matrix* A, const spg_matrix* B, spg_semirin
                         p->sr == SPG_MAX_TIMES_F32);
   p->off_bpair = off;
   if (p->pair) off = align_up(off + static_cast<size_t>(p->b_nnz) * sizeof(int2));
+  // selector of a semiring sum: ptr (m+1), ids and values (k per row)
+  p->off_sel = p->off_sel_idx = p->off_sel_val = off;
+  if (p->sum_k > 0) {
+    const size_t sel = static_cast<size_t>(m) * p->sum_k;
+    off = align_up(off + static_cast<size_t>(m + 1) * sizeof(int64_t));
+    p->off_sel_idx = off;
+    off = align_up(off + sel * sizeof(int32_t));
+    p->off_sel_val = off;
+    off = align_up(off + sel * 8);
+  }
   p->seg_total = 0;
   p->pnum_ready = false;
   p->ws_bytes = off;
@@ -357,11 +315,112 @@ spg_status spg_plan_create(const spg_matrix* A, const spg_matrix* B, spg_semirin
   if (p->opt.timing) {
     bool ok = true;
     for (int i = 0; i < 2 * SPG_NUM_PHASES; ++i) ok = ok && hipEventCreate(&p->ev[i]) == hipSuccess;
-    if (!ok) {
-      delete p;
-      return SPG_E_DEVICE;
-    }
+    if (!ok) return SPG_E_DEVICE;
     p->ev_made = true;
+  }
+  return SPG_OK;
+}
+
+extern "C" {
+
+const char* spg_status_str(spg_status s) {
+  switch (s) {
+    case SPG_OK: return "ok";
+    case SPG_E_INVALID: return "invalid argument or malformed matrix";
+    case SPG_E_SHAPE: return "shape mismatch";
+    case SPG_E_LAYOUT: return "bad or mixed layout";
+    case SPG_E_SEMIRING: return "unknown semiring or missing values";
+    case SPG_E_NOMEM: return "workspace too small or over budget";
+    case SPG_E_OVERFLOW: return "integer overflow";
+    case SPG_E_DEVICE: return "HIP device error";
+    case SPG_E_STATE: return "call out of order";
+  }
+  return "unknown status";
+}
+
+spg_status spg_plan_create(const spg_matrix* A, const spg_matrix* B, spg_semiring sr_in,
+                           const spg_options* opt_in, void* stream, spg_plan** out) {
+  if (!out) return SPG_E_INVALID;
+  *out = nullptr;
+  spg_status st;
+  if ((st = check_matrix(A)) != SPG_OK) return st;
+  if ((st = check_matrix(B)) != SPG_OK) return st;
+  const int sr = static_cast<int>(sr_in);
+  if (!valid_semiring(sr)) return SPG_E_SEMIRING;
+  if (A->layout != B->layout) return SPG_E_LAYOUT;
+  if (A->ncols != B->nrows) return SPG_E_SHAPE;
+  const bool bool_sr = sr == SPG_OR_AND_BOOL;
+  if (!bool_sr && ((A->nnz > 0 && !A->val) || (B->nnz > 0 && !B->val))) return SPG_E_SEMIRING;
+
+  auto* p = new (std::nothrow) spg_plan();
+  if (!p) return SPG_E_NOMEM;
+  p->user_sr = sr;
+  p->csc = A->layout == SPG_CSC;
+  p->stream = static_cast<hipStream_t>(stream);
+  // Orientation.  CSR: C = A B row by row.  CSC: the arrays of a CSC matrix
+  // are the CSR arrays of its transpose, and C^T = B^T A^T, so the CSR kernel
+  // runs on (B^T, A^T).  Every listed multiplication is commutative, so the
+  // operand swap needs no change to (x).
+  const spg_matrix* L = p->csc ? B : A;
+  const spg_matrix* R = p->csc ? A : B;
+  p->op.a_ptr = L->ptr;
+  p->op.a_idx = L->idx;
+  p->op.a_val = L->val;
+  p->op.b_ptr = R->ptr;
+  p->op.b_idx = R->idx;
+  p->op.b_val = R->val;
+  p->a_nnz = L->nnz;
+  p->b_nnz = R->nnz;
+  p->op.m = p->csc ? B->ncols : A->nrows;
+  p->op.n = A->ncols;
+  p->op.k = p->csc ? A->nrows : B->ncols;
+  p->sr = (bool_sr && !A->val && !B->val) ? 7 : sr;
+
+  spg_status sti = plan_init(p, opt_in);
+  if (sti != SPG_OK) {
+    delete p;
+    return sti;
+  }
+  *out = p;
+  return SPG_OK;
+}
+
+spg_status spg_sum_plan_create(int k, const spg_matrix* P, spg_semiring sr_in, const spg_options* opt_in,
+                               void* stream, spg_plan** out) {
+  if (!out) return SPG_E_INVALID;
+  *out = nullptr;
+  spg_status st;
+  if ((st = check_matrix(P)) != SPG_OK) return st;
+  const int sr = static_cast<int>(sr_in);
+  if (!valid_semiring(sr)) return SPG_E_SEMIRING;
+  if (k < 1) return SPG_E_INVALID;
+  const bool csc = P->layout == SPG_CSC;
+  const int64_t major = csc ? P->ncols : P->nrows;
+  const int64_t minor = csc ? P->nrows : P->ncols;
+  if (major % k != 0) return SPG_E_SHAPE;
+  const int64_t m = major / k;
+  const bool bool_sr = sr == SPG_OR_AND_BOOL;
+  if (!bool_sr && P->nnz > 0 && !P->val) return SPG_E_SEMIRING;
+  auto* p = new (std::nothrow) spg_plan();
+  if (!p) return SPG_E_NOMEM;
+  p->user_sr = sr;
+  p->csc = csc;
+  p->stream = static_cast<hipStream_t>(stream);
+  // Oriented: C = S P with S the m x (k m) selector (built at symbolic time),
+  // P's slices as the rows of the right operand.
+  p->op.b_ptr = P->ptr;
+  p->op.b_idx = P->idx;
+  p->op.b_val = P->val;
+  p->b_nnz = P->nnz;
+  p->a_nnz = m * k;
+  p->op.m = static_cast<int32_t>(m);
+  p->op.n = static_cast<int32_t>(major);
+  p->op.k = static_cast<int32_t>(minor);
+  p->sr = (bool_sr && !P->val) ? 7 : sr;
+  p->sum_k = k;
+  if ((st = plan_init(p, opt_in)) != SPG_OK) {
+    delete p;
+    return st;
   }
   *out = p;
   return SPG_OK;
@@ -471,6 +530,15 @@ spg_status spg_symbolic(spg_plan* p, void* ws, int64_t* c_ptr, int64_t* c_nnz) {
   auto* rows_num = reinterpret_cast<int32_t*>(w + p->off_rows_num);
   auto* scan = reinterpret_cast<int64_t*>(w + p->off_scan);
   auto* psym = reinterpret_cast<int32_t*>(w + p->off_psym);
+  if (p->sum_k > 0) {
+    // the selector: row i takes the parts' rows t*m + i with the (x)-identity
+    p->op.a_ptr = reinterpret_cast<int64_t*>(w + p->off_sel);
+    p->op.a_idx = reinterpret_cast<int32_t*>(w + p->off_sel_idx);
+    p->op.a_val = p->sr == 7 ? nullptr : w + p->off_sel_val;
+    SPG_TRY_HIP(launch_selector(p->op.m, p->sum_k, reinterpret_cast<int64_t*>(w + p->off_sel),
+                                reinterpret_cast<int32_t*>(w + p->off_sel_idx),
+                                p->sr == 7 ? nullptr : w + p->off_sel_val, p->sr, s));
+  }
   const Operands& op = p->op;
   const int32_t m = op.m;
 

@@ -16,6 +16,9 @@
 // cores are involved.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cstring>
+
 #include "spg_launch.h"
 
 namespace spg {
@@ -185,6 +188,48 @@ hipError_t launch_scatter(int mode, int32_t m, const int64_t* flops, const int64
   const int nt = 256;
   hipLaunchKernelGGL(k_scatter, dim3((m + nt - 1) / nt), dim3(nt), 0, s, mode, m, flops, c_ptr, bp,
                      offs, cursors, rows_out);
+  return hipGetLastError();
+}
+
+// Selector of a semiring sum of k stacked parts (m slices each): slice i
+// has k entries, at t*m + i for t = 0..k-1, each the (x)-identity of the
+// semiring's input type (es bytes, given as raw bits in `one`).
+__global__ void k_selector(int32_t m, int k, int64_t* __restrict__ ptr, int32_t* __restrict__ idx,
+                           unsigned char* __restrict__ val, int es, uint64_t one) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  const int64_t first = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  for (int64_t i = first; i <= m; i += stride) ptr[i] = i * k;
+  const int64_t total = static_cast<int64_t>(m) * k;
+  for (int64_t e = first; e < total; e += stride) {
+    const int64_t i = e / k;
+    const int64_t t = e - i * k;
+    idx[e] = static_cast<int32_t>(t * m + i);
+    if (val) {
+      if (es == 8)
+        reinterpret_cast<uint64_t*>(val)[e] = one;
+      else if (es == 4)
+        reinterpret_cast<uint32_t*>(val)[e] = static_cast<uint32_t>(one);
+      else
+        val[e] = static_cast<unsigned char>(one);
+    }
+  }
+}
+
+hipError_t launch_selector(int32_t m, int k, int64_t* ptr, int32_t* idx, void* val, int sr, hipStream_t s) {
+  // the (x)-identity: 1 for (+,x), (max,x) and (OR,AND); 0 for (min,+)
+  uint64_t one = 0;
+  int es = 0;
+  switch (sr) {
+    case 0: case 5: { const double v = 1.0; std::memcpy(&one, &v, 8); es = 8; break; }
+    case 1: case 6: { const float v = 1.0f; uint32_t b; std::memcpy(&b, &v, 4); one = b; es = 4; break; }
+    case 2: case 3: one = 0; es = 4; break;  // int32 0 and float +0.0f
+    case 4: one = 1; es = 1; break;
+    default: es = 0; break;                  // pattern only: no values
+  }
+  const int64_t work = static_cast<int64_t>(m) * k + m + 1;
+  const int64_t nb = std::max<int64_t>(1, std::min<int64_t>((work + 255) / 256, 65536));
+  hipLaunchKernelGGL(k_selector, dim3(static_cast<unsigned>(nb)), dim3(256), 0, s, m, k, ptr, idx,
+                     static_cast<unsigned char*>(es ? val : nullptr), es, one);
   return hipGetLastError();
 }
 

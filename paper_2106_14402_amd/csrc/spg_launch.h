@@ -104,6 +104,8 @@ hipError_t launch_scatter(int mode, int32_t m, const int64_t* flops, const int64
                           int32_t* rows_out, hipStream_t s);
 hipError_t launch_panel_index(const int64_t* b_ptr, const int32_t* b_idx, int32_t nrows, int wlog2,
                               int P, int32_t* pidx, hipStream_t s);
+// Selector of a semiring sum (see k_selector); sr is the kernel semiring code.
+hipError_t launch_selector(int32_t m, int k, int64_t* ptr, int32_t* idx, void* val, int sr, hipStream_t s);
 // (column id, value bits) pairs of B's entries, for 4-byte values.
 hipError_t launch_interleave_b(const Operands& op, int64_t nnz, int2* out, hipStream_t s);
 // In-place inclusive scan of x[0..len); then x[-1] = 0 (x points one past a

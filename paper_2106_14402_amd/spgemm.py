@@ -120,6 +120,56 @@ class Product:
             pass
 
 
+class SumPlan(Product):
+    """C = (+)_t P_t for k parts of one shape, given stacked in one matrix
+    (slice i of part t is slice t*m + i); runs through the product engine."""
+
+    def __init__(self, P: DeviceMatrix, k: int, semiring: str, options=None, stream=None):
+        self.A, self.B, self.semiring = P, P, semiring
+        self.stream = stream if stream is not None else torch.cuda.current_stream(P.ptr.device)
+        self._dp = P.descriptor()
+        self.plan = B_.spg_sum_plan_create(k, self._dp, semiring, options, self.stream)
+        self.ws = torch.empty(max(1, B_.spg_workspace_size(self.plan)), dtype=torch.uint8,
+                              device=P.ptr.device)
+        major = P.nrows if P.layout == "csr" else P.ncols
+        m = major // k
+        self.nslices = m
+        if P.layout == "csr":
+            self.out_rows, self.out_cols = m, P.ncols
+        else:
+            self.out_rows, self.out_cols = P.nrows, m
+        self.c_ptr = None
+        self.c_nnz = None
+
+
+def stack(parts) -> DeviceMatrix:
+    """k device matrices of one shape and layout stacked slice-wise."""
+    lay = parts[0].layout
+    assert all(p.layout == lay and p.nrows == parts[0].nrows and p.ncols == parts[0].ncols for p in parts)
+    ptrs, base = [parts[0].ptr[:1]], 0
+    for p in parts:
+        ptrs.append(p.ptr[1:] + base)
+        base += p.nnz
+    ptr = torch.cat(ptrs)
+    idx = torch.cat([p.idx for p in parts])
+    val = None if parts[0].val is None else torch.cat([p.val for p in parts])
+    k = len(parts)
+    if lay == "csr":
+        return DeviceMatrix(parts[0].nrows * k, parts[0].ncols, lay, ptr, idx, val)
+    return DeviceMatrix(parts[0].nrows, parts[0].ncols * k, lay, ptr, idx, val)
+
+
+def spg_sum(parts, semiring: str, options=None, stream=None) -> DeviceMatrix:
+    """(+)_t parts[t] over the semiring (the merge of partial products)."""
+    P = stack(parts)
+    p = SumPlan(P, len(parts), semiring, options, stream)
+    try:
+        p.symbolic()
+        return p.numeric()
+    finally:
+        p.close()
+
+
 def spgemm(A: DeviceMatrix, B: DeviceMatrix, semiring: str, options=None, stream=None) -> DeviceMatrix:
     """C = A (x).(+) B; both operands in one layout, C in that layout."""
     p = Product(A, B, semiring, options, stream)
