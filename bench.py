@@ -40,7 +40,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target host time of the oracle sample (0 disables)")
     ap.add_argument("--semirings", default="or_and_bool,min_plus_i32")
-    ap.add_argument("--workload", default="rmat", choices=["rmat", "er", "mcl", "batched", "served"],
+    ap.add_argument("--workload", default="rmat", choices=["rmat", "er", "mcl", "batched", "served", "merge"],
                     help="rmat (default) is the named benchmark workload; the others are the "
                          "remaining configurations, printed in the same JSON form")
     ap.add_argument("--nprod", type=int, default=512, help="batched: number of products")
@@ -111,7 +111,7 @@ def main():
               f"(the product is a single-GPU kernel path)", file=sys.stderr)
         sys.exit(2)
     run = {"rmat": run_rmat, "er": run_er, "mcl": run_mcl, "batched": run_batched,
-           "served": run_served}[args.workload]
+           "served": run_served, "merge": run_merge}[args.workload]
     out = run(args)
     print(json.dumps(out), flush=True)
 
@@ -479,6 +479,70 @@ def run_served(args):
                        "n": A.nrows, "nnz_A": A.nnz, "requests_per_rate": args.requests}, higher=False)
     out["mu1_req_s"] = round(mu1, 1)
     out["rates"] = rates
+    return out
+
+
+def run_merge(args):
+    """Merge of SUMMA partial products: R-MAT scale 18 (symmetrised, int32
+    weights) squared over (min,+) with the inner dimension cut into 4 equal
+    blocks; the 4 partial products A(:,K_t) A(K_t,:) are formed once, and a
+    step is their semiring sum (symbolic + numeric).  Reported as HBM GB/s of
+    the algorithmic bytes (read every part once, write C once)."""
+    import torch
+
+    import spgen
+    from paper_2106_14402_amd import spgemm as S
+    t0 = time.time()
+    H = spgen.rmat_graph(18, 16, spgen.rng_for(1, 18), symmetric=True, weights="i32")
+    log(f"[bench] R-MAT scale 18 nnz={H.nnz} in {time.time() - t0:.1f}s")
+    k, n = 4, H.nrows
+    cuts = [n * t // k for t in range(k + 1)]
+    rows = np.repeat(np.arange(n), np.diff(H.ptr))
+    parts = []
+    for lo, hi in zip(cuts[:-1], cuts[1:]):
+        kc = (H.idx >= lo) & (H.idx < hi)
+        kr = (rows >= lo) & (rows < hi)
+        Ac = spgen.from_pairs(n, n, rows[kc], H.idx[kc], H.val[kc])
+        Br = spgen.from_pairs(n, n, rows[kr], H.idx[kr], H.val[kr])
+        parts.append(S.spgemm(S.to_device(Ac), S.to_device(Br), "min_plus_i32"))
+    torch.cuda.synchronize()
+    P = S.stack(parts)
+    in_nnz = int(P.nnz)
+    p = S.SumPlan(P, k, "min_plus_i32")
+    nnz = p.symbolic()
+    c_idx = torch.empty(nnz, dtype=torch.int32, device="cuda")
+    c_val = torch.empty(nnz, dtype=torch.int32, device="cuda")
+
+    def step():
+        p.symbolic(p.c_ptr)
+        p.numeric(c_idx, c_val)
+    ms = timed(step, args.steps, args.warmup)
+    alg = 8 * in_nnz + 8 * (k * n + 1) + 8 * nnz + 8 * (n + 1)
+    gbs = alg / (ms * 1e-3) / 1e9
+    out = base_record(args, round(gbs, 1), "GB/s", ms, "int32",
+                      {"workload": "merge of 4 SUMMA partial products of R-MAT scale 18 squared over (min,+) int32",
+                       "n": n, "parts": k, "entries_in": in_nnz, "nnz_C": nnz})
+    out["roofline"] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "whole merge step",
+                       "alg_bytes": alg}
+    if args.cpu_seconds > 0:
+        import oracle
+        nthreads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+        hp = [(x.ptr.cpu().numpy(), x.idx.cpu().numpy(), x.val.cpu().numpy()) for x in parts]
+        sel = np.sort(np.random.default_rng(7).choice(n, size=min(n, 20000), replace=False))
+        sub = []
+        for pp, pi, pv in hp:
+            cnt = pp[sel + 1] - pp[sel]
+            ptr = np.concatenate([[0], np.cumsum(cnt)]).astype(np.int64)
+            take = np.concatenate([np.arange(pp[r], pp[r + 1]) for r in sel])
+            sub.append(spgen.SparseMatrix(sel.size, n, "csr", ptr, pi[take], pv[take]))
+        t = time.perf_counter()
+        res = oracle.sum_parts(sub, "min_plus_i32", nthreads=nthreads)
+        dt = time.perf_counter() - t
+        sub_alg = 8 * sum(x.nnz for x in sub) + 8 * (k * sel.size + 1) + 8 * int(res[0][-1]) + 8 * (sel.size + 1)
+        out["cpu_baseline"] = {"value": round(sub_alg / dt / 1e9, 3), "unit": "GB/s", "cores": nthreads,
+                               "kind": "oracle", "sample": f"{sel.size} seeded random rows of {n} ({dt:.1f} s)"}
+    p.close()
     return out
 
 
