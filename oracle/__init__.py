@@ -170,6 +170,20 @@ def sum_parts(parts, semiring, nthreads: int = 0, _lib=None) -> Tuple[np.ndarray
     return ptr, idx, val
 
 
+def inflate(C, r: float) -> np.ndarray:
+    """Inflation with renormalisation, in float64: every slice's values to
+    the power r, divided by their sum (slices summing to 0 are kept).
+    Returns the new values in C's entry order."""
+    v = np.asarray(C.val, dtype=np.float64) ** float(r)
+    out = v.copy()
+    for s in range(C.ptr.size - 1):
+        lo, hi = int(C.ptr[s]), int(C.ptr[s + 1])
+        tot = v[lo:hi].sum()
+        if tot != 0.0:
+            out[lo:hi] = v[lo:hi] / tot
+    return out
+
+
 def flops(A, B, select: Optional[Sequence[int]] = None) -> np.ndarray:
     """Number of (x) operations per output slice."""
     layout = 0 if A.layout == "csr" else 1

@@ -106,6 +106,8 @@ def load(path: str = LIB_PATH):
     pint = ctypes.POINTER(ctypes.c_int)
     L.spg_plan_panels.restype = st
     L.spg_plan_panels.argtypes = [vp, pint, pint, pint, pint]
+    L.spg_inflate_f32.restype = st
+    L.spg_inflate_f32.argtypes = [pm, ctypes.c_float, vp, vp]
     L.spg_sum_plan_create.restype = st
     L.spg_sum_plan_create.argtypes = [ctypes.c_int, pm, ctypes.c_int, po, vp, ctypes.POINTER(vp)]
     L.spg_plan_options.restype = st
@@ -197,6 +199,10 @@ def spg_plan_create(A: spg_matrix, B: spg_matrix, semiring, options: Optional[sp
                                   ctypes.byref(options) if options is not None else None,
                                   _stream(stream), ctypes.byref(plan)), "spg_plan_create")
     return plan
+
+
+def spg_inflate_f32(C: spg_matrix, r: float, val_out, stream=None) -> None:
+    _check(load().spg_inflate_f32(ctypes.byref(C), float(r), _addr(val_out), _stream(stream)), "spg_inflate_f32")
 
 
 def spg_sum_plan_create(k: int, P: spg_matrix, semiring, options: Optional[spg_options] = None,

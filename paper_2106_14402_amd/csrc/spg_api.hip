@@ -801,6 +801,17 @@ spg_status spg_prune_count_f32(const spg_matrix* C, float thresh, void* ws, void
   return SPG_OK;
 }
 
+spg_status spg_inflate_f32(const spg_matrix* C, float r, float* val_out, void* stream) {
+  spg_status st = check_matrix(C);
+  if (st != SPG_OK) return st;
+  if (C->nnz > 0 && (!C->val || !val_out)) return SPG_E_INVALID;
+  if (!(r > 0.0f)) return SPG_E_INVALID;
+  const int64_t nmajor = C->layout == SPG_CSR ? C->nrows : C->ncols;
+  SPG_TRY_HIP(launch_inflate(C->ptr, static_cast<const float*>(C->val), nmajor, r, val_out,
+                             static_cast<hipStream_t>(stream)));
+  return SPG_OK;
+}
+
 spg_status spg_prune_apply_f32(const spg_matrix* C, float thresh, void* ws, void* stream,
                                const int64_t* new_ptr, int32_t* new_idx, float* new_val) {
   spg_status st = check_matrix(C);

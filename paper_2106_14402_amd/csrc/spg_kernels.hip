@@ -1788,6 +1788,33 @@ __global__ void k_prune_apply(const int64_t* __restrict__ ptr, const int32_t* __
   }
 }
 
+// Inflation and renormalisation (the Markov-clustering step after pruning):
+// every slice's values raised to the power r, then divided by their sum
+// (taken in float64).  One wave per slice; val_out may be val.
+__global__ void k_inflate(const int64_t* __restrict__ ptr, const float* val, int64_t nmajor, float r,
+                          float* val_out) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t s = static_cast<int64_t>(blockIdx.x) * (blockDim.x / kWave) + (threadIdx.x >> 6);
+  if (s >= nmajor) return;
+  const int64_t lo = ptr[s], hi = ptr[s + 1];
+  double sum = 0.0;
+  for (int64_t p = lo + lane; p < hi; p += kWave) sum += static_cast<double>(powf(val[p], r));
+  sum = wave_sum(sum);
+  if (sum == 0.0) return;
+  const double inv = 1.0 / sum;
+  for (int64_t p = lo + lane; p < hi; p += kWave)
+    val_out[p] = static_cast<float>(static_cast<double>(powf(val[p], r)) * inv);
+}
+
+hipError_t launch_inflate(const int64_t* ptr, const float* val, int64_t nmajor, float r, float* val_out,
+                          hipStream_t s) {
+  if (nmajor <= 0) return hipSuccess;
+  const int nt = 256;
+  const int64_t nb = (nmajor + nt / kWave - 1) / (nt / kWave);
+  hipLaunchKernelGGL(k_inflate, dim3(static_cast<unsigned>(nb)), dim3(nt), 0, s, ptr, val, nmajor, r, val_out);
+  return hipGetLastError();
+}
+
 hipError_t launch_prune_count(const int64_t* ptr, const float* val, int64_t nmajor, float thresh,
                               int64_t* new_ptr, hipStream_t s) {
   if (nmajor <= 0) return hipSuccess;

@@ -104,6 +104,9 @@ hipError_t launch_scatter(int mode, int32_t m, const int64_t* flops, const int64
                           int32_t* rows_out, hipStream_t s);
 hipError_t launch_panel_index(const int64_t* b_ptr, const int32_t* b_idx, int32_t nrows, int wlog2,
                               int P, int32_t* pidx, hipStream_t s);
+// Inflation + renormalisation of every slice of a float32 matrix.
+hipError_t launch_inflate(const int64_t* ptr, const float* val, int64_t nmajor, float r, float* val_out,
+                          hipStream_t s);
 // Selector of a semiring sum (see k_selector); sr is the kernel semiring code.
 hipError_t launch_selector(int32_t m, int k, int64_t* ptr, int32_t* idx, void* val, int sr, hipStream_t s);
 // (column id, value bits) pairs of B's entries, for 4-byte values.

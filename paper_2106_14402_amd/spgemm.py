@@ -120,6 +120,14 @@ class Product:
             pass
 
 
+def inflate_f32(C: DeviceMatrix, r: float, in_place: bool = True, stream=None) -> DeviceMatrix:
+    """Raise every value to the power r and renormalise each slice to sum 1."""
+    stream = stream if stream is not None else torch.cuda.current_stream(C.ptr.device)
+    out = C.val if in_place else torch.empty_like(C.val)
+    B_.spg_inflate_f32(C.descriptor(), r, out, stream)
+    return DeviceMatrix(C.nrows, C.ncols, C.layout, C.ptr, C.idx, out)
+
+
 class SumPlan(Product):
     """C = (+)_t P_t for k parts of one shape, given stacked in one matrix
     (slice i of part t is slice t*m + i); runs through the product engine."""
