@@ -40,9 +40,10 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target host time of the oracle sample (0 disables)")
     ap.add_argument("--semirings", default="or_and_bool,min_plus_i32")
-    ap.add_argument("--workload", default="rmat", choices=["rmat", "er", "mcl", "batched", "served", "merge"],
+    ap.add_argument("--workload", default="rmat", choices=["rmat", "er", "mcl", "batched", "served", "merge", "outbatch"],
                     help="rmat (default) is the named benchmark workload; the others are the "
                          "remaining configurations, printed in the same JSON form")
+    ap.add_argument("--batches", type=int, default=4, help="outbatch: output budget = nnz(C) / batches")
     ap.add_argument("--nprod", type=int, default=512, help="batched: number of products")
     ap.add_argument("--requests", type=int, default=2000, help="served: requests per arrival rate")
     ap.add_argument("--autotune-cache", default=None,
@@ -111,7 +112,7 @@ def main():
               f"(the product is a single-GPU kernel path)", file=sys.stderr)
         sys.exit(2)
     run = {"rmat": run_rmat, "er": run_er, "mcl": run_mcl, "batched": run_batched,
-           "served": run_served, "merge": run_merge}[args.workload]
+           "served": run_served, "merge": run_merge, "outbatch": run_outbatch}[args.workload]
     out = run(args)
     print(json.dumps(out), flush=True)
 
@@ -548,6 +549,61 @@ def run_merge(args):
         sub_alg = 8 * sum(x.nnz for x in sub) + 8 * (k * sel.size + 1) + 8 * int(res[0][-1]) + 8 * (sel.size + 1)
         out["cpu_baseline"] = {"value": round(sub_alg / dt / 1e9, 3), "unit": "GB/s", "cores": nthreads,
                                "kind": "oracle", "sample": f"{sel.size} seeded random rows of {n} ({dt:.1f} s)"}
+    p.close()
+    return out
+
+
+def run_outbatch(args):
+    """Output formed in batches: R-MAT scale 20 (symmetrised, int32 weights)
+    squared over (min,+), with an output budget of nnz(C) / 4 entries (the
+    paper forms its largest product in 4 batches).  A step is the symbolic
+    phase, the split of the slices into ranges that fit the budget (from the
+    offsets, on the host), and the numeric phase of each range into the same
+    two buffers of budget size.  The same product in one call is timed
+    beside it."""
+    import torch
+
+    import spgen
+    from paper_2106_14402_amd import binding as B
+    from paper_2106_14402_amd import spgemm as S
+    t0 = time.time()
+    H = spgen.rmat_graph(args.scale, 16, spgen.rng_for(1), symmetric=True, weights="i32")
+    log(f"[bench] R-MAT scale {args.scale} nnz={H.nnz} in {time.time() - t0:.1f}s")
+    extra = {k: int(v) for k, v in (o.split("=") for o in args.opt)}
+    dA = S.to_device(H)
+    p = S.Product(dA, dA, "min_plus_i32", B.make_options(bitmap_mib=args.bitmap_mib_valued, **extra))
+    nnz = p.symbolic()
+    flops = p.stats()[0]
+    budget = -(-nnz // args.batches)
+    ranges = p.row_batches(budget)
+    cap = max(int(p.c_ptr[re] - p.c_ptr[rb]) for rb, re in ranges)
+    idx = torch.empty(cap, dtype=torch.int32, device="cuda")
+    val = torch.empty(cap, dtype=torch.int32, device="cuda")
+    log(f"[bench] nnz(C)={nnz} budget={budget} -> {len(ranges)} ranges, largest {cap}")
+
+    def step():
+        p.symbolic(p.c_ptr)
+        for rb, re in p.row_batches(budget):
+            p.numeric_rows(rb, re, idx, val)
+    ms = timed(step, args.steps, args.warmup)
+    del idx, val
+    full_idx = torch.empty(nnz, dtype=torch.int32, device="cuda")
+    full_val = torch.empty(nnz, dtype=torch.int32, device="cuda")
+
+    def single():
+        p.symbolic(p.c_ptr)
+        p.numeric(full_idx, full_val)
+    ms_single = timed(single, args.steps, args.warmup)
+    out = base_record(args, round(2.0 * flops / (ms * 1e-3) / 1e9, 2), "GFLOP/s", ms, "int32",
+                      {"workload": f"R-MAT scale {args.scale} squared over (min,+) int32, output formed in batches "
+                                   f"of at most nnz(C)/{args.batches} entries",
+                       "flops": flops, "nnz_C": nnz, "batches": len(ranges), "budget_entries": budget})
+    out["output_buffer_bytes"] = 8 * cap
+    out["single_call_output_bytes"] = 8 * nnz
+    out["single_call_ms"] = round(ms_single, 3)
+    out["batched_over_single"] = round(ms / ms_single, 4)
+    if args.cpu_seconds > 0:
+        out["cpu_baseline"] = cpu_baseline_generic(H, "min_plus_i32", args.cpu_seconds)
     p.close()
     return out
 

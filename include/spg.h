@@ -220,6 +220,29 @@ spg_status spg_symbolic(spg_plan* plan, void* ws, int64_t* c_ptr, int64_t* c_nnz
  * Asynchronous: returns once the work is enqueued. */
 spg_status spg_numeric(spg_plan* plan, void* ws, int32_t* c_idx, void* c_val);
 
+/* Numeric phase of output slices [row_begin, row_end) only: forming C in
+ * batches when the whole output does not fit in memory (paper Sec. 7.2 and
+ * 7.3: the product is formed in b batches, b computed from a symbolic step).
+ * After one spg_symbolic, the caller picks slice ranges from c_ptr (each
+ * range's entries are c_ptr[row_end] - c_ptr[row_begin]) and calls this once
+ * per range, into buffers that need only hold that range:
+ *   c_idx  device, int32[c_ptr[row_end] - c_ptr[row_begin]]; entry e of
+ *          slice r (e from 0) is written at c_ptr[r] - c_ptr[row_begin] + e
+ *   c_val  device, values of the same count and position (rules of
+ *          spg_numeric)
+ * The ids and values written are those spg_numeric writes for these slices.
+ * Each call re-bins the numeric row lists of its range (one device pass over
+ * the range and one device-to-host copy, which synchronise the stream); the
+ * kernels then run asynchronously.  A plan and its workspace run one range
+ * at a time; calls on one stream are ordered.  spg_numeric afterwards
+ * re-bins the whole product by itself.
+ * Errors: SPG_E_INVALID (range outside [0, nslices], row_end < row_begin,
+ * NULL outputs for a non-empty range), SPG_E_STATE (no symbolic phase yet,
+ * or a plan with options.split_panels = 1 and a range that is not the whole
+ * product: its (slice, window) work items span every slice). */
+spg_status spg_numeric_rows(spg_plan* plan, void* ws, int64_t row_begin, int64_t row_end, int32_t* c_idx,
+                            void* c_val);
+
 /* Statistics of the last symbolic phase (host): total products (flops, the
  * paper's count of nonzero multiplications) and number of output slices. */
 spg_status spg_plan_stats(const spg_plan* plan, int64_t* flops, int64_t* nslices);

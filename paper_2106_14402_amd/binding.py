@@ -95,6 +95,8 @@ def load(path: str = LIB_PATH):
     L.spg_symbolic.argtypes = [vp, vp, vp, ctypes.POINTER(i64)]
     L.spg_numeric.restype = st
     L.spg_numeric.argtypes = [vp, vp, vp, vp]
+    L.spg_numeric_rows.restype = st
+    L.spg_numeric_rows.argtypes = [vp, vp, i64, i64, vp, vp]
     L.spg_plan_stats.restype = st
     L.spg_plan_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     L.spg_plan_timings.restype = st
@@ -229,6 +231,11 @@ def spg_symbolic(plan, ws, c_ptr) -> int:
 
 def spg_numeric(plan, ws, c_idx, c_val) -> None:
     _check(load().spg_numeric(plan, _addr(ws), _addr(c_idx), _addr(c_val)), "spg_numeric")
+
+
+def spg_numeric_rows(plan, ws, row_begin: int, row_end: int, c_idx, c_val) -> None:
+    _check(load().spg_numeric_rows(plan, _addr(ws), int(row_begin), int(row_end), _addr(c_idx), _addr(c_val)),
+           "spg_numeric_rows")
 
 
 def spg_plan_stats(plan):

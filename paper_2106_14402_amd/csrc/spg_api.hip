@@ -45,6 +45,7 @@ struct spg_plan {
   size_t off_rcnt, off_pchunk;
   bool pair;                     // rank passes read B through (column, value) pairs
   size_t off_bpair;
+  int32_t lists_rb, lists_re;    // rows [lists_rb, lists_re) fill the numeric row lists
   int sum_k;                     // > 0: a semiring sum of sum_k stacked parts; A is the selector
   size_t off_sel, off_sel_idx, off_sel_val;  // built in the workspace by spg_symbolic
   int64_t seg_cap, seg_total;
@@ -571,7 +572,7 @@ spg_status spg_symbolic(spg_plan* p, void* ws, int64_t* c_ptr, int64_t* c_nnz) {
   for (int b = kDenseBinBase; b < kNumBins; ++b) ndense += static_cast<int64_t>(p->sym_counts[b]);
   {
     PhaseTimer t(p, SPG_PHASE_SYM_HASH);
-    SPG_TRY_HIP(launch_scatter(0, m, flops, c_ptr, p->bp, so, ctr + kCtrCursor, rows_sym, s));
+    SPG_TRY_HIP(launch_scatter(0, m, 0, flops, c_ptr, p->bp, so, ctr + kCtrCursor, rows_sym, s));
     for (int c = 1; c < kDenseBinBase; ++c) {
       if (!p->sym_counts[c]) continue;
       SPG_TRY_HIP(launch_hash_sym(op, rows_sym + so.v[c], static_cast<int64_t>(p->sym_counts[c]),
@@ -611,7 +612,7 @@ spg_status spg_symbolic(spg_plan* p, void* ws, int64_t* c_ptr, int64_t* c_nnz) {
       (p->keep && p->sr == 7 && ndense > 0) ? reinterpret_cast<const int32_t*>(w + p->off_rowslot) : nullptr;
   {
     PhaseTimer t(p, SPG_PHASE_SCAN);
-    SPG_TRY_HIP(launch_count_num_bins(m, flops, c_ptr, p->bp, ctr + kCtrNum, s));
+    SPG_TRY_HIP(launch_count_num_bins(m, 0, 0, flops, c_ptr, p->bp, ctr + kCtrNum, s));
     SPG_TRY_HIP(launch_scan_inplace(c_ptr + 1, m, scan, s));
     if (p->split && ndense > 0)
       SPG_TRY_HIP(launch_sub_prepare(ndense, p->num_P, reinterpret_cast<int32_t*>(w + p->off_subcnt),
@@ -642,7 +643,9 @@ spg_status spg_symbolic(spg_plan* p, void* ws, int64_t* c_ptr, int64_t* c_nnz) {
   SPG_TRY_HIP(hipStreamSynchronize(s));
   const BinOffsets no = offsets_of(p->num_counts);
   SPG_TRY_HIP(launch_fill_u64(reinterpret_cast<uint64_t*>(ctr + kCtrCursor), kNumBins, 0, s));
-  SPG_TRY_HIP(launch_scatter(1, m, flops, c_ptr, p->bp, no, ctr + kCtrCursor, rows_num, s));
+  SPG_TRY_HIP(launch_scatter(1, m, 0, flops, c_ptr, p->bp, no, ctr + kCtrCursor, rows_num, s));
+  p->lists_rb = 0;
+  p->lists_re = m;
   if (p->split && ndense > 0) {
     const BinOffsets sbo = offsets_of(p->sub_counts);
     SPG_TRY_HIP(launch_fill_u64(reinterpret_cast<uint64_t*>(ctr + kCtrSym), kNumBins, 0, s));
@@ -657,13 +660,61 @@ spg_status spg_symbolic(spg_plan* p, void* ws, int64_t* c_ptr, int64_t* c_nnz) {
   return SPG_OK;
 }
 
-spg_status spg_numeric(spg_plan* p, void* ws, int32_t* c_idx, void* c_val) {
-  if (!p) return SPG_E_INVALID;
+// Bytes of one output value (0: pattern only).
+static int out_bytes(int sr) {
+  switch (sr) {
+    case 0: case 5: return 8;
+    case 4: return 1;
+    case 7: return 0;
+    default: return 4;
+  }
+}
+
+// Numeric row lists for rows [rb, re) only (after the offsets scan).
+static spg_status rebin_rows(spg_plan* p, unsigned char* w, int32_t rb, int32_t re) {
+  hipStream_t s = p->stream;
+  auto* ctr = reinterpret_cast<unsigned long long*>(w + p->off_ctr);
+  auto* flops = reinterpret_cast<int64_t*>(w + p->off_flops);
+  auto* rows_num = reinterpret_cast<int32_t*>(w + p->off_rows_num);
+  SPG_TRY_HIP(launch_fill_u64(reinterpret_cast<uint64_t*>(ctr + kCtrNum), kNumBins, 0, s));
+  SPG_TRY_HIP(launch_count_num_bins(re, rb, 1, flops, p->c_ptr, p->bp, ctr + kCtrNum, s));
+  SPG_TRY_HIP(hipMemcpyAsync(p->num_counts, ctr + kCtrNum, kNumBins * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+  SPG_TRY_HIP(hipStreamSynchronize(s));
+  const BinOffsets no = offsets_of(p->num_counts);
+  SPG_TRY_HIP(launch_fill_u64(reinterpret_cast<uint64_t*>(ctr + kCtrCursor), kNumBins, 0, s));
+  SPG_TRY_HIP(launch_scatter(1, re, rb, flops, p->c_ptr, p->bp, no, ctr + kCtrCursor, rows_num, s));
+  p->lists_rb = rb;
+  p->lists_re = re;
+  return SPG_OK;
+}
+
+// Numeric phase of rows [rb, re); their entries go to c_idx/c_val from
+// position 0 (C entry c_ptr[rb] + e is written at e).
+static spg_status numeric_range(spg_plan* p, void* ws, int32_t rb, int32_t re, int32_t* c_idx_in, void* c_val_in) {
   if (p->state != kSymbolicDone) return SPG_E_STATE;
-  if (p->c_nnz > 0 && !c_idx) return SPG_E_INVALID;
-  if (p->c_nnz > 0 && !c_val && p->sr != 7) return SPG_E_INVALID;
   hipStream_t s = p->stream;
   unsigned char* w = static_cast<unsigned char*>(ws);
+  int64_t base = 0, range_nnz = p->c_nnz;
+  if (rb != 0 || re != p->op.m) {
+    if (p->split) return SPG_E_STATE;  // (row, window) items cover the whole product
+    int64_t ends[2] = {0, 0};
+    SPG_TRY_HIP(hipMemcpyAsync(&ends[0], p->c_ptr + rb, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    SPG_TRY_HIP(hipMemcpyAsync(&ends[1], p->c_ptr + re, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    SPG_TRY_HIP(hipStreamSynchronize(s));
+    base = ends[0];
+    range_nnz = ends[1] - ends[0];
+  }
+  if (range_nnz > 0 && !c_idx_in) return SPG_E_INVALID;
+  if (range_nnz > 0 && !c_val_in && p->sr != 7) return SPG_E_INVALID;
+  if (rb != p->lists_rb || re != p->lists_re) {
+    spg_status st = rebin_rows(p, w, rb, re);
+    if (st != SPG_OK) return st;
+  }
+  // The kernels write entry c_ptr[row] + e; shift the outputs so that entry
+  // c_ptr[rb] lands at position 0 of the caller's buffers.
+  int32_t* c_idx = reinterpret_cast<int32_t*>(reinterpret_cast<uintptr_t>(c_idx_in) - base * sizeof(int32_t));
+  void* c_val = c_val_in ? reinterpret_cast<void*>(reinterpret_cast<uintptr_t>(c_val_in) - base * out_bytes(p->sr))
+                         : nullptr;
   auto* rows_num = reinterpret_cast<int32_t*>(w + p->off_rows_num);
   auto* pnum = reinterpret_cast<int32_t*>(w + p->off_pnum);
   const Operands& op = p->op;
@@ -746,7 +797,8 @@ spg_status spg_numeric(spg_plan* p, void* ws, int32_t* c_idx, void* c_val) {
   const int32_t* kslot = p->keep ? reinterpret_cast<const int32_t*>(w + p->off_rowslot) : nullptr;
   const int32_t* rcnt = reinterpret_cast<const int32_t*>(w + p->off_rcnt);
   auto rank_launch = [&](bool fixed) {
-    return launch_rank_num(p->sr, fixed, opr, rows_dense_sym, p->n_dense_sym, p->rank_cw, p->rank_NC,
+    return launch_rank_num(p->sr, fixed, opr, rows_dense_sym, p->n_dense_sym, p->lists_rb, p->lists_re,
+                           p->rank_cw, p->rank_NC,
                            p->rank_maxc, pchunk, rcnt, p->bp.hash_max_nnz, p->opt.rank_dense_div, p->num_wlog2,
                            p->num_P, p->opt.dense_threads, p->opt.short_seg, kstore, kslot, p->keep_stride,
                            p->c_ptr, c_idx, c_val, s);
@@ -773,6 +825,18 @@ spg_status spg_numeric(spg_plan* p, void* ws, int32_t* c_idx, void* c_val) {
     SPG_TRY_HIP(rank_launch(false));
   }
   return SPG_OK;
+}
+
+spg_status spg_numeric(spg_plan* p, void* ws, int32_t* c_idx, void* c_val) {
+  if (!p) return SPG_E_INVALID;
+  return numeric_range(p, ws, 0, p->op.m, c_idx, c_val);
+}
+
+spg_status spg_numeric_rows(spg_plan* p, void* ws, int64_t row_begin, int64_t row_end, int32_t* c_idx,
+                            void* c_val) {
+  if (!p) return SPG_E_INVALID;
+  if (row_begin < 0 || row_end < row_begin || row_end > p->op.m) return SPG_E_INVALID;
+  return numeric_range(p, ws, static_cast<int32_t>(row_begin), static_cast<int32_t>(row_end), c_idx, c_val);
 }
 
 spg_status spg_prune_workspace_size(const spg_matrix* C, size_t* bytes) {

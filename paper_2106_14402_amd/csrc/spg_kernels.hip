@@ -121,37 +121,39 @@ hipError_t launch_flops_bin(const Operands& op, BinParams bp, int64_t* flops, in
   return hipGetLastError();
 }
 
-// Numeric bin counts; c_ptr[i+1] still holds nnz of row i (before the scan).
-__global__ void k_count_num_bins(int32_t m, const int64_t* __restrict__ flops,
+// Numeric bin counts of rows [r0, m).  Before the scan c_ptr[i+1] holds the
+// nnz of row i (scanned = 0); after it, c_ptr holds offsets (scanned = 1).
+__global__ void k_count_num_bins(int32_t m, int32_t r0, int scanned, const int64_t* __restrict__ flops,
                                  const int64_t* __restrict__ c_ptr, BinParams bp,
                                  unsigned long long* counts) {
   __shared__ unsigned int lc[kNumBins];
   const int tid = threadIdx.x;
   if (tid < kNumBins) lc[tid] = 0;
   __syncthreads();
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + tid;
+  const int64_t i = r0 + static_cast<int64_t>(blockIdx.x) * blockDim.x + tid;
   if (i < m) {
+    const int64_t nz = scanned ? c_ptr[i + 1] - c_ptr[i] : c_ptr[i + 1];
     const bool split = bp.split_heavy && flops[i] > bp.hash_max_flops;
-    const bool ranked = bp.rank_heavy && flops[i] > bp.hash_max_flops && c_ptr[i + 1] > bp.hash_max_nnz;
+    const bool ranked = bp.rank_heavy && flops[i] > bp.hash_max_flops && nz > bp.hash_max_nnz;
     const bool kept = bp.row_slot && flops[i] > bp.hash_max_flops && bp.row_slot[i] >= 0;
-    atomicAdd(&lc[kept ? kExpandBin : ((split || ranked) ? 0 : num_bin(c_ptr[i + 1], flops[i], bp))], 1u);
+    atomicAdd(&lc[kept ? kExpandBin : ((split || ranked) ? 0 : num_bin(nz, flops[i], bp))], 1u);
   }
   __syncthreads();
   if (tid < kNumBins && lc[tid]) atomicAdd(&counts[tid], static_cast<unsigned long long>(lc[tid]));
 }
 
-hipError_t launch_count_num_bins(int32_t m, const int64_t* flops, const int64_t* c_ptr, BinParams bp,
-                                 unsigned long long* counts, hipStream_t s) {
-  if (m <= 0) return hipSuccess;
+hipError_t launch_count_num_bins(int32_t m, int32_t r0, int scanned, const int64_t* flops, const int64_t* c_ptr,
+                                 BinParams bp, unsigned long long* counts, hipStream_t s) {
+  if (m - r0 <= 0) return hipSuccess;
   const int nt = 256;
-  hipLaunchKernelGGL(k_count_num_bins, dim3((m + nt - 1) / nt), dim3(nt), 0, s, m, flops, c_ptr, bp,
-                     counts);
+  hipLaunchKernelGGL(k_count_num_bins, dim3((m - r0 + nt - 1) / nt), dim3(nt), 0, s, m, r0, scanned, flops,
+                     c_ptr, bp, counts);
   return hipGetLastError();
 }
 
 // Row lists per bin.  Each block reserves one range per bin with a single
 // global atomic; row order inside a bin is unspecified.
-__global__ void k_scatter(int mode, int32_t m, const int64_t* __restrict__ flops,
+__global__ void k_scatter(int mode, int32_t m, int32_t r0, const int64_t* __restrict__ flops,
                           const int64_t* __restrict__ c_ptr, BinParams bp, BinOffsets offs,
                           unsigned long long* cursors, int32_t* __restrict__ rows_out) {
   __shared__ unsigned int lc[kNumBins];
@@ -159,7 +161,7 @@ __global__ void k_scatter(int mode, int32_t m, const int64_t* __restrict__ flops
   const int tid = threadIdx.x;
   if (tid < kNumBins) lc[tid] = 0;
   __syncthreads();
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + tid;
+  const int64_t i = r0 + static_cast<int64_t>(blockIdx.x) * blockDim.x + tid;
   int bin = 0;
   unsigned int local = 0;
   if (i < m) {
@@ -181,12 +183,12 @@ __global__ void k_scatter(int mode, int32_t m, const int64_t* __restrict__ flops
   if (bin > 0) rows_out[offs.v[bin] + static_cast<int64_t>(lbase[bin]) + local] = static_cast<int32_t>(i);
 }
 
-hipError_t launch_scatter(int mode, int32_t m, const int64_t* flops, const int64_t* c_ptr,
+hipError_t launch_scatter(int mode, int32_t m, int32_t r0, const int64_t* flops, const int64_t* c_ptr,
                           BinParams bp, const BinOffsets& offs, unsigned long long* cursors,
                           int32_t* rows_out, hipStream_t s) {
-  if (m <= 0) return hipSuccess;
+  if (m - r0 <= 0) return hipSuccess;
   const int nt = 256;
-  hipLaunchKernelGGL(k_scatter, dim3((m + nt - 1) / nt), dim3(nt), 0, s, mode, m, flops, c_ptr, bp,
+  hipLaunchKernelGGL(k_scatter, dim3((m - r0 + nt - 1) / nt), dim3(nt), 0, s, mode, m, r0, flops, c_ptr, bp,
                      offs, cursors, rows_out);
   return hipGetLastError();
 }
@@ -1240,7 +1242,8 @@ __device__ void rank_num_row(const Operands& op, int64_t a_lo, int64_t a_hi, int
 // than hash_max_nnz entries; the others went to the hash numeric bins.
 template <class SR, bool kFixed>
 __global__ __launch_bounds__(1024) void k_rank_num(Operands op, const int32_t* __restrict__ rows,
-                                                   int64_t nrows, int cw, int NC, int max_chunks,
+                                                   int64_t nrows, int32_t rb, int32_t re, int cw, int NC,
+                                                   int max_chunks,
                                                    const int32_t* __restrict__ pchunk,
                                                    const int32_t* __restrict__ rcnt, int64_t hash_max_nnz,
                                                    int dense_div, int wlog2, int P, int short_seg,
@@ -1253,6 +1256,7 @@ __global__ __launch_bounds__(1024) void k_rank_num(Operands op, const int32_t* _
   __shared__ int info[2];
   for (int64_t it = blockIdx.x; it < nrows; it += gridDim.x) {
     const int32_t row = uniform(rows[it]);
+    if (row < rb || row >= re) continue;  // another range of rows
     const int64_t out = uniform64(c_ptr[row]), out_end = uniform64(c_ptr[row + 1]);
     const int64_t nnz = out_end - out;
     if (nnz <= hash_max_nnz) continue;
@@ -1525,26 +1529,28 @@ static size_t rank_num_lds_t(int cw, int max_chunks, int wlog2, int nt) {
 }
 
 template <class SR>
-static hipError_t rank_num_launch(bool fixed, const Operands& op, const int32_t* rows, int64_t nrows, int cw,
+static hipError_t rank_num_launch(bool fixed, const Operands& op, const int32_t* rows, int64_t nrows, int32_t rb,
+                                  int32_t re, int cw,
                                   int NC, int max_chunks, const int32_t* pchunk, const int32_t* rcnt,
                                   int64_t hash_max_nnz, int dense_div, int wlog2, int P, int nt, int short_seg,
                                   const uint32_t* keep_store, const int32_t* keep_slot, int64_t keep_nwords,
                                   const int64_t* c_ptr, int32_t* c_idx, void* c_val, hipStream_t s) {
   if (fixed)
     hipLaunchKernelGGL((k_rank_num<SR, true>), dim3(grid_for(nrows, 0)), dim3(nt), dense_num_lds_t<SR>(wlog2, nt),
-                       s, op, rows, nrows, cw, NC, max_chunks, pchunk, rcnt, hash_max_nnz, dense_div, wlog2, P,
-                       short_seg, keep_store, keep_slot, keep_nwords, c_ptr, c_idx,
+                       s, op, rows, nrows, rb, re, cw, NC, max_chunks, pchunk, rcnt, hash_max_nnz, dense_div, wlog2,
+                       P, short_seg, keep_store, keep_slot, keep_nwords, c_ptr, c_idx,
                        static_cast<typename SR::Out*>(c_val));
   else
     hipLaunchKernelGGL((k_rank_num<SR, false>), dim3(grid_for(nrows, 0)), dim3(nt),
-                       rank_num_lds_bytes<SR>(cw, max_chunks, nt), s, op, rows, nrows, cw, NC, max_chunks, pchunk,
+                       rank_num_lds_bytes<SR>(cw, max_chunks, nt), s, op, rows, nrows, rb, re, cw, NC, max_chunks, pchunk,
                        rcnt, hash_max_nnz, dense_div, wlog2, P, short_seg, keep_store, keep_slot, keep_nwords, c_ptr,
                        c_idx, static_cast<typename SR::Out*>(c_val));
   return hipGetLastError();
 }
 
 template <class SR>
-static hipError_t rank_num_t(bool fixed, const Operands& op, const int32_t* rows, int64_t nrows, int cw, int NC,
+static hipError_t rank_num_t(bool fixed, const Operands& op, const int32_t* rows, int64_t nrows, int32_t rb,
+                             int32_t re, int cw, int NC,
                              int max_chunks, const int32_t* pchunk, const int32_t* rcnt, int64_t hash_max_nnz,
                              int dense_div, int wlog2, int P, int nt, int short_seg, const uint32_t* keep_store,
                              const int32_t* keep_slot, int64_t keep_nwords, const int64_t* c_ptr,
@@ -1554,14 +1560,14 @@ static hipError_t rank_num_t(bool fixed, const Operands& op, const int32_t* rows
     return hipErrorInvalidValue;  // pattern-only rows use the bitmap paths
   } else if constexpr (sizeof(typename SR::In) == 4 && !IsPairedB<SR>::value) {
     if (op.b_pair)  // B is read through its (column id, value) pairs
-      return rank_num_t<PairedB<SR>>(fixed, op, rows, nrows, cw, NC, max_chunks, pchunk, rcnt, hash_max_nnz,
+      return rank_num_t<PairedB<SR>>(fixed, op, rows, nrows, rb, re, cw, NC, max_chunks, pchunk, rcnt, hash_max_nnz,
                                      dense_div, wlog2, P, nt, short_seg, keep_store, keep_slot, keep_nwords,
                                      c_ptr, c_idx, c_val, s);
-    return rank_num_launch<SR>(fixed, op, rows, nrows, cw, NC, max_chunks, pchunk, rcnt, hash_max_nnz,
+    return rank_num_launch<SR>(fixed, op, rows, nrows, rb, re, cw, NC, max_chunks, pchunk, rcnt, hash_max_nnz,
                                dense_div, wlog2, P, nt, short_seg, keep_store, keep_slot, keep_nwords, c_ptr,
                                c_idx, c_val, s);
   } else {
-    return rank_num_launch<SR>(fixed, op, rows, nrows, cw, NC, max_chunks, pchunk, rcnt, hash_max_nnz,
+    return rank_num_launch<SR>(fixed, op, rows, nrows, rb, re, cw, NC, max_chunks, pchunk, rcnt, hash_max_nnz,
                                dense_div, wlog2, P, nt, short_seg, keep_store, keep_slot, keep_nwords, c_ptr,
                                c_idx, c_val, s);
   }
@@ -1666,12 +1672,13 @@ hipError_t launch_dense_num(int sr, const Operands& op, const int32_t* rows, int
                s)
 }
 
-hipError_t launch_rank_num(int sr, bool fixed, const Operands& op, const int32_t* rows, int64_t nrows, int cw, int NC,
+hipError_t launch_rank_num(int sr, bool fixed, const Operands& op, const int32_t* rows, int64_t nrows, int32_t rb,
+                           int32_t re, int cw, int NC,
                            int max_chunks, const int32_t* pchunk, const int32_t* rcnt, int64_t hash_max_nnz,
                            int dense_div, int wlog2, int P, int nt, int short_seg, const uint32_t* keep_store,
                            const int32_t* keep_slot, int64_t keep_nwords, const int64_t* c_ptr,
                            int32_t* c_idx, void* c_val, hipStream_t s) {
-  SPG_DISPATCH(sr, rank_num_t, fixed, op, rows, nrows, cw, NC, max_chunks, pchunk, rcnt, hash_max_nnz, dense_div,
+  SPG_DISPATCH(sr, rank_num_t, fixed, op, rows, nrows, rb, re, cw, NC, max_chunks, pchunk, rcnt, hash_max_nnz, dense_div,
                wlog2, P, nt, short_seg, keep_store, keep_slot, keep_nwords, c_ptr, c_idx, c_val, s)
 }
 

@@ -96,10 +96,11 @@ hipError_t launch_validate(const int64_t* ptr, const int32_t* idx, int64_t nmajo
                            int32_t nminor, int* err, hipStream_t s);
 hipError_t launch_flops_bin(const Operands& op, BinParams bp, int64_t* flops, int64_t* c_ptr,
                             unsigned long long* counts, unsigned long long* total, hipStream_t s);
-hipError_t launch_count_num_bins(int32_t m, const int64_t* flops, const int64_t* c_ptr, BinParams bp,
-                                 unsigned long long* counts, hipStream_t s);
-// mode 0: bins by flops; mode 1: bins by nnz = c_ptr[i+1]-c_ptr[i] (scanned)
-hipError_t launch_scatter(int mode, int32_t m, const int64_t* flops, const int64_t* c_ptr,
+// Rows [r0, m); scanned: c_ptr holds offsets (else c_ptr[i+1] is row i's nnz).
+hipError_t launch_count_num_bins(int32_t m, int32_t r0, int scanned, const int64_t* flops, const int64_t* c_ptr,
+                                 BinParams bp, unsigned long long* counts, hipStream_t s);
+// Rows [r0, m).  mode 0: bins by flops; mode 1: bins by nnz = c_ptr[i+1]-c_ptr[i] (scanned)
+hipError_t launch_scatter(int mode, int32_t m, int32_t r0, const int64_t* flops, const int64_t* c_ptr,
                           BinParams bp, const BinOffsets& offs, unsigned long long* cursors,
                           int32_t* rows_out, hipStream_t s);
 hipError_t launch_panel_index(const int64_t* b_ptr, const int32_t* b_idx, int32_t nrows, int wlog2,
@@ -148,12 +149,13 @@ hipError_t launch_dense_num(int sr, const Operands& op, const int32_t* rows, int
                             const int64_t* c_ptr, int32_t* c_idx, void* c_val, hipStream_t s);
 // Heavy valued rows (the dense symbolic list, slot order) through rank-compressed
 // panels: chunks of 2^cw columns, rcnt[slot*NC + c] entries per chunk, pchunk
-// the chunk index of B.  fixed: only the rows with nnz*dense_div >= k, by
+// the chunk index of B; only rows in [rb, re).  fixed: only the rows with nnz*dense_div >= k, by
 // fixed panels of 2^wlog2 columns (P of them) over the same index; otherwise
 // only the other rows.  Rows with a kept symbolic
 // bitmap (keep_slot[row] >= 0, slots of keep_nwords words in keep_store) read
 // their pattern from it.
-hipError_t launch_rank_num(int sr, bool fixed, const Operands& op, const int32_t* rows, int64_t nrows, int cw, int NC,
+hipError_t launch_rank_num(int sr, bool fixed, const Operands& op, const int32_t* rows, int64_t nrows, int32_t rb,
+                           int32_t re, int cw, int NC,
                            int max_chunks, const int32_t* pchunk, const int32_t* rcnt, int64_t hash_max_nnz,
                            int dense_div, int wlog2, int P, int nt, int short_seg, const uint32_t* keep_store,
                            const int32_t* keep_slot, int64_t keep_nwords, const int64_t* c_ptr,

@@ -8,6 +8,7 @@ from __future__ import annotations
 import dataclasses
 from typing import Optional
 
+import numpy as np
 import torch
 
 from . import binding as B_
@@ -89,6 +90,28 @@ class Product:
         B_.spg_numeric(self.plan, self.ws, c_idx, c_val)
         return DeviceMatrix(self.out_rows, self.out_cols, self.A.layout, self.c_ptr, c_idx, c_val)
 
+    def numeric_rows(self, row_begin: int, row_end: int, c_idx: Optional[torch.Tensor] = None,
+                     c_val: Optional[torch.Tensor] = None) -> DeviceMatrix:
+        """Output slices [row_begin, row_end) only, into buffers sized for
+        that range; returns them as a matrix of row_end - row_begin slices."""
+        dev = self.A.ptr.device
+        ends = self.c_ptr[[row_begin, row_end]].cpu()
+        nnz = int(ends[1] - ends[0])
+        if c_idx is None:
+            c_idx = torch.empty(nnz, dtype=torch.int32, device=dev)
+        if c_val is None and not self.pattern_only():
+            c_val = torch.empty(nnz, dtype=OUT_DTYPE[self.semiring], device=dev)
+        B_.spg_numeric_rows(self.plan, self.ws, row_begin, row_end, c_idx, c_val)
+        ptr = self.c_ptr[row_begin:row_end + 1] - ends[0].to(dev)
+        k = row_end - row_begin
+        rows, cols = (k, self.out_cols) if self.A.layout == "csr" else (self.out_rows, k)
+        return DeviceMatrix(rows, cols, self.A.layout, ptr, c_idx[:nnz], None if c_val is None else c_val[:nnz])
+
+    def row_batches(self, max_nnz: int):
+        """Slice ranges whose outputs hold at most max_nnz entries each (a
+        slice larger than that gets a range of its own), from c_ptr."""
+        return row_batches(self.c_ptr.cpu().numpy(), max_nnz)
+
     def stats(self):
         return B_.spg_plan_stats(self.plan)
 
@@ -118,6 +141,23 @@ class Product:
             self.close()
         except Exception:
             pass
+
+
+def row_batches(c_ptr, max_nnz: int):
+    """Greedy split of slices 0..len(c_ptr)-2 into consecutive ranges
+    [rb, re) with c_ptr[re] - c_ptr[rb] <= max_nnz, or a single slice when
+    that slice alone is larger; every slice is in exactly one range."""
+    c_ptr = np.asarray(c_ptr, dtype=np.int64)
+    m = c_ptr.size - 1
+    if max_nnz < 1:
+        raise ValueError("max_nnz must be positive")
+    out, rb = [], 0
+    while rb < m:
+        re = int(np.searchsorted(c_ptr, c_ptr[rb] + max_nnz, side="right")) - 1
+        re = min(max(re, rb + 1), m)
+        out.append((rb, re))
+        rb = re
+    return out
 
 
 def inflate_f32(C: DeviceMatrix, r: float, in_place: bool = True, stream=None) -> DeviceMatrix:
