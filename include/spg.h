@@ -235,7 +235,8 @@ spg_status spg_numeric(spg_plan* plan, void* ws, int32_t* c_idx, void* c_val);
  * the range and one device-to-host copy, which synchronise the stream); the
  * kernels then run asynchronously.  A plan and its workspace run one range
  * at a time; calls on one stream are ordered.  spg_numeric afterwards
- * re-bins the whole product by itself.
+ * re-bins the whole product by itself; in between, spg_plan_bins reports the
+ * numeric classes of the last range.
  * Errors: SPG_E_INVALID (range outside [0, nslices], row_end < row_begin,
  * NULL outputs for a non-empty range), SPG_E_STATE (no symbolic phase yet,
  * or a plan with options.split_panels = 1 and a range that is not the whole

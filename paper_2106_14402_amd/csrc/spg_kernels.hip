@@ -1807,7 +1807,10 @@ __global__ void k_inflate(const int64_t* __restrict__ ptr, const float* val, int
   double sum = 0.0;
   for (int64_t p = lo + lane; p < hi; p += kWave) sum += static_cast<double>(powf(val[p], r));
   sum = wave_sum(sum);
-  if (sum == 0.0) return;
+  if (sum == 0.0) {  // the slice is left as it is
+    for (int64_t p = lo + lane; p < hi; p += kWave) val_out[p] = val[p];
+    return;
+  }
   const double inv = 1.0 / sum;
   for (int64_t p = lo + lane; p < hi; p += kWave)
     val_out[p] = static_cast<float>(static_cast<double>(powf(val[p], r)) * inv);

@@ -53,3 +53,26 @@ def test_mcl_iteration():
     sums = cs[Ph.ptr[1:]] - cs[Ph.ptr[:-1]]
     nonempty = np.diff(Ph.ptr) > 0
     assert np.all(np.abs(sums[nonempty] - 1.0) < 1e-5)
+
+
+@pytest.mark.parametrize("in_place", [False, True])
+def test_inflation_zero_and_empty_slices(in_place):
+    """Slices whose values are all zero are left as they are (also into a
+    separate output buffer); empty slices stay empty; the others sum to 1."""
+    import torch
+
+    from paper_2106_14402_amd import spgemm as S
+    ptr = np.array([0, 3, 3, 5, 6, 6], np.int64)
+    idx = np.array([0, 2, 5, 1, 4, 3], np.int32)
+    val = np.array([0.0, 0.0, 0.0, 1.0, 3.0, 0.0], np.float32)
+    M = spgen.SparseMatrix(6, 5, "csc", ptr, idx, val)
+    d = S.to_device(M)
+    before = d.val.clone()
+    out = S.inflate_f32(d, 2.0, in_place=in_place)
+    torch.cuda.synchronize()
+    got = out.val.cpu().numpy().astype(np.float64)
+    want = oracle.inflate(M, 2.0)
+    assert np.array_equal(want, [0.0, 0.0, 0.0, 0.1, 0.9, 0.0])
+    assert np.all(np.abs(got - want) <= 1e-6 * want)
+    if not in_place:
+        assert torch.equal(d.val, before)
