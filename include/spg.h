@@ -299,6 +299,10 @@ spg_status spg_plan_set_panels(spg_plan* plan, int which, const void* pidx, int 
  *   new_nnz    host, receives the kept count (synchronises the stream)
  *   new_idx/new_val  device outputs of new_nnz entries */
 spg_status spg_prune_workspace_size(const spg_matrix* C, size_t* bytes);
+spg_status spg_prune_count_f32(const spg_matrix* C, float thresh, void* ws, void* stream,
+                               int64_t* new_ptr, int64_t* new_nnz);
+spg_status spg_prune_apply_f32(const spg_matrix* C, float thresh, void* ws, void* stream,
+                               const int64_t* new_ptr, int32_t* new_idx, float* new_val);
 
 /* Inflation (the Markov-clustering step after pruning, paper Sec. 7.5: the
  * HipMCL iteration is expansion, pruning, inflation): every slice's values
@@ -308,14 +312,11 @@ spg_status spg_prune_workspace_size(const spg_matrix* C, size_t* bytes);
  *   r        inflation exponent, > 0
  *   val_out  device float[nnz]: the new values in C's entry order; may be
  *            C->val itself (in place).  Slices whose powers sum to 0 are left
- *            as they are.  The sum is taken in float64.
+ *            as they are (copied to val_out).  Powers in float32, their sum
+ *            in float64.
  * Enqueues one kernel on `stream` and returns.
  * Errors: SPG_E_INVALID for r <= 0 or missing values. */
 spg_status spg_inflate_f32(const spg_matrix* C, float r, float* val_out, void* stream);
-spg_status spg_prune_count_f32(const spg_matrix* C, float thresh, void* ws, void* stream,
-                               int64_t* new_ptr, int64_t* new_nnz);
-spg_status spg_prune_apply_f32(const spg_matrix* C, float thresh, void* ws, void* stream,
-                               const int64_t* new_ptr, int32_t* new_idx, float* new_val);
 
 /* ------------------------------------------------------------------------
  * Batched products: nprod independent products C_b = A_b (x).(+) B_b, such

@@ -638,14 +638,16 @@ __device__ __forceinline__ void wave_sync() {
 
 // Numeric phase of a pattern-only row whose bitmap the symbolic phase kept.
 // The row is taken in slabs of nw * 64 * kExpandWords words.  In a slab each
-// wave owns a contiguous range of at most 64 * kExpandWords words, read once
-// into registers (lane l has words l, l+64, ...); one block scan of the wave
-// totals places the ranges.  Then, 64 words at a time, the lanes put the
-// column ids of their words in order into the wave's LDS staging area and
-// the wave writes the staged ids out with consecutive lanes on consecutive
-// slots.
+// wave owns a contiguous range of at most 64 * kExpandWords words, read into
+// registers (lane l has words l, l+64, ...) while the previous slab is being
+// expanded; one block scan of the wave totals places the ranges.  Then, 64
+// words at a time, the lanes put the column ids of their words in order into
+// the wave's LDS staging area, at the same offset modulo 4 as their place in
+// c_idx, and the wave writes the staged ids out with consecutive lanes on
+// consecutive 16-byte groups (single ids at the unaligned ends).
 constexpr int kExpandWords = 16;
 constexpr int kExpandThreads = 1024;
+constexpr int kExpandStage = kWave * 32 + 4;  // ids of 64 words, plus the alignment offset
 
 __global__ __launch_bounds__(kExpandThreads) void k_expand_rows(const int32_t* __restrict__ rows, int64_t nrows,
                                                                 int nwords, int64_t stride,
@@ -658,29 +660,50 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand_rows(const int32_t* _
   const int lane = threadIdx.x & (kWave - 1);
   const int wid = threadIdx.x >> 6;
   const int nw = blockDim.x >> 6;
-  int32_t* stage = reinterpret_cast<int32_t*>(smem + 256) + wid * (kWave * 32);
+  int32_t* stage = reinterpret_cast<int32_t*>(smem + 256) + wid * kExpandStage;
   const int slab = nw * kWave * kExpandWords;
+  // words of this wave in the slab starting at s0: [w_begin, w_end)
+  auto range = [&](int s0, int& w_begin, int& w_end) {
+    const int s1 = min(nwords, s0 + slab);
+    const int wpw = (((s1 - s0 + nw - 1) / nw) + kWave - 1) & ~(kWave - 1);
+    w_begin = min(s1, s0 + wid * wpw);
+    w_end = min(s1, w_begin + wpw);
+  };
   for (int64_t it = blockIdx.x; it < nrows; it += gridDim.x) {
     const int32_t row = uniform(rows[it]);
     const uint32_t* src = store + static_cast<int64_t>(row_slot[row]) * stride;
     const int64_t out_end = c_ptr[row + 1];
     int64_t o_slab = c_ptr[row];
-    for (int s0 = 0; s0 < nwords; s0 += slab) {
-      const int s1 = min(nwords, s0 + slab);
-      const int wpw = (((s1 - s0 + nw - 1) / nw) + kWave - 1) & ~(kWave - 1);
-      const int w_begin = min(s1, s0 + wid * wpw);
-      const int w_end = min(s1, w_begin + wpw);
-      uint32_t wr[kExpandWords];
-      int cnt = 0;
+    uint32_t wr[kExpandWords];
+    {
+      int wb, we;
+      range(0, wb, we);
 #pragma unroll
       for (int j = 0; j < kExpandWords; ++j) {
-        const int w = w_begin + j * kWave + lane;
-        wr[j] = w < w_end ? src[w] : 0u;
-        cnt += __popc(wr[j]);
+        const int w = wb + j * kWave + lane;
+        wr[j] = w < we ? src[w] : 0u;
       }
+    }
+    for (int s0 = 0; s0 < nwords; s0 += slab) {
+      int w_begin, w_end;
+      range(s0, w_begin, w_end);
+      int cnt = 0;
+#pragma unroll
+      for (int j = 0; j < kExpandWords; ++j) cnt += __popc(wr[j]);
       cnt = wave_sum(cnt);
       int ptotal;
       const int woff = __shfl(block_exclusive_scan(lane == 0 ? cnt : 0, tmp, &ptotal), 0, kWave);
+      // the next slab's words, in flight while this one is expanded
+      uint32_t wn[kExpandWords];
+      {
+        int wb = 0, we = 0;
+        if (s0 + slab < nwords) range(s0 + slab, wb, we);
+#pragma unroll
+        for (int j = 0; j < kExpandWords; ++j) {
+          const int w = wb + j * kWave + lane;
+          wn[j] = w < we ? src[w] : 0u;
+        }
+      }
       int64_t o = o_slab + woff;
 #pragma unroll
       for (int j = 0; j < kExpandWords; ++j) {
@@ -689,20 +712,37 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand_rows(const int32_t* _
           const int c = __popc(word);
           const int incl = wave_inclusive_scan(c);
           const int T = __shfl(incl, kWave - 1, kWave);
-          int q = incl - c;
+          // stage index a + t holds the id bound for c_idx[o + t]
+          const int a = static_cast<int>((reinterpret_cast<uintptr_t>(c_idx + o) >> 2) & 3);
+          int q = a + incl - c;
           uint32_t x = word;
           const int col0 = (w_begin + j * kWave + lane) << 5;
-          while (x) {
-            stage[q++] = col0 + __ffs(x) - 1;
-            x &= x - 1;
+          while (x) {  // two ids per step
+            const uint32_t y = x & (x - 1);
+            stage[q] = col0 + __ffs(x) - 1;
+            if (y) stage[q + 1] = col0 + __ffs(y) - 1;
+            x = y & (y - 1);
+            q += 2;
           }
           wave_sync();
-          for (int t = lane; t < T; t += kWave)
-            if (o + t < out_end) c_idx[o + t] = stage[t];
+          const int L = a + static_cast<int>(max<int64_t>(0, min<int64_t>(T, out_end - o)));
+          const int vb = (a + 3) >> 2;                // first whole group of 4
+          const int ve = max(vb, L >> 2);             // past the last whole group
+          int32_t* dst = c_idx + o - a;               // 16-byte aligned
+          if (lane < 4) {
+            const int h = a + lane;                   // head: stage [a, min(4 vb, L))
+            if (h < min(4 * vb, L)) dst[h] = stage[h];
+            const int t = 4 * ve + lane;              // tail: stage [4 ve, L)
+            if (t < L) dst[t] = stage[t];
+          }
+          for (int v = vb + lane; v < ve; v += kWave)
+            reinterpret_cast<int4*>(dst)[v] = reinterpret_cast<const int4*>(stage)[v];
           wave_sync();
           o += T;
         }
       }
+#pragma unroll
+      for (int j = 0; j < kExpandWords; ++j) wr[j] = wn[j];
       o_slab += ptotal;
       __syncthreads();  // tmp is reused by the next scan
     }
@@ -714,7 +754,7 @@ hipError_t launch_expand_rows(const int32_t* rows, int64_t nrows, int nwords, in
                               hipStream_t s) {
   if (nrows <= 0) return hipSuccess;
   (void)nt;
-  const size_t lds = 256 + static_cast<size_t>(kExpandThreads / kWave) * kWave * 32 * sizeof(int32_t);
+  const size_t lds = 256 + static_cast<size_t>(kExpandThreads / kWave) * kExpandStage * sizeof(int32_t);
   hipLaunchKernelGGL(k_expand_rows, dim3(grid_for(nrows, 0)), dim3(kExpandThreads), lds, s, rows, nrows, nwords,
                      stride, store, row_slot, c_ptr, c_idx);
   return hipGetLastError();

@@ -107,6 +107,21 @@ def test_pattern_only_kept_bitmaps(mib):
     assert_parity(A, A, "or_and_bool", got)
 
 
+def test_pattern_only_kept_bitmaps_wide():
+    """Kept bitmaps wider than one expansion slab (600,000 columns = 18,750
+    words, more than the 16,384 words a slab holds): the second slab is read
+    while the first is expanded; rows of uneven lengths put the outputs at
+    every alignment."""
+    rng = np.random.default_rng(21)
+    m, n, k = 160, 3000, 600000
+    A = spgen.from_pairs(m, n, *spgen.distinct_minor(m, n, rng.integers(40, 160, size=m), rng), None,
+                         "csr", presorted=True)
+    B = spgen.from_pairs(n, k, *spgen.distinct_minor(n, k, rng.integers(150, 450, size=n), rng), None,
+                         "csr", presorted=True)
+    got = run_gpu(A, B, "or_and_bool", opts(bitmap_mib=64, hash_max_flops=64))
+    assert_parity(A, B, "or_and_bool", got)
+
+
 def test_bool_one_side_null():
     rng = np.random.default_rng(7)
     A = _skewed(3000, 8, 7)
