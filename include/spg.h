@@ -146,7 +146,11 @@ typedef struct spg_options {
   int32_t rank_dense_div;  /* rows with nnz * rank_dense_div >= columns of C
                               keep fixed-width panels (default 1: only full
                               rows) */
-  int32_t reserved[3];
+  int32_t rank_wide_div;   /* heavy valued rows with nnz * rank_wide_div >= columns
+                              of C (and below the fixed-panel rows) take rank
+                              passes with twice the value slots over fewer
+                              chunks, in the same launch (default 3; -1: off) */
+  int32_t reserved[2];
 } spg_options;
 
 /* Phases reported by spg_plan_timings, in milliseconds. */

@@ -149,19 +149,20 @@ hipError_t launch_dense_num(int sr, const Operands& op, const int32_t* rows, int
                             const int64_t* c_ptr, int32_t* c_idx, void* c_val, hipStream_t s);
 // Heavy valued rows (the dense symbolic list, slot order) through rank-compressed
 // panels: chunks of 2^cw columns, rcnt[slot*NC + c] entries per chunk, pchunk
-// the chunk index of B; only rows in [rb, re).  fixed: only the rows with nnz*dense_div >= k, by
-// fixed panels of 2^wlog2 columns (P of them) over the same index; otherwise
-// only the other rows.  Rows with a kept symbolic
-// bitmap (keep_slot[row] >= 0, slots of keep_nwords words in keep_store) read
-// their pattern from it.
+// the chunk index of B; only rows in [rb, re) with nnz in [nnz_lo, nnz_hi).
+// fixed: by fixed panels of 2^wlog2 columns (P of them) over the same index;
+// otherwise by passes of at most max_chunks chunks and 2^cw value slots, or,
+// for rows of at least wide_lo entries, of at most max_chunks_wide chunks and
+// 2^(cw+1) slots.  Rows with a kept symbolic bitmap (keep_slot[row] >= 0,
+// slots of keep_nwords words in keep_store) read their pattern from it.
 hipError_t launch_rank_num(int sr, bool fixed, const Operands& op, const int32_t* rows, int64_t nrows, int32_t rb,
-                           int32_t re, int cw, int NC,
-                           int max_chunks, const int32_t* pchunk, const int32_t* rcnt, int64_t hash_max_nnz,
-                           int dense_div, int wlog2, int P, int nt, int short_seg, const uint32_t* keep_store,
+                           int32_t re, int cw, int NC, int max_chunks, int64_t wide_lo, int max_chunks_wide,
+                           const int32_t* pchunk, const int32_t* rcnt, int64_t nnz_lo,
+                           int64_t nnz_hi, int wlog2, int P, int nt, int short_seg, const uint32_t* keep_store,
                            const int32_t* keep_slot, int64_t keep_nwords, const int64_t* c_ptr,
                            int32_t* c_idx, void* c_val, hipStream_t s);
-size_t rank_num_lds(int sr, int cw, int max_chunks, int wlog2, int nt);
-size_t rank_pass_lds(int sr, int cw, int max_chunks, int nt);  // the rank passes alone
+size_t rank_num_lds(int sr, int cw, int cs, int max_chunks, int wlog2, int nt);
+size_t rank_pass_lds(int sr, int cw, int cs, int max_chunks, int nt);  // the rank passes alone
 hipError_t launch_hash_sym_b(const BatchDesc* descs, const int64_t* row_off, int nprod,
                              const int32_t* items, int64_t nitems, int T, int nt, int short_seg,
                              int64_t grid_cap, hipStream_t s);

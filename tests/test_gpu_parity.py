@@ -45,13 +45,14 @@ def test_skewed_rmat_default_bins(sr):
 @pytest.mark.parametrize("mode", ["all_dense", "many_panels", "many_panels_in_sequence",
                                   "many_panels_rewalk", "windows", "all_hash_small_threads",
                                   "rank_small_slots", "rank_all", "rank_kept_bitmaps",
-                                  "rank_fixed_via_chunks"])
+                                  "rank_fixed_via_chunks", "rank_wide", "rank_wide_kept", "rank_narrow_only"])
 def test_forced_paths(sr, mode):
     """The same product through forced accumulators: every row dense; dense
     with many narrow panels (panel index in use), as (row, panel) pieces or
     panel after panel in one workgroup; short segments split; rank-compressed
     passes with few value slots (rows over several passes, by slot count and
-    by bitmap width), and fixed panels taken over the chunk index."""
+    by bitmap width), passes with twice the slots for the densest rows, and
+    fixed panels taken over the chunk index."""
     A = with_semiring_values(_skewed(5000, 10, 4), sr, np.random.default_rng(5))
     o = {"all_dense": opts(hash_max_flops=32, hash_max_nnz=32),
          "many_panels": opts(hash_max_flops=32, hash_max_nnz=32, sym_panel_log2=8, lds_budget=1024,
@@ -65,6 +66,11 @@ def test_forced_paths(sr, mode):
          "rank_all": opts(hash_max_flops=64, hash_max_nnz=64, lds_budget=8192, rank_dense_div=1),
          "rank_kept_bitmaps": opts(hash_max_flops=32, hash_max_nnz=32, lds_budget=1024, dense_threads=256,
                                    bitmap_mib=1),
+         # rows at least 1/4 dense take passes with twice the slots
+         "rank_wide": opts(hash_max_flops=64, hash_max_nnz=64, lds_budget=8192, rank_wide_div=4),
+         "rank_wide_kept": opts(hash_max_flops=32, hash_max_nnz=32, lds_budget=1024, dense_threads=256,
+                                bitmap_mib=1, rank_wide_div=8),
+         "rank_narrow_only": opts(hash_max_flops=64, hash_max_nnz=64, lds_budget=8192, rank_wide_div=-1),
          "rank_fixed_via_chunks": opts(hash_max_flops=32, hash_max_nnz=32, sym_panel_log2=8, lds_budget=1024,
                                        rank_dense_div=100000),
          # no room for segment lists: pieces re-walk their rows
