@@ -149,7 +149,7 @@ typedef struct spg_options {
   int32_t rank_wide_div;   /* heavy valued rows with nnz * rank_wide_div >= columns
                               of C (and below the fixed-panel rows) take rank
                               passes with twice the value slots over fewer
-                              chunks, in the same launch (default 3; -1: off) */
+                              chunks, in the same launch (default 4; -1: off) */
   int32_t reserved[2];
 } spg_options;
 

@@ -133,7 +133,7 @@ void resolve_options(const spg_options* in, spg_options* o, int sr) {
   if (o->lds_budget <= 0) o->lds_budget = 131072;
   if (o->seg_mib <= 0) o->seg_mib = 16384;
   if (o->rank_dense_div <= 0) o->rank_dense_div = 1;
-  if (o->rank_wide_div == 0) o->rank_wide_div = 3;
+  if (o->rank_wide_div == 0) o->rank_wide_div = 4;
 }
 
 spg_status check_options(const spg_options& o, int sr) {
@@ -221,7 +221,7 @@ static spg_status plan_init(spg_plan* p, const spg_options* opt_in) {
     int maxw = 64;
     while (maxw > 0 && rank_pass_lds(p->sr, cw, cw + 1, maxw, nt) + 1024 > static_cast<size_t>(max_lds_bytes())) --maxw;
     const int64_t NC = (kk + (int64_t(1) << cw) - 1) >> cw;
-    if (cw >= 5 && cw <= p->sym_wlog2 &&
+    if (cw >= 6 && cw <= p->sym_wlog2 &&
         rank_num_lds(p->sr, cw, cw, maxc, p->num_wlog2, nt) <= static_cast<size_t>(max_lds_bytes()) &&
         static_cast<int64_t>(p->op.m) * NC < (int64_t(1) << 31) && NC < (int64_t(1) << 24)) {
       p->rank = true;

@@ -1154,16 +1154,17 @@ __global__ __launch_bounds__(1024) void k_dense_num(Operands op, const int32_t* 
 // Rows dense enough that fixed panels need fewer passes use fixed panels over
 // the same chunk index.
 // ---------------------------------------------------------------------------
+// The bitmap is read in 64-bit words, each with the rank of its first bit.
 template <class SR>
 struct RankSink {
   using S = typename SR::S;
-  const uint32_t* bits;
+  const uint64_t* bits;
   const uint16_t* pre;
   S* vals;
   __device__ void add(int32_t c, S v) {
-    const int w = c >> 5;
-    const uint32_t below = bits[w] & ((1u << (c & 31)) - 1u);
-    SR::combine(&vals[pre[w] + __popc(below)], v);
+    const int w = c >> 6;
+    const uint64_t below = bits[w] & ((1ull << (c & 63)) - 1ull);
+    SR::combine(&vals[pre[w] + __popcll(below)], v);
   }
 };
 
@@ -1176,8 +1177,8 @@ __host__ __device__ inline size_t rank_queue_bytes(int nt) {
 
 template <class SR>
 __host__ __device__ inline size_t rank_num_lds_bytes(int cw, int cs, int max_chunks, int nt) {
-  const size_t cols = static_cast<size_t>(max_chunks) << cw;
-  return rank_queue_bytes<SR>(nt) + (sizeof(typename SR::S) << cs) + cols / 8 + (cols / 32) * 2;
+  const size_t cols = static_cast<size_t>(max_chunks) << cw;  // a multiple of 64 (cw >= 6)
+  return rank_queue_bytes<SR>(nt) + (sizeof(typename SR::S) << cs) + cols / 8 + (cols / 64) * 2;
 }
 
 template <class SR>
@@ -1223,33 +1224,36 @@ __device__ void rank_num_row(const Operands& op, int64_t a_lo, int64_t a_hi, int
       const int32_t C0 = c_lo << cw;
       const int32_t wcols = min(n << cw, op.k - C0);
       const int nwords = (wcols + 31) >> 5;
+      const int nw64 = (nwords + 1) >> 1;
+      const uint64_t* bits64 = reinterpret_cast<const uint64_t*>(bits);
       for (int t = tid; t < total; t += nt) vals[t] = SR::identity();
       // 1. pattern of the column range: from the kept bitmap, or by a walk
-      //    over B's column ids
+      //    over B's column ids; an odd word count gets a zero word after it
       if (keep) {
         load_words_lds<1>(bits, keep + (C0 >> 5), nwords);
+        if ((nwords & 1) && tid == 0) bits[nwords] = 0u;
         __syncthreads();
       } else {
-        for (int t = tid; t < nwords; t += nt) bits[t] = 0u;
+        for (int t = tid; t < 2 * nw64; t += nt) bits[t] = 0u;
         __syncthreads();
         BitmapSink bs{bits};
         RowSource<SrPattern> ps{&op, a_lo, a_hi, true, pchunk, NC, c_lo, c_hi};
         enumerate_src<SrPattern, 2>(op, ps, C0, short_seg, pq, bs);
       }
-      // 2. rank of the first entry of every bitmap word (contiguous words per thread)
-      const int wpt = (nwords + nt - 1) / nt;
-      const int w0 = min(nwords, tid * wpt), w1 = min(nwords, w0 + wpt);
+      // 2. rank of the first entry of every 64-bit word (contiguous words per thread)
+      const int wpt = (nw64 + nt - 1) / nt;
+      const int w0 = min(nw64, tid * wpt), w1 = min(nw64, w0 + wpt);
       int local = 0;
-      for (int w = w0; w < w1; ++w) local += __popc(bits[w]);
+      for (int w = w0; w < w1; ++w) local += __popcll(bits64[w]);
       int ptotal;
       int run = block_exclusive_scan(local, q.ctr + 2, &ptotal);
       for (int w = w0; w < w1; ++w) {
         pre[w] = static_cast<uint16_t>(run);
-        run += __popc(bits[w]);
+        run += __popcll(bits64[w]);
       }
       __syncthreads();
       // 3. values, combined at their ranks
-      RankSink<SR> rs{bits, pre, vals};
+      RankSink<SR> rs{bits64, pre, vals};
       RowSource<SR> vs{&op, a_lo, a_hi, true, pchunk, NC, c_lo, c_hi};
       enumerate_src<SR, 2>(op, vs, C0, short_seg, q, rs);
       // 4. write the range out: the values in slot order; then the column
@@ -1260,12 +1264,12 @@ __device__ void rank_num_row(const Operands& op, int64_t a_lo, int64_t a_hi, int
       for (int r = tid; r < lim; r += nt) st_stream(&c_val[out + r], SR::out(vals[r]));
       __syncthreads();
       int32_t* ids = reinterpret_cast<int32_t*>(vals);
-      for (int w = tid; w < nwords; w += nt) {
-        uint32_t x = bits[w];
+      for (int w = tid; w < nw64; w += nt) {
+        uint64_t x = bits64[w];
         int q = pre[w];
-        const int32_t col0 = C0 + (w << 5);
+        const int32_t col0 = C0 + (w << 6);
         while (x) {
-          ids[q++] = col0 + __ffs(x) - 1;
+          ids[q++] = col0 + __ffsll(static_cast<unsigned long long>(x)) - 1;
           x &= x - 1;
         }
       }
