@@ -146,10 +146,11 @@ typedef struct spg_options {
   int32_t rank_dense_div;  /* rows with nnz * rank_dense_div >= columns of C
                               keep fixed-width panels (default 1: only full
                               rows) */
-  int32_t rank_wide_div;   /* heavy valued rows with nnz * rank_wide_div >= columns
-                              of C (and below the fixed-panel rows) take rank
-                              passes with twice the value slots over fewer
-                              chunks, in the same launch (default 4; -1: off) */
+  int32_t rank_shapes;     /* pass shapes of the rank passes: 1 = the value
+                              slots of one chunk width (2^cw) with the widest
+                              bitmap; 2 to 5 add 1.25x, 1.5x, 1.75x and 2x the
+                              slots over fewer chunks; each row takes the
+                              shape that needs the fewest passes (default 5) */
   int32_t reserved[2];
 } spg_options;
 

@@ -63,7 +63,7 @@ class spg_options(ctypes.Structure):
         ("seg_mib", ctypes.c_int32),
         ("rank_panels", ctypes.c_int32),
         ("rank_dense_div", ctypes.c_int32),
-        ("rank_wide_div", ctypes.c_int32),
+        ("rank_shapes", ctypes.c_int32),
         ("reserved", ctypes.c_int32 * 2),
     ]
 

@@ -41,8 +41,8 @@ struct spg_plan {
   unsigned int keep_cap;
   size_t off_segoff, off_segs;   // (row, panel) segment lists
   bool rank;                     // heavy valued rows through rank-compressed panels
-  int rank_cw, rank_NC, rank_maxc;
-  int rank_maxc_wide;  // chunks per pass with twice the value slots (0: no such passes)
+  int rank_cw, rank_NC;
+  RankShapes rank_shapes;  // pass shapes of the rank kernel
   size_t off_rcnt, off_pchunk;
   bool pair;                     // rank passes read B through (column, value) pairs
   size_t off_bpair;
@@ -133,7 +133,7 @@ void resolve_options(const spg_options* in, spg_options* o, int sr) {
   if (o->lds_budget <= 0) o->lds_budget = 131072;
   if (o->seg_mib <= 0) o->seg_mib = 16384;
   if (o->rank_dense_div <= 0) o->rank_dense_div = 1;
-  if (o->rank_wide_div == 0) o->rank_wide_div = 4;
+  if (o->rank_shapes <= 0 || o->rank_shapes > kRankShapes) o->rank_shapes = kRankShapes;
 }
 
 spg_status check_options(const spg_options& o, int sr) {
@@ -200,35 +200,48 @@ static spg_status plan_init(spg_plan* p, const spg_options* opt_in) {
              static_cast<int64_t>(p->op.m) * p->num_P < (int64_t(1) << 31);
   p->bp.split_heavy = p->split ? 1 : 0;
 
-  // Rank-compressed panels: half the LDS budget, at most 64 KiB, of value
-  // slots (2^cw of them) per pass, chunks of 2^cw columns, and a bitmap of
-  // as many chunks as the rest of the LDS holds.
+  // Rank-compressed panels: chunks of 2^cw columns, with 2^cw value slots
+  // (half the LDS budget, at most 64 KiB) and a bitmap of as many chunks as
+  // the rest of the LDS holds; further shapes trade bitmap for 1.25x to 2x the
+  // slots, for rows whose entries rather than columns bound their passes.
   p->rank = false;
   p->rank_cw = 0;
   p->rank_NC = 0;
-  p->rank_maxc = 0;
-  p->rank_maxc_wide = 0;
+  p->rank_shapes = RankShapes{};
   if (p->opt.rank_panels >= 0 && sb > 0 && !p->split && p->num_P > 1) {
     const size_t vbytes = std::max<size_t>(1024, std::min<size_t>(65536, p->opt.lds_budget / 2));
     int cw = 5;
     while ((static_cast<size_t>(1) << (cw + 1)) * sb <= vbytes) ++cw;
     cw = std::min(cw, p->num_wlog2);
-    // the bitmap (and its per-word ranks) takes the rest of the LDS, up to
-    // 64 chunks, leaving 1 KiB for the kernel's own shared variables
-    int maxc = 64;
-    while (maxc > 1 && rank_pass_lds(p->sr, cw, cw, maxc, nt) + 1024 > static_cast<size_t>(max_lds_bytes())) --maxc;
-    // passes for rows dense enough to fill twice the slots over fewer chunks
-    int maxw = 64;
-    while (maxw > 0 && rank_pass_lds(p->sr, cw, cw + 1, maxw, nt) + 1024 > static_cast<size_t>(max_lds_bytes())) --maxw;
+    // chunks per pass for a slot count: up to 64, leaving 1 KiB for the
+    // kernel's own shared variables
+    auto chunks_for = [&](int slots) {
+      int c = 64;
+      while (c > 0 && rank_pass_lds(p->sr, cw, slots, c, nt) + 1024 > static_cast<size_t>(max_lds_bytes())) --c;
+      return c;
+    };
+    const int base = 1 << cw;
+    const int maxc = chunks_for(base);
     const int64_t NC = (kk + (int64_t(1) << cw) - 1) >> cw;
-    if (cw >= 6 && cw <= p->sym_wlog2 &&
-        rank_num_lds(p->sr, cw, cw, maxc, p->num_wlog2, nt) <= static_cast<size_t>(max_lds_bytes()) &&
+    if (cw >= 6 && cw <= p->sym_wlog2 && maxc >= 1 &&
+        rank_num_lds(p->sr, cw, base, maxc, p->num_wlog2, nt) <= static_cast<size_t>(max_lds_bytes()) &&
         static_cast<int64_t>(p->op.m) * NC < (int64_t(1) << 31) && NC < (int64_t(1) << 24)) {
       p->rank = true;
       p->rank_cw = cw;
       p->rank_NC = static_cast<int>(NC);
-      p->rank_maxc = maxc;
-      p->rank_maxc_wide = p->opt.rank_wide_div > 0 && maxw >= 2 ? maxw : 0;
+      RankShapes& sh = p->rank_shapes;
+      sh.n = 1;
+      sh.slots[0] = base;
+      sh.maxc[0] = maxc;
+      const int more[kRankShapes - 1] = {base + base / 4, base + base / 2, base + 3 * base / 4, 2 * base};
+      const int want = std::min(p->opt.rank_shapes, kRankShapes);
+      for (int j = 0; j < kRankShapes - 1 && sh.n < want; ++j) {
+        const int c = chunks_for(more[j]);
+        if (c < 2 || more[j] > 65536) break;  // ranks are 16-bit
+        sh.slots[sh.n] = more[j];
+        sh.maxc[sh.n] = c;
+        ++sh.n;
+      }
     }
   }
   p->bp.rank_heavy = p->rank ? 1 : 0;
@@ -803,17 +816,14 @@ static spg_status numeric_range(spg_plan* p, void* ws, int32_t rb, int32_t re, i
   const uint32_t* kstore = p->keep ? reinterpret_cast<const uint32_t*>(w + p->off_store) : nullptr;
   const int32_t* kslot = p->keep ? reinterpret_cast<const int32_t*>(w + p->off_rowslot) : nullptr;
   const int32_t* rcnt = reinterpret_cast<const int32_t*>(w + p->off_rcnt);
-  // Heavy rows by size: rank passes, with twice the slots from wide_lo
-  // entries (nnz * rank_wide_div >= k), and fixed panels from fixed_lo
+  // Heavy rows by size: rank passes, then fixed panels from fixed_lo entries
   // (nnz * rank_dense_div >= k).
   const int64_t kcols = op.k;
   const int64_t fixed_lo = std::max<int64_t>(p->bp.hash_max_nnz + 1,
                                              (kcols + p->opt.rank_dense_div - 1) / p->opt.rank_dense_div);
-  const int64_t wide_lo =
-      p->rank_maxc_wide > 0 ? (kcols + p->opt.rank_wide_div - 1) / p->opt.rank_wide_div : INT64_MAX;
   auto rank_launch = [&](bool fixed) {
     return launch_rank_num(p->sr, fixed, opr, rows_dense_sym, p->n_dense_sym, p->lists_rb, p->lists_re,
-                           p->rank_cw, p->rank_NC, p->rank_maxc, wide_lo, p->rank_maxc_wide, pchunk, rcnt,
+                           p->rank_cw, p->rank_NC, p->rank_shapes, pchunk, rcnt,
                            fixed ? fixed_lo : p->bp.hash_max_nnz + 1, fixed ? INT64_MAX : fixed_lo, p->num_wlog2,
                            p->num_P, p->opt.dense_threads, p->opt.short_seg, kstore, kslot, p->keep_stride,
                            p->c_ptr, c_idx, c_val, s);

@@ -1176,13 +1176,13 @@ __host__ __device__ inline size_t rank_queue_bytes(int nt) {
 }
 
 template <class SR>
-__host__ __device__ inline size_t rank_num_lds_bytes(int cw, int cs, int max_chunks, int nt) {
+__host__ __device__ inline size_t rank_num_lds_bytes(int cw, int slots, int max_chunks, int nt) {
   const size_t cols = static_cast<size_t>(max_chunks) << cw;  // a multiple of 64 (cw >= 6)
-  return rank_queue_bytes<SR>(nt) + (sizeof(typename SR::S) << cs) + cols / 8 + (cols / 64) * 2;
+  return rank_queue_bytes<SR>(nt) + sizeof(typename SR::S) * static_cast<size_t>(slots) + cols / 8 + (cols / 64) * 2;
 }
 
 template <class SR>
-__device__ void rank_num_row(const Operands& op, int64_t a_lo, int64_t a_hi, int cw, int cs, int NC,
+__device__ void rank_num_row(const Operands& op, int64_t a_lo, int64_t a_hi, int cw, int slots, int NC,
                              int max_chunks, const int32_t* __restrict__ pchunk,
                              const int32_t* __restrict__ cnt, const uint32_t* __restrict__ keep,
                              int short_seg, int64_t out, int64_t out_end,
@@ -1192,12 +1192,11 @@ __device__ void rank_num_row(const Operands& op, int64_t a_lo, int64_t a_hi, int
   const int nt = blockDim.x;
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
-  const int slots = 1 << cs;
   auto q = RowQueue<typename SR::In>::carve(smem, nt);
   auto pq = RowQueue<SrPattern::In>::carve(smem, nt);  // same LDS, used by the pattern walk
   unsigned char* p0 = smem + rank_queue_bytes<SR>(nt);
   S* vals = reinterpret_cast<S*>(p0);
-  uint32_t* bits = reinterpret_cast<uint32_t*>(p0 + (sizeof(S) << cs));
+  uint32_t* bits = reinterpret_cast<uint32_t*>(p0 + sizeof(S) * static_cast<size_t>(slots));
   uint16_t* pre = reinterpret_cast<uint16_t*>(bits + (static_cast<size_t>(max_chunks) << (cw - 5)));
   for (int c_lo = 0; c_lo < NC;) {
     if (tid < kWave) {
@@ -1287,7 +1286,7 @@ __device__ void rank_num_row(const Operands& op, int64_t a_lo, int64_t a_hi, int
 template <class SR, bool kFixed>
 __global__ __launch_bounds__(1024) void k_rank_num(Operands op, const int32_t* __restrict__ rows,
                                                    int64_t nrows, int32_t rb, int32_t re, int cw, int NC,
-                                                   int max_chunks, int64_t wide_lo, int max_chunks_wide,
+                                                   RankShapes sh,
                                                    const int32_t* __restrict__ pchunk,
                                                    const int32_t* __restrict__ rcnt, int64_t nnz_lo,
                                                    int64_t nnz_hi, int wlog2, int P, int short_seg,
@@ -1315,11 +1314,20 @@ __global__ __launch_bounds__(1024) void k_rank_num(Operands op, const int32_t* _
     } else {
       const int32_t slot = keep_slot ? uniform(keep_slot[row]) : -1;
       const uint32_t* keep = slot >= 0 ? keep_store + static_cast<int64_t>(slot) * keep_nwords : nullptr;
-      // rows with at least wide_lo entries: twice the slots over fewer chunks
-      const bool wide = nnz >= wide_lo;
-      rank_num_row<SR>(op, a_lo, a_hi, cw, wide ? cw + 1 : cw, NC, wide ? max_chunks_wide : max_chunks, pchunk,
-                       rcnt + it * NC, keep, short_seg, out,
-                       out_end, c_idx, c_val, smem, info);
+      // the pass shape with the fewest passes for a row spread over all
+      // chunks: max(chunks / chunks per pass, entries / slots)
+      int k = 0;
+      int64_t best = INT64_MAX;
+      for (int j = 0; j < sh.n; ++j) {
+        const int64_t pj = max(static_cast<int64_t>((NC + sh.maxc[j] - 1) / sh.maxc[j]),
+                               (nnz + sh.slots[j] - 1) / sh.slots[j]);
+        if (pj < best) {
+          best = pj;
+          k = j;
+        }
+      }
+      rank_num_row<SR>(op, a_lo, a_hi, cw, sh.slots[k], NC, sh.maxc[k], pchunk, rcnt + it * NC, keep, short_seg,
+                       out, out_end, c_idx, c_val, smem, info);
     }
   }
 }
@@ -1568,44 +1576,47 @@ static hipError_t dense_num_t(const Operands& op, const int32_t* rows, int64_t n
 }
 
 template <class SR>
-static size_t rank_num_lds_t(int cw, int cs, int max_chunks, int wlog2, int nt) {
-  const size_t a = rank_num_lds_bytes<SR>(cw, cs, max_chunks, nt);
+static size_t rank_num_lds_t(int cw, int slots, int max_chunks, int wlog2, int nt) {
+  const size_t a = rank_num_lds_bytes<SR>(cw, slots, max_chunks, nt);
   const size_t b = dense_num_lds_t<SR>(wlog2, nt);
   return a > b ? a : b;
 }
 
-// LDS of a rank launch: the larger of its two pass shapes.
+// LDS of a rank launch: the largest of its pass shapes.
 template <class SR>
-static size_t rank_launch_lds(int cw, int max_chunks, int max_chunks_wide, int nt) {
-  const size_t a = rank_num_lds_bytes<SR>(cw, cw, max_chunks, nt);
-  const size_t b = max_chunks_wide > 0 ? rank_num_lds_bytes<SR>(cw, cw + 1, max_chunks_wide, nt) : 0;
-  return a > b ? a : b;
+static size_t rank_launch_lds(int cw, const RankShapes& sh, int nt) {
+  size_t b = 0;
+  for (int j = 0; j < sh.n; ++j) {
+    const size_t a = rank_num_lds_bytes<SR>(cw, sh.slots[j], sh.maxc[j], nt);
+    b = a > b ? a : b;
+  }
+  return b;
 }
 
 template <class SR>
 static hipError_t rank_num_launch(bool fixed, const Operands& op, const int32_t* rows, int64_t nrows, int32_t rb,
-                                  int32_t re, int cw, int NC, int max_chunks, int64_t wide_lo, int max_chunks_wide,
+                                  int32_t re, int cw, int NC, const RankShapes& sh,
                                   const int32_t* pchunk, const int32_t* rcnt,
                                   int64_t nnz_lo, int64_t nnz_hi, int wlog2, int P, int nt, int short_seg,
                                   const uint32_t* keep_store, const int32_t* keep_slot, int64_t keep_nwords,
                                   const int64_t* c_ptr, int32_t* c_idx, void* c_val, hipStream_t s) {
   if (fixed)
     hipLaunchKernelGGL((k_rank_num<SR, true>), dim3(grid_for(nrows, 0)), dim3(nt), dense_num_lds_t<SR>(wlog2, nt),
-                       s, op, rows, nrows, rb, re, cw, NC, max_chunks, wide_lo, max_chunks_wide, pchunk, rcnt, nnz_lo,
+                       s, op, rows, nrows, rb, re, cw, NC, sh, pchunk, rcnt, nnz_lo,
                        nnz_hi, wlog2,
                        P, short_seg, keep_store, keep_slot, keep_nwords, c_ptr, c_idx,
                        static_cast<typename SR::Out*>(c_val));
   else
     hipLaunchKernelGGL((k_rank_num<SR, false>), dim3(grid_for(nrows, 0)), dim3(nt),
-                       rank_launch_lds<SR>(cw, max_chunks, max_chunks_wide, nt), s, op, rows, nrows, rb, re, cw, NC,
-                       max_chunks, wide_lo, max_chunks_wide, pchunk, rcnt, nnz_lo, nnz_hi, wlog2, P, short_seg, keep_store, keep_slot, keep_nwords, c_ptr,
+                       rank_launch_lds<SR>(cw, sh, nt), s, op, rows, nrows, rb, re, cw, NC,
+                       sh, pchunk, rcnt, nnz_lo, nnz_hi, wlog2, P, short_seg, keep_store, keep_slot, keep_nwords, c_ptr,
                        c_idx, static_cast<typename SR::Out*>(c_val));
   return hipGetLastError();
 }
 
 template <class SR>
 static hipError_t rank_num_t(bool fixed, const Operands& op, const int32_t* rows, int64_t nrows, int32_t rb,
-                             int32_t re, int cw, int NC, int max_chunks, int64_t wide_lo, int max_chunks_wide,
+                             int32_t re, int cw, int NC, const RankShapes& sh,
                              const int32_t* pchunk, const int32_t* rcnt, int64_t nnz_lo,
                              int64_t nnz_hi, int wlog2, int P, int nt, int short_seg, const uint32_t* keep_store,
                              const int32_t* keep_slot, int64_t keep_nwords, const int64_t* c_ptr,
@@ -1615,14 +1626,14 @@ static hipError_t rank_num_t(bool fixed, const Operands& op, const int32_t* rows
     return hipErrorInvalidValue;  // pattern-only rows use the bitmap paths
   } else if constexpr (sizeof(typename SR::In) == 4 && !IsPairedB<SR>::value) {
     if (op.b_pair)  // B is read through its (column id, value) pairs
-      return rank_num_t<PairedB<SR>>(fixed, op, rows, nrows, rb, re, cw, NC, max_chunks, wide_lo, max_chunks_wide, pchunk, rcnt, nnz_lo,
+      return rank_num_t<PairedB<SR>>(fixed, op, rows, nrows, rb, re, cw, NC, sh, pchunk, rcnt, nnz_lo,
                                      nnz_hi, wlog2, P, nt, short_seg, keep_store, keep_slot, keep_nwords,
                                      c_ptr, c_idx, c_val, s);
-    return rank_num_launch<SR>(fixed, op, rows, nrows, rb, re, cw, NC, max_chunks, wide_lo, max_chunks_wide, pchunk, rcnt, nnz_lo,
+    return rank_num_launch<SR>(fixed, op, rows, nrows, rb, re, cw, NC, sh, pchunk, rcnt, nnz_lo,
                                nnz_hi, wlog2, P, nt, short_seg, keep_store, keep_slot, keep_nwords, c_ptr,
                                c_idx, c_val, s);
   } else {
-    return rank_num_launch<SR>(fixed, op, rows, nrows, rb, re, cw, NC, max_chunks, wide_lo, max_chunks_wide, pchunk, rcnt, nnz_lo,
+    return rank_num_launch<SR>(fixed, op, rows, nrows, rb, re, cw, NC, sh, pchunk, rcnt, nnz_lo,
                                nnz_hi, wlog2, P, nt, short_seg, keep_store, keep_slot, keep_nwords, c_ptr,
                                c_idx, c_val, s);
   }
@@ -1728,12 +1739,12 @@ hipError_t launch_dense_num(int sr, const Operands& op, const int32_t* rows, int
 }
 
 hipError_t launch_rank_num(int sr, bool fixed, const Operands& op, const int32_t* rows, int64_t nrows, int32_t rb,
-                           int32_t re, int cw, int NC, int max_chunks, int64_t wide_lo, int max_chunks_wide,
+                           int32_t re, int cw, int NC, const RankShapes& sh,
                            const int32_t* pchunk, const int32_t* rcnt, int64_t nnz_lo,
                            int64_t nnz_hi, int wlog2, int P, int nt, int short_seg, const uint32_t* keep_store,
                            const int32_t* keep_slot, int64_t keep_nwords, const int64_t* c_ptr,
                            int32_t* c_idx, void* c_val, hipStream_t s) {
-  SPG_DISPATCH(sr, rank_num_t, fixed, op, rows, nrows, rb, re, cw, NC, max_chunks, wide_lo, max_chunks_wide, pchunk, rcnt, nnz_lo, nnz_hi,
+  SPG_DISPATCH(sr, rank_num_t, fixed, op, rows, nrows, rb, re, cw, NC, sh, pchunk, rcnt, nnz_lo, nnz_hi,
                wlog2, P, nt, short_seg, keep_store, keep_slot, keep_nwords, c_ptr, c_idx, c_val, s)
 }
 
@@ -1790,14 +1801,14 @@ size_t seg_desc_bytes() { return sizeof(SegDesc); }
 size_t hash_num_lds(int sr, int T, int nt) { SPG_DISPATCH(sr, hash_num_lds_t, T, nt) }
 size_t dense_num_lds(int sr, int wlog2, int nt) { SPG_DISPATCH(sr, dense_num_lds_t, wlog2, nt) }
 template <class SR>
-static size_t rank_pass_lds_t(int cw, int cs, int max_chunks, int nt) {
-  return rank_num_lds_bytes<SR>(cw, cs, max_chunks, nt);
+static size_t rank_pass_lds_t(int cw, int slots, int max_chunks, int nt) {
+  return rank_num_lds_bytes<SR>(cw, slots, max_chunks, nt);
 }
-size_t rank_pass_lds(int sr, int cw, int cs, int max_chunks, int nt) {
-  SPG_DISPATCH(sr, rank_pass_lds_t, cw, cs, max_chunks, nt)
+size_t rank_pass_lds(int sr, int cw, int slots, int max_chunks, int nt) {
+  SPG_DISPATCH(sr, rank_pass_lds_t, cw, slots, max_chunks, nt)
 }
-size_t rank_num_lds(int sr, int cw, int cs, int max_chunks, int wlog2, int nt) {
-  SPG_DISPATCH(sr, rank_num_lds_t, cw, cs, max_chunks, wlog2, nt)
+size_t rank_num_lds(int sr, int cw, int slots, int max_chunks, int wlog2, int nt) {
+  SPG_DISPATCH(sr, rank_num_lds_t, cw, slots, max_chunks, wlog2, nt)
 }
 
 template <class SR>

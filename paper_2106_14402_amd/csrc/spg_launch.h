@@ -22,6 +22,14 @@ struct BinParams {
 };
 constexpr int kExpandBin = 15;  // numeric bin of rows whose bitmap was kept
 
+// Pass shapes of the rank kernel: value slots and chunks per pass.
+constexpr int kRankShapes = 5;
+struct RankShapes {
+  int n;
+  int slots[kRankShapes];
+  int maxc[kRankShapes];
+};
+
 // Symbolic bitmaps kept for the numeric phase of pattern-only products.
 struct KeepBitmaps {
   uint32_t* store;           // capacity slots of nwords words; NULL: keep none
@@ -151,18 +159,18 @@ hipError_t launch_dense_num(int sr, const Operands& op, const int32_t* rows, int
 // panels: chunks of 2^cw columns, rcnt[slot*NC + c] entries per chunk, pchunk
 // the chunk index of B; only rows in [rb, re) with nnz in [nnz_lo, nnz_hi).
 // fixed: by fixed panels of 2^wlog2 columns (P of them) over the same index;
-// otherwise by passes of at most max_chunks chunks and 2^cw value slots, or,
-// for rows of at least wide_lo entries, of at most max_chunks_wide chunks and
-// 2^(cw+1) slots.  Rows with a kept symbolic bitmap (keep_slot[row] >= 0,
+// otherwise by passes of one of sh.n shapes (at most sh.maxc[j] chunks and
+// sh.slots[j] >= 2^cw value slots), each row taking the shape that needs the
+// fewest passes.  Rows with a kept symbolic bitmap (keep_slot[row] >= 0,
 // slots of keep_nwords words in keep_store) read their pattern from it.
 hipError_t launch_rank_num(int sr, bool fixed, const Operands& op, const int32_t* rows, int64_t nrows, int32_t rb,
-                           int32_t re, int cw, int NC, int max_chunks, int64_t wide_lo, int max_chunks_wide,
+                           int32_t re, int cw, int NC, const RankShapes& sh,
                            const int32_t* pchunk, const int32_t* rcnt, int64_t nnz_lo,
                            int64_t nnz_hi, int wlog2, int P, int nt, int short_seg, const uint32_t* keep_store,
                            const int32_t* keep_slot, int64_t keep_nwords, const int64_t* c_ptr,
                            int32_t* c_idx, void* c_val, hipStream_t s);
-size_t rank_num_lds(int sr, int cw, int cs, int max_chunks, int wlog2, int nt);
-size_t rank_pass_lds(int sr, int cw, int cs, int max_chunks, int nt);  // the rank passes alone
+size_t rank_num_lds(int sr, int cw, int slots, int max_chunks, int wlog2, int nt);
+size_t rank_pass_lds(int sr, int cw, int slots, int max_chunks, int nt);  // the rank passes alone
 hipError_t launch_hash_sym_b(const BatchDesc* descs, const int64_t* row_off, int nprod,
                              const int32_t* items, int64_t nitems, int T, int nt, int short_seg,
                              int64_t grid_cap, hipStream_t s);

@@ -67,10 +67,10 @@ def test_forced_paths(sr, mode):
          "rank_kept_bitmaps": opts(hash_max_flops=32, hash_max_nnz=32, lds_budget=1024, dense_threads=256,
                                    bitmap_mib=1),
          # rows at least 1/4 dense take passes with twice the slots
-         "rank_wide": opts(hash_max_flops=64, hash_max_nnz=64, lds_budget=8192, rank_wide_div=4),
+         "rank_wide": opts(hash_max_flops=64, hash_max_nnz=64, lds_budget=8192, rank_shapes=2),
          "rank_wide_kept": opts(hash_max_flops=32, hash_max_nnz=32, lds_budget=1024, dense_threads=256,
-                                bitmap_mib=1, rank_wide_div=8),
-         "rank_narrow_only": opts(hash_max_flops=64, hash_max_nnz=64, lds_budget=8192, rank_wide_div=-1),
+                                bitmap_mib=1, rank_shapes=3),
+         "rank_narrow_only": opts(hash_max_flops=64, hash_max_nnz=64, lds_budget=8192, rank_shapes=1),
          "rank_fixed_via_chunks": opts(hash_max_flops=32, hash_max_nnz=32, sym_panel_log2=8, lds_budget=1024,
                                        rank_dense_div=100000),
          # no room for segment lists: pieces re-walk their rows

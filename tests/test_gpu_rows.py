@@ -26,7 +26,7 @@ MODES = {
     "rank_all": lambda: opts(hash_max_flops=64, hash_max_nnz=64, lds_budget=8192),
     "rank_kept_bitmaps": lambda: opts(hash_max_flops=32, hash_max_nnz=32, lds_budget=1024, dense_threads=256,
                                       bitmap_mib=1),
-    "rank_wide": lambda: opts(hash_max_flops=64, hash_max_nnz=64, lds_budget=8192, rank_wide_div=4),
+    "rank_wide": lambda: opts(hash_max_flops=64, hash_max_nnz=64, lds_budget=8192, rank_shapes=2),
     "rank_fixed": lambda: opts(hash_max_flops=32, hash_max_nnz=32, sym_panel_log2=8, lds_budget=1024,
                                rank_dense_div=100000),
 }
