@@ -193,7 +193,7 @@ def run_rmat(args):
         # flops per row from the host copy of the operand (bookkeeping only)
         fl = np.bincount(np.repeat(np.arange(H.nrows), deg), weights=deg[H.idx].astype(np.float64),
                          minlength=H.nrows)
-        sym_dense_rows = fl > 8192
+        sym_dense_rows = fl > p.hash_max_flops()
         ranked = phase_ms[sr].get("num_rank", 0.0) > 0
         hmn = p.hash_max_nnz()
         heavy = sym_dense_rows & (rownnz > hmn)

@@ -102,12 +102,11 @@ typedef struct spg_options {
   int32_t validate;        /* 1: check both operands on the device first;
                               a malformed operand gives SPG_E_INVALID */
   int32_t hash_max_flops;  /* symbolic: rows with more products than this use
-                              the dense bitmap accumulator (default 8192) */
+                              the dense bitmap accumulator (default 4096) */
   int32_t hash_max_nnz;    /* numeric: rows with more output entries than this
-                              use the dense panel accumulator (at most 8192,
-                              and only where a table of twice that fits in
-                              LDS; default 8192 for 4-byte accumulators,
-                              4096 for 8-byte ones and the pattern) */
+                              use the rank or dense panel accumulators (at
+                              most 8192, and only where a table of twice that
+                              fits in LDS; default 4096) */
   int32_t short_seg;       /* B-row segments up to this length are walked by
                               one lane; longer ones are split across the
                               waves of a workgroup (default 32) */

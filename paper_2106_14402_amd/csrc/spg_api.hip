@@ -116,17 +116,13 @@ int ilog2_ceil(int64_t x) { return ceil_log2_u64(static_cast<uint64_t>(x < 1 ? 1
 void resolve_options(const spg_options* in, spg_options* o, int sr) {
   std::memset(o, 0, sizeof(*o));
   if (in) *o = *in;
-  if (o->hash_max_flops <= 0) o->hash_max_flops = 8192;
-  if (o->hash_max_nnz <= 0) {
-    // Valued rows: as many output entries as a hash table of twice the size
-    // holds in LDS.  Pattern-only rows: 4096 (a bitmap panel is cheaper than
-    // the largest table for them).
-    const int c = hash_class(8192);
-    o->hash_max_nnz = sr != 7 && hash_num_lds(sr, hash_table_size(c), hash_threads_num(c, sr)) <=
-                                     static_cast<size_t>(max_lds_bytes())
-                          ? 8192
-                          : 4096;
-  }
+  // Rows past 4096 products (symbolic) or 4096 entries (numeric) leave the
+  // LDS hash tables for the bitmap and rank paths: measured on the R-MAT
+  // and Markov-clustering products, the larger tables' sort cost more than
+  // the bitmap passes they replace.
+  (void)sr;
+  if (o->hash_max_flops <= 0) o->hash_max_flops = 4096;
+  if (o->hash_max_nnz <= 0) o->hash_max_nnz = 4096;
   if (o->short_seg <= 0) o->short_seg = 32;
   if (o->dense_threads <= 0) o->dense_threads = 1024;
   if (o->sym_panel_log2 <= 0) o->sym_panel_log2 = 20;

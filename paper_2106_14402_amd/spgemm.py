@@ -122,6 +122,9 @@ class Product:
     def hash_max_nnz(self) -> int:
         return int(self.options().hash_max_nnz)
 
+    def hash_max_flops(self) -> int:
+        return int(self.options().hash_max_flops)
+
     def rank_dense_div(self) -> int:
         return int(self.options().rank_dense_div)
 
