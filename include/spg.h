@@ -81,10 +81,14 @@ typedef enum spg_layout { SPG_CSR = 0, SPG_CSC = 1 } spg_layout;
 /* A compressed sparse matrix held in device memory.
  *  CSR: ptr has nrows+1 entries, idx holds column ids of each row.
  *  CSC: ptr has ncols+1 entries, idx holds row ids of each column.
- * ptr[0] == 0, ptr is non-decreasing and ptr[last] == nnz.  Within a slice
- * the ids are strictly ascending (sorted, no duplicates).  val holds nnz
- * values of the semiring's value type (double, float, int32_t or uint8_t),
- * or NULL for SPG_OR_AND_BOOL (all true).  The library only reads them. */
+ * ptr[0] == 0, ptr is non-decreasing and ptr[last] == nnz.  Ids lie in
+ * [0, minor dimension) with no duplicate within a slice; they need not be
+ * sorted (the paper's local matrices promise no order, Sec. 2.1): every
+ * symbolic phase checks the operands on the device and sorts the slices of
+ * an unsorted operand into the plan's workspace first (options.unsorted).
+ * val holds nnz values of the semiring's value type (double, float, int32_t
+ * or uint8_t), or NULL for SPG_OR_AND_BOOL (all true).  The library only
+ * reads them. */
 typedef struct spg_matrix {
   int32_t nrows;
   int32_t ncols;
@@ -99,8 +103,9 @@ typedef struct spg_matrix {
  * per-slice choice of accumulator by expected output size (Sec. 4.1, hybrid
  * hash/heap by compression ratio). */
 typedef struct spg_options {
-  int32_t validate;        /* 1: check both operands on the device first;
-                              a malformed operand gives SPG_E_INVALID */
+  int32_t validate;        /* ignored: every symbolic phase checks both
+                              operands on the device (offsets, id range,
+                              order); a malformed operand gives SPG_E_INVALID */
   int32_t hash_max_flops;  /* symbolic: rows with more products than this use
                               the dense bitmap accumulator (default 4096) */
   int32_t hash_max_nnz;    /* numeric: rows with more output entries than this
@@ -150,7 +155,17 @@ typedef struct spg_options {
                               bitmap; 2 to 5 add 1.25x, 1.5x, 1.75x and 2x the
                               slots over fewer chunks; each row takes the
                               shape that needs the fewest passes (default 5) */
-  int32_t reserved[2];
+  int32_t unsorted;        /* operands whose slices are not sorted ascending:
+                              0 (default) they are sorted into the workspace,
+                              which holds room for sorted copies of both
+                              operands' ids and values; -1 no room is held and
+                              they give SPG_E_INVALID */
+  int32_t b_checked;       /* 1: the right-hand operand (B; A for CSC
+                              products, the operand whose slices are
+                              gathered) passed spg_matrix_check and has not
+                              changed since: its device check is skipped and
+                              no room is held to sort it.  For a resident
+                              operand shared by many plans. */
 } spg_options;
 
 /* Phases reported by spg_plan_timings, in milliseconds. */
@@ -204,9 +219,13 @@ spg_status spg_sum_plan_create(int k, const spg_matrix* P, spg_semiring sr, cons
  * workspace must be passed, untouched, to spg_symbolic and spg_numeric. */
 spg_status spg_workspace_size(const spg_plan* plan, size_t* bytes);
 
-/* Symbolic phase (paper Sec. 4.1 phases 1-2): per-slice flop count and
- * binning, optional validation, the pattern size of every output slice, and
- * the exclusive scan into c_ptr.
+/* Symbolic phase (paper Sec. 4.1 phases 1-2): the operand check, per-slice
+ * flop count and binning, the pattern size of every output slice, and the
+ * exclusive scan into c_ptr.  The check covers offsets, id range and order:
+ * a malformed operand or a duplicate id gives SPG_E_INVALID before any
+ * kernel uses it to index; an operand with unsorted slices is sorted into
+ * the workspace and the product runs on the sorted copy (its values moved
+ * with their ids), unless options.unsorted = -1 (SPG_E_INVALID).
  *   ws     device workspace of spg_workspace_size() bytes
  *   c_ptr  device, int64[nslices+1] (nslices = rows of C for CSR, columns of
  *          C for CSC), written
@@ -272,6 +291,17 @@ spg_status spg_plan_options(const spg_plan* plan, spg_options* out);
 
 const char* spg_status_str(spg_status s);
 
+/* Device check of one matrix (the check every symbolic phase runs on its
+ * operands): ptr[0] == 0, non-decreasing offsets within [0, nnz],
+ * ptr[last] == nnz, ids in [0, minor dimension), no duplicate id in a slice,
+ * slices sorted ascending.
+ *   ws      device scratch of at least 256 bytes (written)
+ * Synchronises `stream`.  Returns SPG_OK for a well-formed matrix with sorted
+ * slices, SPG_E_INVALID otherwise; *flags (may be NULL) receives the error
+ * bits: 1 bad first/last offset, 2 bad offsets, 4 id out of range,
+ * 8 unsorted slice, 16 duplicate id. */
+spg_status spg_matrix_check(const spg_matrix* M, void* ws, void* stream, int* flags);
+
 /* Column panels.  A dense row accumulator covers 2^wlog2 columns of C at a
  * time; when C is wider, the plan uses P = ceil(ncols(C) / 2^wlog2) panels
  * and a panel index of the right-hand CSR operand: for every row k of it,
@@ -283,7 +313,11 @@ const char* spg_status_str(spg_status s);
  *                           plan creation
  *   spg_panel_index_size:   bytes of the index for operand R (CSR, the
  *                           right-hand operand as the kernels see it)
- *   spg_panel_index_build:  builds it into `out` (device) on `stream`
+ *   spg_panel_index_build:  builds it into `out` (device) on `stream`; R's
+ *                           slices must be sorted (spg_matrix_check): for
+ *                           an unsorted slice every entry of the index is
+ *                           still written, with a value in [0, slice length],
+ *                           but it does not locate the panels
  *   spg_plan_set_panels:    which = 0 symbolic, 1 numeric; `pidx` (device,
  *                           caller-owned, built with the plan's wlog2) is used
  *                           instead of building one in the workspace.
@@ -294,14 +328,21 @@ spg_status spg_panel_index_size(const spg_matrix* R, int wlog2, size_t* bytes);
 spg_status spg_panel_index_build(const spg_matrix* R, int wlog2, void* out, void* stream);
 spg_status spg_plan_set_panels(spg_plan* plan, int which, const void* pidx, int wlog2);
 
-/* Pruning of a float32 matrix (the Markov-clustering step after expansion):
- * keep entries with value >= thresh, drop the rest, order unchanged.  Two
- * phases like the product.
+/* Pruning of a float32 matrix (the Markov-clustering step after expansion;
+ * paper Sec. 7.5: HipMCL runs each expansion's SpGEMM inside an iteration of
+ * expansion, pruning and inflation, and Sec. 7.3 squares protein-similarity
+ * matrices for it): keep entries with value >= thresh, drop the rest, order
+ * unchanged.  Two phases like the product: the count phase sizes the result,
+ * the caller allocates it, the apply phase fills it.  thresh is compared in
+ * float32 with the stored values as they are.
  *   C          float32 matrix in device memory (either layout)
  *   ws         device workspace of at least spg_prune_workspace_size() bytes
  *   new_ptr    device int64[nslices+1], written by the count phase
  *   new_nnz    host, receives the kept count (synchronises the stream)
- *   new_idx/new_val  device outputs of new_nnz entries */
+ *   new_idx/new_val  device outputs of new_nnz entries
+ * Errors: SPG_E_INVALID (NULL outputs or workspace, bad descriptor),
+ * SPG_E_SEMIRING (no values), SPG_E_DEVICE (a launch or the copy failed).
+ * C must be well formed (the product's outputs are); it is not checked. */
 spg_status spg_prune_workspace_size(const spg_matrix* C, size_t* bytes);
 spg_status spg_prune_count_f32(const spg_matrix* C, float thresh, void* ws, void* stream,
                                int64_t* new_ptr, int64_t* new_nnz);

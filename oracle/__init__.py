@@ -69,6 +69,12 @@ def load(path: str):
     L.orc_flops.argtypes = [i32, i64, vp, vp, vp, vp, vp, vp]
     L.orc_prune_f32.restype = i64
     L.orc_prune_f32.argtypes = [i64, vp, vp, vp, ctypes.c_float, vp, vp, vp]
+    L.orc_digest.restype = i32
+    L.orc_digest.argtypes = [i32, i32, i64, vp, vp, vp, vp, vp, vp, vp, i32, vp, vp]
+    L.orc_mix64.restype = None
+    L.orc_mix64.argtypes = [i64, vp, vp]
+    L.orc_select_f32.restype = i64
+    L.orc_select_f32.argtypes = [i64, vp, vp, vp, i64, vp, vp, vp]
     return L
 
 
@@ -211,4 +217,73 @@ def prune_f32(ptr: np.ndarray, idx: np.ndarray, val: np.ndarray, thresh: float):
     nidx = np.empty(nnz, np.int32)
     nval = np.empty(nnz, np.float32)
     L.orc_prune_f32(nmajor, _p(ptr), _p(idx), _p(val), float(thresh), _p(nptr), _p(nidx), _p(nval))
+    return nptr, nidx, nval
+
+
+def digest(A, B, semiring, select: Optional[Sequence[int]] = None, nthreads: int = 0,
+           _lib=None) -> Tuple[np.ndarray, np.ndarray]:
+    """Per-slice digests of C = A (x).(+) B for the slices ``select`` (all
+    when None), without holding C: (nnz int64, hash uint64) per slice, the
+    hash being the sum over the slice's entries t (ascending ids) of
+    mix64(mix64((t << 32) | id) ^ value bits) modulo 2^64, mix64 the output
+    function of SplitMix64.  Exact semirings only."""
+    code = _code(semiring)
+    if A.layout != B.layout or A.ncols != B.nrows:
+        raise ValueError("operands do not conform")
+    layout = 0 if A.layout == "csr" else 1
+    nslices = A.nrows if layout == 0 else B.ncols
+    Ap, Ai, Av = _arrays(A, code, "A")
+    Bp, Bi, Bv = _arrays(B, code, "B")
+    sel = None if select is None else np.ascontiguousarray(select, dtype=np.int64)
+    nsel = nslices if sel is None else sel.size
+    nnz = np.empty(nsel, np.int64)
+    h = np.empty(nsel, np.uint64)
+    L = _lib or lib()
+    rc = L.orc_digest(code, layout, nsel, _p(sel), _p(Ap), _p(Ai), _p(Av), _p(Bp), _p(Bi), _p(Bv),
+                      int(nthreads), _p(nnz), _p(h))
+    if rc != 0:
+        raise ValueError(f"digests are defined for the exact semirings only, not {semiring}")
+    return nnz, h
+
+
+def mix64(x: np.ndarray) -> np.ndarray:
+    """SplitMix64's output function applied to every element."""
+    x = np.ascontiguousarray(x, dtype=np.uint64)
+    out = np.empty_like(x)
+    lib().orc_mix64(x.size, _p(x), _p(out))
+    return out
+
+
+def block_digests(nnz: np.ndarray, h: np.ndarray, first_slice: int = 0,
+                  block: int = 1024) -> Tuple[np.ndarray, np.ndarray]:
+    """Digests of consecutive blocks of ``block`` slices from per-slice
+    digests: the block's entry count, and the sum modulo 2^64 over its slices
+    i (global index first_slice + position) of
+    mix64(h_i ^ mix64((i << 32) | nnz_i))."""
+    nnz = np.asarray(nnz, np.int64)
+    h = np.asarray(h, np.uint64)
+    i = np.arange(first_slice, first_slice + nnz.size, dtype=np.uint64)
+    r = mix64(h ^ mix64((i << np.uint64(32)) | nnz.astype(np.uint64)))
+    nb = -(-nnz.size // block)
+    pad = nb * block - nnz.size
+    rs = np.concatenate([r, np.zeros(pad, np.uint64)]).reshape(nb, block)
+    ns = np.concatenate([nnz, np.zeros(pad, np.int64)]).reshape(nb, block)
+    with np.errstate(over="ignore"):
+        bh = rs.sum(axis=1, dtype=np.uint64)
+    return ns.sum(axis=1), bh
+
+
+def select_f32(ptr: np.ndarray, idx: np.ndarray, val: np.ndarray, S: int):
+    """Selection: every slice keeps its S largest values (ties to the
+    smaller id), in id order.  Returns (ptr, idx, val)."""
+    ptr = np.ascontiguousarray(ptr, np.int64)
+    idx = np.ascontiguousarray(idx, np.int32)
+    val = np.ascontiguousarray(val, np.float32)
+    nmajor = ptr.size - 1
+    L = lib()
+    nnz = L.orc_select_f32(nmajor, _p(ptr), _p(idx), _p(val), int(S), None, None, None)
+    nptr = np.empty(nmajor + 1, np.int64)
+    nidx = np.empty(nnz, np.int32)
+    nval = np.empty(nnz, np.float32)
+    L.orc_select_f32(nmajor, _p(ptr), _p(idx), _p(val), int(S), _p(nptr), _p(nidx), _p(nval))
     return nptr, nidx, nval

@@ -237,6 +237,74 @@ ResultBase* run_sum(int64_t m, int k, const int64_t* Pp, const int32_t* Pi, cons
   return r;
 }
 
+// ---------------------------------------------------------------------------
+// Per-slice digests of a product too large to hold (the definition of C above,
+// checked over every slice without materialising C).
+//
+// mix64 is the output function of SplitMix64 (Steele, Lea and Flood, "Fast
+// splittable pseudorandom number generators", OOPSLA 2014), with the shift
+// and multiplier constants of its published reference implementation.
+// Entry t (0-based, in ascending id order) of a slice, with id j and value
+// bits v (the value's bytes zero-extended to 64 bits; the boolean 0/1 byte),
+// contributes mix64(mix64((t << 32) | j) ^ v); the slice digest is the sum
+// of its entries' contributions modulo 2^64.  Position, id and value all
+// enter, so any change of pattern, order or value changes the digest.
+// ---------------------------------------------------------------------------
+uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+template <class T>
+uint64_t value_bits(T v) {
+  uint64_t b = 0;
+  std::memcpy(&b, &v, sizeof(T));  // little-endian: the value's bytes, zero-extended
+  return b;
+}
+
+template <class S>
+void run_digest(bool csc, int64_t nsel, const int64_t* sel, const int64_t* Ap, const int32_t* Ai, const void* Av,
+                const int64_t* Bp, const int32_t* Bi, const void* Bv, int nthreads, int64_t* nnz_out,
+                uint64_t* hash_out) {
+  if (nthreads <= 0) nthreads = omp_get_max_threads();
+#pragma omp parallel num_threads(nthreads)
+  {
+    std::vector<int32_t> keys;
+    std::vector<typename S::T> vals;
+#pragma omp for schedule(dynamic, 16)
+    for (int64_t t = 0; t < nsel; ++t) {
+      const int64_t s = sel ? sel[t] : t;
+      one_slice<S>(csc, s, Ap, Ai, Av, Bp, Bi, Bv, keys, vals);
+      uint64_t h = 0;
+      for (size_t e = 0; e < keys.size(); ++e) {
+        const uint64_t pos_id = (static_cast<uint64_t>(e) << 32) | static_cast<uint32_t>(keys[e]);
+        h += mix64(mix64(pos_id) ^ value_bits(vals[e]));
+      }
+      nnz_out[t] = static_cast<int64_t>(keys.size());
+      hash_out[t] = h;
+    }
+  }
+}
+
+// Selection (the Markov-clustering step that bounds the entries kept per
+// column): a slice longer than S keeps its S largest values, ties going to
+// the smaller id; the kept entries stay in ascending id order.  Values are
+// compared in float32 with the total order in which -0 < +0.
+void select_slice(int64_t lo, int64_t hi, const int32_t* idx, const float* val, int64_t S,
+                  std::vector<int64_t>& keep) {
+  keep.clear();
+  for (int64_t p = lo; p < hi; ++p) keep.push_back(p);
+  if (hi - lo <= S) return;
+  std::sort(keep.begin(), keep.end(), [&](int64_t x, int64_t y) {
+    if (fless(val[y], val[x])) return true;  // larger value first
+    if (fless(val[x], val[y])) return false;
+    return idx[x] < idx[y];                  // equal values: smaller id first
+  });
+  keep.resize(static_cast<size_t>(S));
+  std::sort(keep.begin(), keep.end(), [&](int64_t x, int64_t y) { return idx[x] < idx[y]; });
+}
+
 }  // namespace
 
 extern "C" {
@@ -326,6 +394,51 @@ int64_t orc_prune_f32(int64_t nmajor, const int64_t* ptr, const int32_t* idx, co
         if (new_val) new_val[out] = val[p];
         ++out;
       }
+    }
+  }
+  if (new_ptr) new_ptr[nmajor] = out;
+  return out;
+}
+
+// Digest of every selected output slice of C = A (x).(+) B (arguments as in
+// orc_spgemm): nnz_out[t] entries and hash_out[t] the slice digest defined
+// above.  Each slice is formed, hashed and dropped, so C is never held.
+// Exact semirings only (codes 2..6); returns -1 for (+,x), 0 otherwise.
+int orc_digest(int semiring, int layout, int64_t nsel, const int64_t* sel, const int64_t* Ap, const int32_t* Ai,
+               const void* Av, const int64_t* Bp, const int32_t* Bi, const void* Bv, int nthreads,
+               int64_t* nnz_out, uint64_t* hash_out) {
+  const bool csc = layout == 1;
+  switch (semiring) {
+    case 2: run_digest<MinPlusI32>(csc, nsel, sel, Ap, Ai, Av, Bp, Bi, Bv, nthreads, nnz_out, hash_out); return 0;
+    case 3: run_digest<MinPlusF32>(csc, nsel, sel, Ap, Ai, Av, Bp, Bi, Bv, nthreads, nnz_out, hash_out); return 0;
+    case 4: run_digest<OrAndBool>(csc, nsel, sel, Ap, Ai, Av, Bp, Bi, Bv, nthreads, nnz_out, hash_out); return 0;
+    case 5: run_digest<MaxTimesF64>(csc, nsel, sel, Ap, Ai, Av, Bp, Bi, Bv, nthreads, nnz_out, hash_out); return 0;
+    case 6: run_digest<MaxTimesF32>(csc, nsel, sel, Ap, Ai, Av, Bp, Bi, Bv, nthreads, nnz_out, hash_out); return 0;
+    default: return -1;
+  }
+}
+
+// mix64 of every element of x (n values), for the block digests built on top
+// of the slice digests.
+void orc_mix64(int64_t n, const uint64_t* x, uint64_t* out) {
+  for (int64_t i = 0; i < n; ++i) out[i] = mix64(x[i]);
+}
+
+// Selection of a float32 compressed matrix: every slice keeps at most S
+// entries, its S largest values (ties to the smaller id), in id order.
+// Returns the kept count; with outputs non-NULL also fills new_ptr
+// (nmajor+1), new_idx and new_val.
+int64_t orc_select_f32(int64_t nmajor, const int64_t* ptr, const int32_t* idx, const float* val, int64_t S,
+                       int64_t* new_ptr, int32_t* new_idx, float* new_val) {
+  std::vector<int64_t> keep;
+  int64_t out = 0;
+  for (int64_t s = 0; s < nmajor; ++s) {
+    if (new_ptr) new_ptr[s] = out;
+    select_slice(ptr[s], ptr[s + 1], idx, val, S, keep);
+    for (int64_t p : keep) {
+      if (new_idx) new_idx[out] = idx[p];
+      if (new_val) new_val[out] = val[p];
+      ++out;
     }
   }
   if (new_ptr) new_ptr[nmajor] = out;

@@ -64,7 +64,8 @@ class spg_options(ctypes.Structure):
         ("rank_panels", ctypes.c_int32),
         ("rank_dense_div", ctypes.c_int32),
         ("rank_shapes", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 2),
+        ("unsorted", ctypes.c_int32),
+        ("b_checked", ctypes.c_int32),
     ]
 
 
@@ -121,6 +122,8 @@ def load(path: str = LIB_PATH):
     L.spg_panel_index_build.argtypes = [pm, ctypes.c_int, vp, vp]
     L.spg_plan_set_panels.restype = st
     L.spg_plan_set_panels.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int]
+    L.spg_matrix_check.restype = st
+    L.spg_matrix_check.argtypes = [pm, vp, vp, ctypes.POINTER(ctypes.c_int)]
     L.spg_prune_workspace_size.restype = st
     L.spg_prune_workspace_size.argtypes = [pm, ctypes.POINTER(ctypes.c_size_t)]
     L.spg_prune_count_f32.restype = st
@@ -294,6 +297,16 @@ def spg_panel_index_build(R: spg_matrix, wlog2: int, out, stream=None) -> None:
 
 def spg_plan_set_panels(plan, which: int, pidx, wlog2: int) -> None:
     _check(load().spg_plan_set_panels(plan, int(which), _addr(pidx), int(wlog2)), "spg_plan_set_panels")
+
+
+def spg_matrix_check(M: spg_matrix, ws, stream=None) -> int:
+    """Error bits of the device check of M (0: well formed and sorted);
+    ws: device scratch of at least 256 bytes."""
+    flags = ctypes.c_int()
+    st = load().spg_matrix_check(ctypes.byref(M), _addr(ws), _stream(stream), ctypes.byref(flags))
+    if st not in (0, 1):
+        _check(st, "spg_matrix_check")
+    return int(flags.value)
 
 
 def spg_prune_workspace_size(C: spg_matrix) -> int:

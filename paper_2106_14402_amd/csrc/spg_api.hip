@@ -53,6 +53,17 @@ struct spg_plan {
   bool pnum_ready;
   unsigned long long sub_counts[kNumBins];
   int64_t a_nnz, b_nnz;  // entries of the oriented operands
+  // the caller's id and value arrays of the oriented operands (op points at
+  // sorted copies in the workspace after a symbolic phase that sorted them)
+  const int32_t* src_a_idx;
+  const void* src_a_val;
+  const int32_t* src_b_idx;
+  const void* src_b_val;
+  int a_es, b_es;                // bytes per input value (0: none)
+  bool room_a, room_b;           // workspace holds room to sort A / B
+  bool check_b;                  // B is checked by the symbolic phase
+  bool b_resorted;               // this symbolic phase sorted B: external panels do not apply
+  size_t off_sa_idx, off_sa_val, off_sb_idx, off_sb_val, off_spos;
   const int32_t* ext_psym;  // caller-built panel indexes (NULL: build in workspace)
   const int32_t* ext_pnum;
   int state;
@@ -101,6 +112,15 @@ spg_status from_hip(hipError_t e) { return e == hipSuccess ? SPG_OK : SPG_E_DEVI
   } while (0)
 
 bool valid_semiring(int sr) { return sr >= 0 && sr <= 6; }
+
+// Bytes of one input value of a user semiring code.
+int in_bytes(int user_sr) {
+  switch (user_sr) {
+    case SPG_PLUS_TIMES_F64: case SPG_MAX_TIMES_F64: return 8;
+    case SPG_OR_AND_BOOL: return 1;
+    default: return 4;
+  }
+}
 
 spg_status check_matrix(const spg_matrix* M) {
   if (!M) return SPG_E_INVALID;
@@ -320,6 +340,29 @@ static spg_status plan_init(spg_plan* p, const spg_options* opt_in) {
     p->off_sel_val = off;
     off = align_up(off + sel * 8);
   }
+  // sorted copies of operands found unsorted (ids, values) and the position
+  // scratch of the sort
+  p->check_b = p->opt.b_checked != 1;
+  p->room_a = p->opt.unsorted != -1 && p->sum_k == 0;
+  p->room_b = p->opt.unsorted != -1 && p->check_b;
+  p->off_sa_idx = p->off_sa_val = p->off_sb_idx = p->off_sb_val = p->off_spos = off;
+  if (p->room_a) {
+    p->off_sa_idx = off;
+    off = align_up(off + static_cast<size_t>(p->a_nnz) * sizeof(int32_t));
+    p->off_sa_val = off;
+    off = align_up(off + static_cast<size_t>(p->a_nnz) * p->a_es);
+  }
+  if (p->room_b) {
+    p->off_sb_idx = off;
+    off = align_up(off + static_cast<size_t>(p->b_nnz) * sizeof(int32_t));
+    p->off_sb_val = off;
+    off = align_up(off + static_cast<size_t>(p->b_nnz) * p->b_es);
+  }
+  if (p->room_a || p->room_b) {
+    p->off_spos = off;
+    off = align_up(off + static_cast<size_t>(std::max(p->room_a ? p->a_nnz : 0, p->room_b ? p->b_nnz : 0)) *
+                             sizeof(int32_t));
+  }
   p->seg_total = 0;
   p->pnum_ready = false;
   p->ws_bytes = off;
@@ -327,6 +370,7 @@ static spg_status plan_init(spg_plan* p, const spg_options* opt_in) {
   p->c_ptr = nullptr;
   p->ext_psym = nullptr;
   p->ext_pnum = nullptr;
+  p->b_resorted = false;
   p->ev_made = false;
   for (int i = 0; i < SPG_NUM_PHASES; ++i) p->ran[i] = false;
   if (p->opt.timing) {
@@ -388,6 +432,12 @@ spg_status spg_plan_create(const spg_matrix* A, const spg_matrix* B, spg_semirin
   p->op.b_val = R->val;
   p->a_nnz = L->nnz;
   p->b_nnz = R->nnz;
+  p->src_a_idx = L->idx;
+  p->src_a_val = L->val;
+  p->src_b_idx = R->idx;
+  p->src_b_val = R->val;
+  p->a_es = L->val ? in_bytes(sr) : 0;
+  p->b_es = R->val ? in_bytes(sr) : 0;
   p->op.m = p->csc ? B->ncols : A->nrows;
   p->op.n = A->ncols;
   p->op.k = p->csc ? A->nrows : B->ncols;
@@ -429,6 +479,12 @@ spg_status spg_sum_plan_create(int k, const spg_matrix* P, spg_semiring sr_in, c
   p->op.b_idx = P->idx;
   p->op.b_val = P->val;
   p->b_nnz = P->nnz;
+  p->src_a_idx = nullptr;
+  p->src_a_val = nullptr;
+  p->src_b_idx = P->idx;
+  p->src_b_val = P->val;
+  p->a_es = 0;
+  p->b_es = P->val ? in_bytes(sr) : 0;
   p->a_nnz = m * k;
   p->op.m = static_cast<int32_t>(m);
   p->op.n = static_cast<int32_t>(major);
@@ -560,28 +616,69 @@ spg_status spg_symbolic(spg_plan* p, void* ws, int64_t* c_ptr, int64_t* c_nnz) {
   const int32_t m = op.m;
 
   for (int i = 0; i < SPG_NUM_PHASES; ++i) p->ran[i] = false;
-  SPG_TRY_HIP(launch_fill_u64(reinterpret_cast<uint64_t*>(ctr), kCtrWords, 0, s));
-  if (p->opt.validate) {
-    PhaseTimer t(p, SPG_PHASE_VALIDATE);
-    if ((op.m == 0 && p->a_nnz != 0) || (op.n == 0 && p->b_nnz != 0)) return SPG_E_INVALID;
-    int* err = reinterpret_cast<int*>(ctr + kCtrMisc + 1);
-    SPG_TRY_HIP(launch_validate(op.a_ptr, op.a_idx, op.m, p->a_nnz, op.n, err, s));
-    SPG_TRY_HIP(launch_validate(op.b_ptr, op.b_idx, op.n, p->b_nnz, op.k, err, s));
-    int herr = 0;
-    SPG_TRY_HIP(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, s));
-    SPG_TRY_HIP(hipStreamSynchronize(s));
-    if (herr) return SPG_E_INVALID;
+  if (p->sum_k == 0) {
+    p->op.a_idx = p->src_a_idx;
+    p->op.a_val = p->src_a_val;
   }
-  unsigned long long hcounts[kNumBins + 1];
+  p->op.b_idx = p->src_b_idx;
+  p->op.b_val = p->src_b_val;
+  p->b_resorted = false;
+  if ((op.m == 0 && p->a_nnz != 0) || (op.n == 0 && p->b_nnz != 0)) return SPG_E_INVALID;
+  SPG_TRY_HIP(launch_fill_u64(reinterpret_cast<uint64_t*>(ctr), kCtrWords, 0, s));
+  // The operand check rides along: B's slices by k_validate, A's inside the
+  // flop count, which never indexes with an id it has not range-checked.  The
+  // bin counts and both error words come back in one copy.
+  int* err_a = reinterpret_cast<int*>(ctr + kCtrMisc + 1);
+  int* err_b = reinterpret_cast<int*>(ctr + kCtrMisc + 3);
+  unsigned long long hcounts[kNumBins + 4];
   {
     PhaseTimer t(p, SPG_PHASE_FLOPS_BIN);
-    SPG_TRY_HIP(launch_flops_bin(op, p->bp, flops, c_ptr, ctr + kCtrSym, ctr + kCtrMisc, s));
+    if (p->check_b) SPG_TRY_HIP(launch_validate(op.b_ptr, op.b_idx, op.n, p->b_nnz, op.k, err_b, s));
+    SPG_TRY_HIP(launch_flops_bin(op, p->a_nnz, p->bp, flops, c_ptr, ctr + kCtrSym, ctr + kCtrMisc, err_a, s));
   }
   SPG_TRY_HIP(hipMemcpyAsync(hcounts, ctr + kCtrSym, kNumBins * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
-  SPG_TRY_HIP(hipMemcpyAsync(&hcounts[kNumBins], ctr + kCtrMisc, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+  SPG_TRY_HIP(hipMemcpyAsync(&hcounts[kNumBins], ctr + kCtrMisc, 4 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
   SPG_TRY_HIP(hipStreamSynchronize(s));
   std::memcpy(p->sym_counts, hcounts, sizeof(p->sym_counts));
   p->flops_total = static_cast<int64_t>(hcounts[kNumBins]);
+  {
+    const int ea = static_cast<int>(hcounts[kNumBins + 1] & 0xffffffffu);
+    const int eb = static_cast<int>(hcounts[kNumBins + 3] & 0xffffffffu);
+    if ((ea | eb) & kCheckMalformed) return SPG_E_INVALID;
+    // an equal adjacent pair in a sorted slice is a duplicate; in an
+    // unsorted one it is decided on the sorted copy
+    if ((ea & kCheckDuplicate) && !(ea & kCheckUnsorted)) return SPG_E_INVALID;
+    if ((eb & kCheckDuplicate) && !(eb & kCheckUnsorted)) return SPG_E_INVALID;
+    const bool sort_a = (ea & kCheckUnsorted) != 0, sort_b = (eb & kCheckUnsorted) != 0;
+    if ((sort_a && !p->room_a) || (sort_b && !p->room_b)) return SPG_E_INVALID;
+    if (sort_a || sort_b) {
+      PhaseTimer t(p, SPG_PHASE_VALIDATE);
+      auto* pos = reinterpret_cast<int32_t*>(w + p->off_spos);
+      int herr = 0;
+      SPG_TRY_HIP(launch_fill_u64(reinterpret_cast<uint64_t*>(ctr + kCtrMisc + 1), 1, 0, s));
+      if (sort_a) {
+        auto* si = reinterpret_cast<int32_t*>(w + p->off_sa_idx);
+        void* sv = p->a_es ? w + p->off_sa_val : nullptr;
+        SPG_TRY_HIP(launch_sort_slices(op.a_ptr, op.a_idx, op.a_val, p->a_es, op.m, si, sv, pos, s));
+        p->op.a_idx = si;
+        p->op.a_val = sv;
+        SPG_TRY_HIP(launch_validate(op.a_ptr, op.a_idx, op.m, p->a_nnz, op.n, err_a, s));
+      }
+      if (sort_b) {
+        auto* si = reinterpret_cast<int32_t*>(w + p->off_sb_idx);
+        void* sv = p->b_es ? w + p->off_sb_val : nullptr;
+        SPG_TRY_HIP(launch_sort_slices(op.b_ptr, op.b_idx, op.b_val, p->b_es, op.n, si, sv, pos, s));
+        p->op.b_idx = si;
+        p->op.b_val = sv;
+        SPG_TRY_HIP(launch_validate(op.b_ptr, op.b_idx, op.n, p->b_nnz, op.k, err_a, s));
+      }
+      SPG_TRY_HIP(hipMemcpyAsync(&herr, err_a, sizeof(int), hipMemcpyDeviceToHost, s));
+      SPG_TRY_HIP(hipStreamSynchronize(s));
+      if (herr) return SPG_E_INVALID;  // duplicates
+      // external panel indexes were built over the caller's order
+      p->b_resorted = sort_b;
+    }
+  }
 
   const BinOffsets so = offsets_of(p->sym_counts);
   int64_t ndense = 0;
@@ -596,7 +693,7 @@ spg_status spg_symbolic(spg_plan* p, void* ws, int64_t* c_ptr, int64_t* c_nnz) {
     }
   }
   if (ndense > 0) {
-    if (p->sym_P > 1 && p->ext_psym) {
+    if (p->sym_P > 1 && p->ext_psym && !p->b_resorted) {
       psym = const_cast<int32_t*>(p->ext_psym);
     } else if (p->sym_P > 1) {
       PhaseTimer tp(p, SPG_PHASE_SYM_PANELS);
@@ -639,7 +736,7 @@ spg_status spg_symbolic(spg_plan* p, void* ws, int64_t* c_ptr, int64_t* c_nnz) {
   p->seg_total = 0;
   if (p->split && ndense > 0) {
     auto* pnum = reinterpret_cast<int32_t*>(w + p->off_pnum);
-    if (!p->ext_pnum) {
+    if (!p->ext_pnum || p->b_resorted) {
       PhaseTimer tp(p, SPG_PHASE_NUM_PANELS);
       SPG_TRY_HIP(launch_panel_index(op.b_ptr, op.b_idx, op.n, p->num_wlog2, p->num_P, pnum, s));
     }
@@ -647,7 +744,7 @@ spg_status spg_symbolic(spg_plan* p, void* ws, int64_t* c_ptr, int64_t* c_nnz) {
     PhaseTimer tc(p, SPG_PHASE_SEG_COUNT);
     auto* segoff = reinterpret_cast<int64_t*>(w + p->off_segoff);
     SPG_TRY_HIP(launch_seg_count(op, rows_sym + so.v[kDenseBinBase], ndense, p->num_P,
-                                 p->ext_pnum ? p->ext_pnum : pnum,
+                                 (p->ext_pnum && !p->b_resorted) ? p->ext_pnum : pnum,
                                  reinterpret_cast<const int32_t*>(w + p->off_wend), segoff + 1, s));
     SPG_TRY_HIP(launch_scan_inplace(segoff + 1, ndense * p->num_P, scan, s));
     SPG_TRY_HIP(hipMemcpyAsync(&p->seg_total, segoff + ndense * p->num_P, sizeof(int64_t),
@@ -751,7 +848,7 @@ static spg_status numeric_range(spg_plan* p, void* ws, int32_t rb, int32_t re, i
   const int32_t* wend = reinterpret_cast<const int32_t*>(w + p->off_wend);
   p->ran[SPG_PHASE_SEG_WRITE] = false;
   if ((ndense > 0 || sub) && p->num_P > 1) {
-    if (p->ext_pnum) {
+    if (p->ext_pnum && !p->b_resorted) {
       pnum = const_cast<int32_t*>(p->ext_pnum);
     } else if (!p->pnum_ready) {
       PhaseTimer tp(p, SPG_PHASE_NUM_PANELS);
@@ -858,6 +955,27 @@ spg_status spg_numeric_rows(spg_plan* p, void* ws, int64_t row_begin, int64_t ro
   if (!p) return SPG_E_INVALID;
   if (row_begin < 0 || row_end < row_begin || row_end > p->op.m) return SPG_E_INVALID;
   return numeric_range(p, ws, static_cast<int32_t>(row_begin), static_cast<int32_t>(row_end), c_idx, c_val);
+}
+
+spg_status spg_matrix_check(const spg_matrix* M, void* ws, void* stream, int* flags) {
+  spg_status st = check_matrix(M);
+  if (st != SPG_OK) return st;
+  if (!ws) return SPG_E_INVALID;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int64_t nmajor = M->layout == SPG_CSR ? M->nrows : M->ncols;
+  const int32_t nminor = M->layout == SPG_CSR ? M->ncols : M->nrows;
+  int* err = static_cast<int*>(ws);
+  int h = 0;
+  if (nmajor == 0) {
+    h = M->nnz != 0 ? kCheckEnds : 0;
+  } else {
+    SPG_TRY_HIP(launch_fill_u64(static_cast<uint64_t*>(ws), 1, 0, s));
+    SPG_TRY_HIP(launch_validate(M->ptr, M->idx, nmajor, M->nnz, nminor, err, s));
+    SPG_TRY_HIP(hipMemcpyAsync(&h, err, sizeof(int), hipMemcpyDeviceToHost, s));
+    SPG_TRY_HIP(hipStreamSynchronize(s));
+  }
+  if (flags) *flags = h;
+  return h ? SPG_E_INVALID : SPG_OK;
 }
 
 spg_status spg_prune_workspace_size(const spg_matrix* C, size_t* bytes) {

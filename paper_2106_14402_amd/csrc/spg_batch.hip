@@ -17,6 +17,7 @@
 
 #include "../../include/spg.h"
 #include "spg_launch.h"
+#include "spg_rowlogic.h"
 
 using namespace spg;
 
@@ -40,6 +41,43 @@ __device__ __forceinline__ int find_segment(const int64_t* __restrict__ off, int
       hi = mid;
   }
   return lo;
+}
+
+// Operand check of every product (the checks of k_validate, error bits into
+// *err): global waves [0, mtot) take the A slices, [mtot, mtot + ntot) the B
+// slices.
+__global__ void kb_validate(const BatchDesc* __restrict__ d, const int64_t* __restrict__ row_off,
+                            const int64_t* __restrict__ brow_off, int nprod, int64_t mtot, int64_t ntot,
+                            int* err) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t g = static_cast<int64_t>(blockIdx.x) * (blockDim.x / kWave) + (threadIdx.x >> 6);
+  if (g >= mtot + ntot) return;
+  const bool is_a = g < mtot;
+  const int b = is_a ? find_segment(row_off, nprod, g) : find_segment(brow_off, nprod, g - mtot);
+  const Operands& op = d[b].op;
+  const int64_t s = is_a ? g - row_off[b] : g - mtot - brow_off[b];
+  const int64_t nmajor = is_a ? op.m : op.n;
+  const int64_t nnz = is_a ? d[b].a_nnz : d[b].b_nnz;
+  const int32_t nminor = is_a ? op.n : op.k;
+  const int64_t* ptr = is_a ? op.a_ptr : op.b_ptr;
+  const int32_t* idx = is_a ? op.a_idx : op.b_idx;
+  int e = 0;
+  if (lane == 0) {
+    if (s == 0 && ptr[0] != 0) e |= kCheckEnds;
+    if (s == nmajor - 1 && ptr[nmajor] != nnz) e |= kCheckEnds;
+  }
+  const int64_t lo = ptr[s], hi = ptr[s + 1];
+  if (lo < 0 || hi > nnz || hi < lo) {
+    e |= kCheckOffsets;
+  } else {
+    for (int64_t q = lo + lane; q < hi; q += kWave) {
+      const int32_t c = idx[q];
+      if (c < 0 || c >= nminor) e |= kCheckRange;
+      if (q > lo && idx[q - 1] >= c) e |= idx[q - 1] > c ? kCheckUnsorted : kCheckDuplicate;
+    }
+  }
+  e = wave_or(e);
+  if (lane == 0 && e) atomicOr(err, e);
 }
 
 // flops per global row, symbolic bin counts, zero nnz for empty rows.
@@ -142,15 +180,12 @@ __global__ void kb_panel_index(const BatchDesc* __restrict__ d, const int64_t* _
   const int64_t k = g - brow_off[b];
   const int64_t lo = db.op.b_ptr[k], hi = db.op.b_ptr[k + 1];
   int32_t* out = pidx + k * (P + 1);
-  for (int64_t q = lo + lane; q < hi; q += kWave) {
-    const int cp = db.op.b_idx[q] >> wlog2;
-    const int pp = q == lo ? -1 : (db.op.b_idx[q - 1] >> wlog2);
-    for (int p = pp + 1; p <= cp; ++p) out[p] = static_cast<int32_t>(q - lo);
-  }
-  if (lane == 0) {
-    const int lp = hi > lo ? (db.op.b_idx[hi - 1] >> wlog2) : -1;
-    for (int p = lp + 1; p <= P; ++p) out[p] = static_cast<int32_t>(hi - lo);
-  }
+  // as k_panel_index: every slot first holds the row length, then a sorted
+  // row's entries open their panels
+  panel_index_fill(out, P, static_cast<int32_t>(hi - lo), lane, kWave);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_s_waitcnt(0);
+  panel_index_open(db.op.b_idx + lo, hi - lo, wlog2, P, out, lane, kWave);
 }
 
 // pool[po_b] = 0 for every product (the leading slot of each offsets array).
@@ -362,6 +397,8 @@ spg_status spg_batch_plan_create(int nprod, const spg_matrix* A, const spg_matri
     d.sr = (bool_sr && !A[b].val && !B[b].val) ? 7 : sr;
     p->a_nnz[b] = L.nnz;
     p->b_nnz[b] = R.nnz;
+    d.a_nnz = L.nnz;
+    d.b_nnz = R.nnz;
     int slot = -1;
     for (size_t s2 = 0; s2 < p->slot_sr.size(); ++s2)
       if (p->slot_sr[s2] == d.sr) slot = static_cast<int>(s2);
@@ -488,13 +525,11 @@ spg_status spg_batch_symbolic(spg_batch_plan* p, void* ws, int64_t* c_ptr_pool, 
     SPG_TRY_HIP(hipMemcpyAsync(slot_of, p->h_slots.data(), sizeof(int32_t) * nprod, hipMemcpyHostToDevice, s));
   }
   SPG_TRY_HIP(launch_fill_u64(reinterpret_cast<uint64_t*>(ctr), kCtrWords, 0, s));
-  if (p->opt.validate) {
+  // Operand check of every product before any kernel indexes with their ids.
+  if (p->mtot + p->ntot > 0) {
     int* err = reinterpret_cast<int*>(ctr + kCtrMisc + 1);
-    for (int b = 0; b < nprod; ++b) {
-      const Operands& op = p->desc[b].op;
-      SPG_TRY_HIP(launch_validate(op.a_ptr, op.a_idx, op.m, p->a_nnz[b], op.n, err, s));
-      SPG_TRY_HIP(launch_validate(op.b_ptr, op.b_idx, op.n, p->b_nnz[b], op.k, err, s));
-    }
+    hipLaunchKernelGGL(kb_validate, dim3(blocks(p->mtot + p->ntot, 4)), dim3(256), 0, s, d, row_off, brow_off,
+                       nprod, p->mtot, p->ntot, err);
     int herr = 0;
     SPG_TRY_HIP(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, s));
     SPG_TRY_HIP(hipStreamSynchronize(s));

@@ -173,6 +173,12 @@ __device__ __forceinline__ T wave_sum(T x) {
   return x;
 }
 
+__device__ __forceinline__ int wave_or(int x) {
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) x |= __shfl_xor(x, d, kWave);
+  return x;
+}
+
 template <class T>
 __device__ T block_exclusive_scan(T v, T* tmp, T* total) {
   const int lane = threadIdx.x & (kWave - 1);

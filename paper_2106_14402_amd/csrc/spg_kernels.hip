@@ -20,6 +20,7 @@
 #include <cstring>
 
 #include "spg_launch.h"
+#include "spg_rowlogic.h"
 
 namespace spg {
 
@@ -40,9 +41,11 @@ hipError_t launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s) {
 }
 
 // Operand check: ptr[0] == 0, ptr non-decreasing within [0, nnz],
-// ptr[nmajor] == nnz, ids in [0, nminor) and strictly ascending per slice.
-// Error bits: 1 bad endpoints, 2 bad offsets, 4 id out of range, 8 unsorted
-// or duplicate ids.  One wave per slice; never reads outside [0, nnz).
+// ptr[nmajor] == nnz, ids in [0, nminor), and the order of the ids of each
+// slice.  Error bits (kCheck*): bad endpoints, bad offsets, an id out of
+// range, a descending pair of adjacent ids (the slice is not sorted), an equal
+// pair of adjacent ids (a duplicate, or a possible one in an unsorted slice).
+// One wave per slice; never reads outside [0, nnz).
 __global__ void k_validate(const int64_t* __restrict__ ptr, const int32_t* __restrict__ idx,
                            int64_t nmajor, int64_t nnz, int32_t nminor, int* err) {
   const int lane = threadIdx.x & (kWave - 1);
@@ -50,20 +53,25 @@ __global__ void k_validate(const int64_t* __restrict__ ptr, const int32_t* __res
   if (s >= nmajor) return;
   int e = 0;
   if (lane == 0) {
-    if (s == 0 && ptr[0] != 0) e |= 1;
-    if (s == nmajor - 1 && ptr[nmajor] != nnz) e |= 1;
+    if (s == 0 && ptr[0] != 0) e |= kCheckEnds;
+    if (s == nmajor - 1 && ptr[nmajor] != nnz) e |= kCheckEnds;
   }
   const int64_t lo = ptr[s], hi = ptr[s + 1];
   if (lo < 0 || hi > nnz || hi < lo) {
-    e |= 2;
+    e |= kCheckOffsets;
   } else {
     for (int64_t q = lo + lane; q < hi; q += kWave) {
       const int32_t c = idx[q];
-      if (c < 0 || c >= nminor) e |= 4;
-      if (q > lo && idx[q - 1] >= c) e |= 8;
+      if (c < 0 || c >= nminor) e |= kCheckRange;
+      if (q > lo) {
+        const int32_t b = idx[q - 1];
+        if (b > c) e |= kCheckUnsorted;
+        if (b == c) e |= kCheckDuplicate;
+      }
     }
   }
-  if (e) atomicOr(err, e);
+  e = wave_or(e);
+  if (lane == 0 && e) atomicOr(err, e);
 }
 
 hipError_t launch_validate(const int64_t* ptr, const int32_t* idx, int64_t nmajor, int64_t nnz,
@@ -77,13 +85,105 @@ hipError_t launch_validate(const int64_t* ptr, const int32_t* idx, int64_t nmajo
 }
 
 // ---------------------------------------------------------------------------
+// Sorted copy of a CSR operand whose slices are not all sorted: the ids of
+// every slice in ascending order, with their values, into out_idx / out_val
+// (same offsets).  One workgroup per slice.  A slice that is already sorted
+// is copied as it is.  Otherwise its (id, position) pairs go through a
+// bitonic sorting network: in LDS up to kSortLds ids, else in global memory
+// (out_idx and the position scratch `pos`, both indexed like idx).  The
+// network is the variant in which each merge starts with a mirrored
+// compare-exchange step, so every comparator puts the smaller id first; the
+// padding up to a power of two is then never touched (it would hold +inf and
+// stay in place).  Values follow their ids through the positions.  Equal ids
+// keep an arbitrary order: the caller checks the copy for duplicates.
+// ---------------------------------------------------------------------------
+constexpr int kSortThreads = 256;
+constexpr int kSortLds = 2048;
+
+template <class K>
+__device__ __forceinline__ void sort_network(K* key, int32_t* pos, int L) {
+  const int N = network_size(L);
+  for (int k = 2; k <= N; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      sort_network_step(key, pos, L, N, k, j, static_cast<int>(threadIdx.x), static_cast<int>(blockDim.x));
+      __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_sort_slices(const int64_t* __restrict__ ptr,
+                                                              const int32_t* __restrict__ idx,
+                                                              const unsigned char* __restrict__ val, int es,
+                                                              int64_t nmajor, int32_t* __restrict__ out_idx,
+                                                              unsigned char* __restrict__ out_val,
+                                                              int32_t* __restrict__ pos) {
+  __shared__ int32_t skey[kSortLds];
+  __shared__ int32_t spos[kSortLds];
+  __shared__ int unsorted;
+  for (int64_t s = blockIdx.x; s < nmajor; s += gridDim.x) {
+    const int64_t lo = ptr[s], hi = ptr[s + 1];
+    const int L = static_cast<int>(hi - lo);
+    if (threadIdx.x == 0) unsorted = 0;
+    __syncthreads();
+    int u = 0;
+    for (int t = threadIdx.x + 1; t < L; t += blockDim.x) u |= idx[lo + t - 1] > idx[lo + t];
+    if (u) unsorted = 1;
+    __syncthreads();
+    if (!unsorted) {
+      for (int t = threadIdx.x; t < L; t += blockDim.x) out_idx[lo + t] = idx[lo + t];
+      for (int64_t b = threadIdx.x; b < static_cast<int64_t>(L) * es; b += blockDim.x)
+        out_val[lo * es + b] = val[lo * es + b];
+      __syncthreads();
+      continue;
+    }
+    int32_t* key;
+    int32_t* ps;
+    if (L <= kSortLds) {
+      key = skey;
+      ps = spos;
+    } else {
+      key = out_idx + lo;
+      ps = pos + lo;
+    }
+    for (int t = threadIdx.x; t < L; t += blockDim.x) {
+      key[t] = idx[lo + t];
+      ps[t] = t;
+    }
+    __syncthreads();
+    sort_network(key, ps, L);
+    for (int t = threadIdx.x; t < L; t += blockDim.x) {
+      const int src = ps[t];
+      if (L <= kSortLds) out_idx[lo + t] = key[t];
+      if (es == 8)
+        reinterpret_cast<uint64_t*>(out_val)[lo + t] = reinterpret_cast<const uint64_t*>(val)[lo + src];
+      else if (es == 4)
+        reinterpret_cast<uint32_t*>(out_val)[lo + t] = reinterpret_cast<const uint32_t*>(val)[lo + src];
+      else if (es == 1)
+        out_val[lo + t] = val[lo + src];
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_sort_slices(const int64_t* ptr, const int32_t* idx, const void* val, int es, int64_t nmajor,
+                              int32_t* out_idx, void* out_val, int32_t* pos, hipStream_t s) {
+  if (nmajor <= 0) return hipSuccess;
+  const unsigned nb = static_cast<unsigned>(std::min<int64_t>(nmajor, 65536));
+  hipLaunchKernelGGL(k_sort_slices, dim3(nb), dim3(kSortThreads), 0, s, ptr, idx,
+                     static_cast<const unsigned char*>(val), val ? es : 0, nmajor, out_idx,
+                     static_cast<unsigned char*>(out_val), pos);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Flop count and binning (paper Sec. 4.1 phase 1: estimate the flops of every
 // output slice before splitting the work).  flops_i = sum over A(i,k) of
 // nnz(B(k,:)).  One wave per row.
 // ---------------------------------------------------------------------------
-__global__ void k_flops_bin(Operands op, BinParams bp, int64_t* __restrict__ flops,
+__global__ void k_flops_bin(Operands op, int64_t a_nnz, BinParams bp, int64_t* __restrict__ flops,
                             int64_t* __restrict__ c_ptr, unsigned long long* counts,
-                            unsigned long long* total) {
+                            unsigned long long* total, int* err) {
+  // Also checks A as k_validate does (same error bits into *err), and reads
+  // nothing outside A's arrays or B's offsets whatever A holds.
   __shared__ unsigned int lc[kNumBins];
   __shared__ unsigned long long ltot;
   const int tid = threadIdx.x;
@@ -93,17 +193,38 @@ __global__ void k_flops_bin(Operands op, BinParams bp, int64_t* __restrict__ flo
   __syncthreads();
   const int64_t i = static_cast<int64_t>(blockIdx.x) * (blockDim.x / kWave) + (tid >> 6);
   if (i < op.m) {
+    int e = 0;
     int64_t f = 0;
-    for (int64_t p = op.a_ptr[i] + lane; p < op.a_ptr[i + 1]; p += kWave) {
-      const int32_t k = op.a_idx[p];
-      f += op.b_ptr[k + 1] - op.b_ptr[k];
+    const int64_t lo = op.a_ptr[i], hi = op.a_ptr[i + 1];
+    if (lane == 0) {
+      if (i == 0 && lo != 0) e |= kCheckEnds;
+      if (i == op.m - 1 && hi != a_nnz) e |= kCheckEnds;
+    }
+    if (lo < 0 || hi > a_nnz || hi < lo) {
+      e |= kCheckOffsets;
+    } else {
+      for (int64_t p = lo + lane; p < hi; p += kWave) {
+        const int32_t k = op.a_idx[p];
+        if (k < 0 || k >= op.n) {
+          e |= kCheckRange;
+          continue;
+        }
+        if (p > lo) {
+          const int32_t b = op.a_idx[p - 1];
+          if (b > k) e |= kCheckUnsorted;
+          if (b == k) e |= kCheckDuplicate;
+        }
+        f += op.b_ptr[k + 1] - op.b_ptr[k];
+      }
     }
     f = wave_sum(f);
+    e = wave_or(e);
     if (lane == 0) {
       flops[i] = f;
       if (f == 0) c_ptr[i + 1] = 0;
       atomicAdd(&lc[sym_bin(f, bp)], 1u);
       atomicAdd(&ltot, static_cast<unsigned long long>(f));
+      if (e) atomicOr(err, e);
     }
   }
   __syncthreads();
@@ -111,13 +232,13 @@ __global__ void k_flops_bin(Operands op, BinParams bp, int64_t* __restrict__ flo
   if (tid == 0 && ltot) atomicAdd(total, ltot);
 }
 
-hipError_t launch_flops_bin(const Operands& op, BinParams bp, int64_t* flops, int64_t* c_ptr,
-                            unsigned long long* counts, unsigned long long* total, hipStream_t s) {
+hipError_t launch_flops_bin(const Operands& op, int64_t a_nnz, BinParams bp, int64_t* flops, int64_t* c_ptr,
+                            unsigned long long* counts, unsigned long long* total, int* err, hipStream_t s) {
   if (op.m <= 0) return hipSuccess;
   const int nt = 256;
   const int64_t nb = (static_cast<int64_t>(op.m) + nt / kWave - 1) / (nt / kWave);
-  hipLaunchKernelGGL(k_flops_bin, dim3(static_cast<unsigned>(nb)), dim3(nt), 0, s, op, bp, flops,
-                     c_ptr, counts, total);
+  hipLaunchKernelGGL(k_flops_bin, dim3(static_cast<unsigned>(nb)), dim3(nt), 0, s, op, a_nnz, bp, flops,
+                     c_ptr, counts, total, err);
   return hipGetLastError();
 }
 
@@ -253,8 +374,12 @@ hipError_t launch_interleave_b(const Operands& op, int64_t nnz, int2* out, hipSt
 
 // ---------------------------------------------------------------------------
 // Panel index: for B row k and panel p (columns [p*W, (p+1)*W)),
-// pidx[k*(P+1) + p] = number of entries of B(k,:) with column < p*W.  Rows
-// must be sorted.  One wave per row; every slot is written exactly once.
+// pidx[k*(P+1) + p] = number of entries of B(k,:) with column < p*W, for a
+// row sorted ascending.  One wave per row.  Every slot is first set to the
+// row length, so the index holds values in [0, len] for any order of ids;
+// then, for a sorted row, each slot up to the last entry's panel is written
+// by the entry that opens it.  (The library builds indexes only over
+// operands it has checked to be sorted.)
 // ---------------------------------------------------------------------------
 __global__ void k_panel_index(const int64_t* __restrict__ b_ptr, const int32_t* __restrict__ b_idx,
                               int32_t nrows, int wlog2, int P, int32_t* __restrict__ pidx) {
@@ -263,15 +388,11 @@ __global__ void k_panel_index(const int64_t* __restrict__ b_ptr, const int32_t* 
   if (k >= nrows) return;
   const int64_t lo = b_ptr[k], hi = b_ptr[k + 1];
   int32_t* out = pidx + k * (P + 1);
-  for (int64_t q = lo + lane; q < hi; q += kWave) {
-    const int cp = b_idx[q] >> wlog2;
-    const int pp = q == lo ? -1 : (b_idx[q - 1] >> wlog2);
-    for (int p = pp + 1; p <= cp; ++p) out[p] = static_cast<int32_t>(q - lo);
-  }
-  if (lane == 0) {
-    const int lp = hi > lo ? (b_idx[hi - 1] >> wlog2) : -1;
-    for (int p = lp + 1; p <= P; ++p) out[p] = static_cast<int32_t>(hi - lo);
-  }
+  panel_index_fill(out, P, static_cast<int32_t>(hi - lo), lane, kWave);
+  // the fills reach memory before the writes below (same addresses)
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_s_waitcnt(0);
+  panel_index_open(b_idx + lo, hi - lo, wlog2, P, out, lane, kWave);
 }
 
 hipError_t launch_panel_index(const int64_t* b_ptr, const int32_t* b_idx, int32_t nrows, int wlog2,

@@ -12,6 +12,14 @@ constexpr int kNumBins = 64;
 constexpr int kDenseBinBase = 16;  // bins >= this use a dense accumulator
 constexpr int kScanTile = 8192;    // elements per scan block
 
+// Operand check error bits (k_validate, k_flops_bin).
+constexpr int kCheckEnds = 1;       // ptr[0] != 0 or ptr[last] != nnz
+constexpr int kCheckOffsets = 2;    // a slice's offsets outside [0, nnz] or decreasing
+constexpr int kCheckRange = 4;      // an id outside [0, minor dimension)
+constexpr int kCheckUnsorted = 8;   // a descending pair of adjacent ids
+constexpr int kCheckDuplicate = 16; // an equal pair of adjacent ids
+constexpr int kCheckMalformed = kCheckEnds | kCheckOffsets | kCheckRange;
+
 struct BinParams {
   int64_t hash_max_flops;  // symbolic: hash when flops <= this
   int64_t hash_max_nnz;    // numeric: hash when nnz <= this
@@ -89,6 +97,7 @@ struct BatchDesc {
   int32_t sym_wlog2, sym_P, num_wlog2, num_P;
   int32_t sr;              // kernel semiring code
   int32_t pad;
+  int64_t a_nnz, b_nnz;    // entries of the oriented operands
 };
 
 // Hash table size and workgroup size of hash class c.
@@ -102,8 +111,14 @@ inline int hash_threads(int c) {
 hipError_t launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s);
 hipError_t launch_validate(const int64_t* ptr, const int32_t* idx, int64_t nmajor, int64_t nnz,
                            int32_t nminor, int* err, hipStream_t s);
-hipError_t launch_flops_bin(const Operands& op, BinParams bp, int64_t* flops, int64_t* c_ptr,
-                            unsigned long long* counts, unsigned long long* total, hipStream_t s);
+// Also checks A (error bits into *err); a_nnz = entries of A.
+hipError_t launch_flops_bin(const Operands& op, int64_t a_nnz, BinParams bp, int64_t* flops, int64_t* c_ptr,
+                            unsigned long long* counts, unsigned long long* total, int* err, hipStream_t s);
+// Sorted copy of a CSR operand (ids ascending in every slice, values along;
+// es = bytes per value, 0 or val NULL for none).  pos: int32 scratch indexed
+// like idx.
+hipError_t launch_sort_slices(const int64_t* ptr, const int32_t* idx, const void* val, int es, int64_t nmajor,
+                              int32_t* out_idx, void* out_val, int32_t* pos, hipStream_t s);
 // Rows [r0, m); scanned: c_ptr holds offsets (else c_ptr[i+1] is row i's nnz).
 hipError_t launch_count_num_bins(int32_t m, int32_t r0, int scanned, const int64_t* flops, const int64_t* c_ptr,
                                  BinParams bp, unsigned long long* counts, hipStream_t s);

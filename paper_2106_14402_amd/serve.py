@@ -29,7 +29,7 @@ import torch
 from . import binding as B_
 from .spgemm import DeviceMatrix, Product
 
-SPG_OK, SPG_E_INVALID, SPG_E_NOMEM = 0, 1, 5
+SPG_OK, SPG_E_INVALID, SPG_E_NOMEM, SPG_E_DEVICE = 0, 1, 5, 7
 
 
 @dataclasses.dataclass
@@ -51,9 +51,11 @@ class Result:
 
 class ResidentGraph:
     """The adjacency kept in HBM (pattern-only CSR of out-neighbour lists),
-    its host degree array for admission bounds, and panel indexes built once."""
+    its host degree array for admission bounds, and panel indexes built once.
+    The operand is checked on the device once, at load; the plans that use it
+    skip that check (options.b_checked)."""
 
-    def __init__(self, A_host, device="cuda"):
+    def __init__(self, A_host, device="cuda", options=None):
         assert A_host.layout == "csr"
         self.n = A_host.nrows
         self.outdeg = np.diff(A_host.ptr).astype(np.int64)
@@ -61,6 +63,12 @@ class ResidentGraph:
         self.A = DeviceMatrix(A_host.nrows, A_host.ncols, "csr",
                               torch.from_numpy(A_host.ptr).to(self.device),
                               torch.from_numpy(A_host.idx).to(self.device), None)
+        scratch = torch.zeros(64, dtype=torch.int32, device=self.device)
+        flags = B_.spg_matrix_check(self.A.descriptor(), scratch)
+        if flags:
+            raise ValueError(f"resident operand fails the device check (error bits {flags})")
+        self.options = B_.make_options(b_checked=1) if options is None else options
+        self.options.b_checked = 1
         self._panels = {}
         self._lock = threading.Lock()
 
@@ -75,13 +83,32 @@ class ResidentGraph:
                 self._panels[wlog2] = t
             return self._panels[wlog2]
 
+    def workspace_bytes(self, rows: int, entries: int) -> int:
+        """Device workspace of the product of a batch of `rows` frontier rows
+        holding `entries` sources: the size the library reports for that plan
+        (plan creation is host-only and reads only the descriptors)."""
+        return plan_workspace_bytes(self.A.descriptor(), self.n, rows, entries, self.options)
+
+
+def plan_workspace_bytes(Adesc, n: int, rows: int, entries: int, options) -> int:
+    """Workspace of F^T (rows x n, `entries` entries) times the resident
+    operand, from a plan created for the descriptors alone and destroyed."""
+    F = B_.spg_matrix(int(rows), int(n), int(entries), B_.SPG_CSR, Adesc.ptr, Adesc.idx if entries else None,
+                      None)
+    plan = B_.spg_plan_create(F, Adesc, "or_and_bool", options, 0)
+    try:
+        return B_.spg_workspace_size(plan)
+    finally:
+        B_.spg_plan_destroy(plan)
+
 
 def request_bound_bytes(graph: ResidentGraph, Ft) -> int:
-    """Upper bound of a request's device footprint: its frontier, an output
-    with one entry per product, offsets, and the per-row workspace."""
+    """Upper bound of a request's device footprint without the workspace: its
+    frontier, an output with one entry per product, and offsets.  Admission
+    adds the workspace of the whole batch (ResidentGraph.workspace_bytes)."""
     k = Ft.nrows
     flops = int(graph.outdeg[Ft.idx].sum()) if Ft.nnz else 0
-    return 12 * Ft.nnz + 8 * (k + 1) + 4 * flops + 8 * (k + 1) + 24 * k + 4096
+    return 12 * Ft.nnz + 8 * (k + 1) + 4 * flops + 8 * (k + 1) + 4096
 
 
 def check_frontier(graph: ResidentGraph, Ft) -> bool:
@@ -109,7 +136,9 @@ class FrontierServer:
         self.max_rows = max_batch_rows
         self.max_reqs = max_batch_requests
         self.nworkers = workers
-        self.options = options
+        # plans skip the check of the resident operand (checked at load)
+        self.options = B_.make_options(b_checked=1) if options is None else options
+        self.options.b_checked = 1
         self._cv = threading.Condition()
         self._pending = collections.deque()   # (arrival, rid, Ft, bound)
         self._in_flight = 0
@@ -118,24 +147,34 @@ class FrontierServer:
         self._feeding = False
 
     # ---- admission ---------------------------------------------------------
+    def workspace_bytes(self, rows: int, entries: int) -> int:
+        """Workspace of the product of a batch of `rows` frontier rows with
+        `entries` sources, as the library sizes it for this server's options."""
+        return plan_workspace_bytes(self.g.A.descriptor(), self.g.n, rows, entries, self.options)
+
     def _take_batch(self):
         """Block until at least one request fits the budget, then take every
-        waiting request that fits (FIFO) up to the batch caps."""
+        waiting request that fits (FIFO) up to the batch caps.  A batch's
+        admitted bytes are its requests' bounds plus the workspace of its
+        product."""
         with self._cv:
             while True:
                 if self._pending:
-                    batch, rows, need = [], 0, 0
+                    batch, rows, ents, need = [], 0, 0, 0
                     while self._pending and len(batch) < self.max_reqs:
                         arr, rid, Ft, bound = self._pending[0]
                         if batch and rows + Ft.nrows > self.max_rows:
                             break
-                        if self._in_flight + need + bound > self.budget:
+                        ws = self.workspace_bytes(rows + Ft.nrows, ents + Ft.nnz)
+                        if self._in_flight + need + bound + ws > self.budget:
                             break
                         self._pending.popleft()
                         batch.append((arr, rid, Ft, bound))
                         rows += Ft.nrows
+                        ents += Ft.nnz
                         need += bound
                     if batch:
+                        need += self.workspace_bytes(rows, ents)
                         self._in_flight += need
                         return batch, need
                 if self._stop and not self._feeding and not self._pending:
@@ -152,7 +191,7 @@ class FrontierServer:
         if not check_frontier(self.g, Ft):
             return Result(rid, SPG_E_INVALID, arrival, arrival, time.perf_counter())
         bound = request_bound_bytes(self.g, Ft)
-        if bound > self.budget:
+        if bound + self.workspace_bytes(Ft.nrows, Ft.nnz) > self.budget:
             return Result(rid, SPG_E_NOMEM, arrival, arrival, time.perf_counter())
         with self._cv:
             self._pending.append((arrival, rid, Ft, bound))
@@ -203,7 +242,9 @@ class FrontierServer:
         return out
 
     def _worker(self):
-        stream = torch.cuda.Stream(self.g.device)
+        self._worker_loop(torch.cuda.Stream(self.g.device))
+
+    def _worker_loop(self, stream):
         while True:
             batch, need = self._take_batch()
             if batch is None:
@@ -213,6 +254,9 @@ class FrontierServer:
             except B_.SpgError as e:
                 now = time.perf_counter()
                 res = [Result(rid, e.status, arr, now, now) for arr, rid, _, _ in batch]
+            except Exception:  # noqa: BLE001 - a failed batch must not drop its requests
+                now = time.perf_counter()
+                res = [Result(rid, SPG_E_DEVICE, arr, now, now) for arr, rid, _, _ in batch]
             finally:
                 self._release(need)
             with self._cv:
@@ -251,7 +295,7 @@ def expand_alone(graph: ResidentGraph, Ft, options=None):
     dev = graph.device
     F = DeviceMatrix(Ft.nrows, graph.n, "csr", torch.from_numpy(Ft.ptr).to(dev),
                      torch.from_numpy(Ft.idx.astype(np.int32)).to(dev), None)
-    prod = Product(F, graph.A, "or_and_bool", options)
+    prod = Product(F, graph.A, "or_and_bool", options or graph.options)
     try:
         prod.symbolic()
         C = prod.numeric()

@@ -71,6 +71,11 @@ def assert_parity(A, B, sr, got, select=None, want=None):
         bound = PLUS_TOL[sr] * absv
         bad = err > bound
         assert not bad.any(), f"{bad.sum()} values outside tolerance; worst {np.max(err - bound)}"
+        if (A.val >= 0).all() and (B.val >= 0).all():
+            # non-negative operands: (|A||B|)_ij is C_ij itself, so the bound
+            # above is the plain relative error |c - c*| / |c*|
+            rel = err <= PLUS_TOL[sr] * np.abs(ov) * (1 + 1e-9) + 1e-300
+            assert rel.all(), f"{(~rel).sum()} values over the relative tolerance"
     else:
         assert gv.dtype == ov.dtype
         assert np.array_equal(gv.view(np.uint8), ov.view(np.uint8)), "values differ"

@@ -300,10 +300,20 @@ def test_error_codes():
                  options=opts(validate=1))
     assert e.value.status == 1
     uns = dA.idx.clone()
-    uns[0], uns[1] = dA.idx[1], dA.idx[0]                 # unsorted row
+    uns[0], uns[1] = dA.idx[1], dA.idx[0]                 # unsorted row: rejected only without sort room
     with pytest.raises(B.SpgError) as e:
         S.spgemm(S.DeviceMatrix(50, 50, "csr", dA.ptr, uns, dA.val), dA, "min_plus_i32",
-                 options=opts(validate=1))
+                 options=opts(unsorted=-1))
+    assert e.value.status == 1
+    dup = dA.idx.clone()
+    dup[1] = dA.idx[0]                                    # duplicate id in a row
+    with pytest.raises(B.SpgError) as e:
+        S.spgemm(S.DeviceMatrix(50, 50, "csr", dA.ptr, dup, dA.val), dA, "min_plus_i32")
+    assert e.value.status == 1
+    bad_ptr = dA.ptr.clone()
+    bad_ptr[3] = bad_ptr[4] + 1                           # decreasing offsets
+    with pytest.raises(B.SpgError) as e:
+        S.spgemm(dA, S.DeviceMatrix(50, 50, "csr", bad_ptr, dA.idx, dA.val), "min_plus_i32")
     assert e.value.status == 1
     p = S.Product(dA, dA, "min_plus_i32")
     with pytest.raises(B.SpgError) as e:

@@ -9,9 +9,15 @@ from paper_2106_14402_amd import serve as SV
 
 
 def fake_graph(n=1000, seed=0):
+    """Host stand-in of a ResidentGraph: degrees for the bounds, and a
+    descriptor whose device addresses are never dereferenced (plan creation
+    and workspace sizing are host-only)."""
+    from paper_2106_14402_amd import binding as B
     rng = np.random.default_rng(seed)
     A = spgen.rmat_graph(0, 6, rng, symmetric=False, n=n)
-    g = types.SimpleNamespace(n=n, outdeg=np.diff(A.ptr).astype(np.int64), device=None)
+    desc = B.spg_matrix(n, n, A.nnz, B.SPG_CSR, 0x10000, 0x20000, None)
+    g = types.SimpleNamespace(n=n, outdeg=np.diff(A.ptr).astype(np.int64), device=None,
+                              A=types.SimpleNamespace(descriptor=lambda: desc))
     return g, A
 
 
@@ -52,23 +58,29 @@ def test_admission_respects_budget_and_rejects():
     rng = np.random.default_rng(3)
     reqs = [spgen.frontier(g.n, 3, rng) for _ in range(6)]
     bounds = [SV.request_bound_bytes(g, F) for F in reqs]
-    budget = sum(sorted(bounds)[:2]) + 1
+    probe = SV.FrontierServer(g, workers=1)
+    alone = [b + probe.workspace_bytes(F.nrows, F.nnz) for b, F in zip(bounds, reqs)]
+    budget = sum(sorted(alone)[:2]) + 1
     srv = SV.FrontierServer(g, hbm_budget=budget, workers=1)
     for i, F in enumerate(reqs):
-        if bounds[i] <= budget:
+        if alone[i] <= budget:
             assert srv.submit(i, F, 0.0) is None
     srv._feeding = False
     taken = 0
     while srv._pending:
         batch, need = srv._take_batch()
+        rows = sum(F.nrows for _, _, F, _ in batch)
+        ents = sum(F.nnz for _, _, F, _ in batch)
+        # admitted bytes: the requests' bounds plus their product's workspace
+        assert need == sum(b for _, _, _, b in batch) + srv.workspace_bytes(rows, ents)
         assert need <= budget
         assert srv._in_flight <= budget
         taken += len(batch)
         srv._release(need)
-    assert taken == sum(1 for b in bounds if b <= budget)
+    assert taken == sum(1 for a in alone if a <= budget)
     # a request larger than the whole budget is rejected with SPG_E_NOMEM
-    big = max(range(len(reqs)), key=lambda i: bounds[i])
-    srv2 = SV.FrontierServer(g, hbm_budget=bounds[big] - 1, workers=1)
+    big = max(range(len(reqs)), key=lambda i: alone[i])
+    srv2 = SV.FrontierServer(g, hbm_budget=alone[big] - 1, workers=1)
     r = srv2.submit(99, reqs[big], 0.0)
     assert r is not None and r.status == SV.SPG_E_NOMEM
     # an invalid frontier is rejected with SPG_E_INVALID and queues nothing
@@ -76,6 +88,68 @@ def test_admission_respects_budget_and_rejects():
     r = srv2.submit(100, bad, 0.0)
     assert r is not None and r.status == SV.SPG_E_INVALID
     assert not srv2._pending
+
+
+def test_admission_counts_the_workspace():
+    """The workspace the plan asks for (offsets, row lists, panel indexes of
+    the resident operand, sort room for the frontier) is part of a request's
+    admitted bytes: a budget that covers the bound alone rejects it."""
+    g, _ = fake_graph()
+    F = spgen.frontier(g.n, 8, np.random.default_rng(5))
+    bound = SV.request_bound_bytes(g, F)
+    srv = SV.FrontierServer(g, workers=1)
+    ws = srv.workspace_bytes(F.nrows, F.nnz)
+    assert ws > 0
+    tight = SV.FrontierServer(g, hbm_budget=bound + ws - 1, workers=1)
+    r = tight.submit(1, F, 0.0)
+    assert r is not None and r.status == SV.SPG_E_NOMEM
+    ok = SV.FrontierServer(g, hbm_budget=bound + ws, workers=1)
+    assert ok.submit(1, F, 0.0) is None
+
+
+def test_worker_survives_a_failing_batch():
+    """An exception that is not an SpgError (a torch allocation failure, say)
+    turns the batch's requests into error results; the worker keeps going and
+    the budget is released."""
+    import threading
+    g, _ = fake_graph()
+    rng = np.random.default_rng(6)
+    srv = SV.FrontierServer(g, workers=1)
+    calls = []
+
+    def failing(batch, stream):
+        calls.append(len(batch))
+        if len(calls) == 1:
+            raise RuntimeError("out of memory")
+        return [SV.Result(rid, SV.SPG_OK, arr) for arr, rid, _, _ in batch]
+
+    srv._execute = failing
+    srv._feeding = True
+    for i in range(3):
+        srv.submit(i, spgen.frontier(g.n, 2, rng), 0.0)
+    t = threading.Thread(target=srv._worker_loop, args=(None,), daemon=True)
+    t.start()
+    import time
+
+    def wait_for(n):
+        t_end = time.time() + 10
+        while len(srv._results) < n and t.is_alive() and time.time() < t_end:
+            time.sleep(0.01)
+
+    wait_for(3)                          # the first batch failed
+    for i in range(3, 5):
+        srv.submit(i, spgen.frontier(g.n, 2, rng), 0.0)
+    wait_for(5)
+    with srv._cv:
+        srv._feeding = False
+        srv._stop = True
+        srv._cv.notify_all()
+    t.join(timeout=10)
+    assert not t.is_alive()
+    st = {r.rid: r.status for r in srv._results}
+    assert all(st[i] == SV.SPG_E_DEVICE for i in range(3))
+    assert all(st[i] == SV.SPG_OK for i in range(3, 5))
+    assert srv._in_flight == 0
 
 
 def test_batch_caps():
