@@ -66,12 +66,15 @@ def test_large_output_rows_use_dense_panels():
 
 
 def test_tight_budget_queues_and_rejects():
+    """A request is rejected when its own bound plus the workspace of a batch
+    holding it alone exceeds the budget; the others queue and complete."""
     from paper_2106_14402_amd import serve as SV
     A = _graph()
     g = SV.ResidentGraph(A)
     reqs = spgen.request_stream(A.nrows, 60, rate=50000.0, rng=np.random.default_rng(6), k_max=16)
-    bounds = [SV.request_bound_bytes(g, q.Ft) for q in reqs]
-    budget = int(np.percentile(bounds, 60)) * 2
+    bounds = [SV.request_bound_bytes(g, q.Ft) + g.workspace_bytes(q.Ft.nrows, q.Ft.nnz) for q in reqs]
+    budget = int(np.percentile(bounds, 60)) + int(np.percentile(bounds, 10))
+    assert 0 < sum(b > budget for b in bounds) < len(bounds)
     bad = spgen.SparseMatrix(1, A.nrows, "csr", np.array([0, 1]), np.array([A.nrows + 3], np.int32), None)
     reqs.append(type("R", (), {"rid": 1000, "arrival": reqs[-1].arrival, "Ft": bad})())
     srv = SV.FrontierServer(g, hbm_budget=budget, workers=2)
