@@ -349,6 +349,23 @@ spg_status spg_prune_count_f32(const spg_matrix* C, float thresh, void* ws, void
 spg_status spg_prune_apply_f32(const spg_matrix* C, float thresh, void* ws, void* stream,
                                const int64_t* new_ptr, int32_t* new_idx, float* new_val);
 
+/* Count phase of the prune for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): spg_prune_count_f32 with the workspace replaced by a 64 KiB
+ * array of the library's own (SPG_NOALLOC_SCRATCH_WORDS int64 words of
+ * device memory per GPU, held until the process ends).  It calls no
+ * allocating routine.  Same arguments, results and errors as
+ * spg_prune_count_f32, for C with at most SPG_NOALLOC_MAX_SLICES slices;
+ * larger C gives SPG_E_NOMEM before any device work.  The stream must belong
+ * to the current device.  Every call on one GPU uses the same array: calls
+ * that overlap on one GPU (other streams, other host threads) race and must
+ * be serialised by the caller.  The apply phase is spg_prune_apply_f32 (it
+ * uses no workspace; pass ws = NULL). */
+#define SPG_NOALLOC_SCRATCH_WORDS 8192
+#define SPG_NOALLOC_MAX_SLICES ((int64_t)(SPG_NOALLOC_SCRATCH_WORDS - 1) * 8192)
+spg_status spg_prune_count_f32_noalloc(const spg_matrix* C, float thresh, void* stream, int64_t* new_ptr,
+                                       int64_t* new_nnz);
+
 /* Inflation (the Markov-clustering step after pruning, paper Sec. 7.5: the
  * HipMCL iteration is expansion, pruning, inflation): every slice's values
  * raised to the power r and divided by their sum, so each slice sums to 1

@@ -15,6 +15,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libspg.so")
 
 SPG_CSR, SPG_CSC = 0, 1
+# scratch of spg_prune_count_f32_noalloc (int64 words) and the slices it serves
+SPG_NOALLOC_SCRATCH_WORDS = 8192
+SPG_NOALLOC_MAX_SLICES = (SPG_NOALLOC_SCRATCH_WORDS - 1) * 8192
 SEMIRINGS = {
     "plus_times_f64": 0,
     "plus_times_f32": 1,
@@ -130,6 +133,8 @@ def load(path: str = LIB_PATH):
     L.spg_prune_count_f32.argtypes = [pm, ctypes.c_float, vp, vp, vp, ctypes.POINTER(i64)]
     L.spg_prune_apply_f32.restype = st
     L.spg_prune_apply_f32.argtypes = [pm, ctypes.c_float, vp, vp, vp, vp, vp]
+    L.spg_prune_count_f32_noalloc.restype = st
+    L.spg_prune_count_f32_noalloc.argtypes = [pm, ctypes.c_float, vp, vp, ctypes.POINTER(i64)]
     _declare_batch(L)
     _lib = L
     return L
@@ -319,6 +324,13 @@ def spg_prune_count_f32(C: spg_matrix, thresh: float, ws, new_ptr, stream=None) 
     nnz = ctypes.c_int64()
     _check(load().spg_prune_count_f32(ctypes.byref(C), float(thresh), _addr(ws), _stream(stream),
                                       _addr(new_ptr), ctypes.byref(nnz)), "spg_prune_count_f32")
+    return int(nnz.value)
+
+
+def spg_prune_count_f32_noalloc(C: spg_matrix, thresh: float, new_ptr, stream=None) -> int:
+    nnz = ctypes.c_int64()
+    _check(load().spg_prune_count_f32_noalloc(ctypes.byref(C), float(thresh), _stream(stream), _addr(new_ptr),
+                                              ctypes.byref(nnz)), "spg_prune_count_f32_noalloc")
     return int(nnz.value)
 
 

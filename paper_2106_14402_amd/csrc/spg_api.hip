@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "../../include/spg.h"
@@ -987,21 +988,74 @@ spg_status spg_prune_workspace_size(const spg_matrix* C, size_t* bytes) {
   return SPG_OK;
 }
 
+}  // extern "C"
+
+// Count phase of the prune with the scan's tile partials in `partials`
+// (at least (nslices + kScanTile - 1) / kScanTile words; every word the scan
+// reads it writes first, so nothing needs clearing).
+static spg_status prune_count(const spg_matrix* C, float thresh, int64_t* partials, hipStream_t s,
+                              int64_t* new_ptr, int64_t* new_nnz) {
+  const int64_t nmajor = C->layout == SPG_CSR ? C->nrows : C->ncols;
+  SPG_TRY_HIP(launch_prune_count(C->ptr, static_cast<const float*>(C->val), nmajor, thresh, new_ptr, s));
+  SPG_TRY_HIP(launch_scan_inplace(new_ptr + 1, nmajor, partials, s));
+  int64_t total = 0;
+  SPG_TRY_HIP(hipMemcpyAsync(&total, new_ptr + nmajor, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  SPG_TRY_HIP(hipStreamSynchronize(s));
+  *new_nnz = total;
+  return SPG_OK;
+}
+
+// Scratch of spg_prune_count_f32_noalloc: the scan's tile partials.  Every
+// GPU the library runs on holds its own copy until the process ends; host
+// code reaches it only through the address hipGetSymbolAddress returns for
+// that device (the array's name is not a device address on the host).
+static __device__ __align__(256) int64_t scratch[SPG_NOALLOC_SCRATCH_WORDS];
+static_assert(SPG_NOALLOC_MAX_SLICES <= static_cast<int64_t>(SPG_NOALLOC_SCRATCH_WORDS - 1) * kScanTile,
+              "the scan of SPG_NOALLOC_MAX_SLICES slices needs more tile partials than the scratch holds");
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+int64_t* g_scratch_addr[kMaxDevices];  // device address of `scratch`, per device
+
+// Address of `scratch` on the current device, looked up on the first call
+// for that device.
+spg_status scratch_address(int64_t** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return SPG_E_DEVICE;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* a = nullptr;
+    if (hipGetSymbolAddress(&a, HIP_SYMBOL(scratch)) != hipSuccess || !a) return SPG_E_DEVICE;
+    g_scratch_addr[dev] = static_cast<int64_t*>(a);
+  }
+  *out = g_scratch_addr[dev];
+  return SPG_OK;
+}
+}  // namespace
+
+extern "C" {
+
 spg_status spg_prune_count_f32(const spg_matrix* C, float thresh, void* ws, void* stream,
                                int64_t* new_ptr, int64_t* new_nnz) {
   spg_status st = check_matrix(C);
   if (st != SPG_OK) return st;
   if (!new_ptr || !new_nnz || !ws) return SPG_E_INVALID;
   if (C->nnz > 0 && !C->val) return SPG_E_SEMIRING;
-  hipStream_t s = static_cast<hipStream_t>(stream);
+  return prune_count(C, thresh, static_cast<int64_t*>(ws), static_cast<hipStream_t>(stream), new_ptr, new_nnz);
+}
+
+spg_status spg_prune_count_f32_noalloc(const spg_matrix* C, float thresh, void* stream, int64_t* new_ptr,
+                                       int64_t* new_nnz) {
+  spg_status st = check_matrix(C);
+  if (st != SPG_OK) return st;
+  if (!new_ptr || !new_nnz) return SPG_E_INVALID;
+  if (C->nnz > 0 && !C->val) return SPG_E_SEMIRING;
   const int64_t nmajor = C->layout == SPG_CSR ? C->nrows : C->ncols;
-  SPG_TRY_HIP(launch_prune_count(C->ptr, static_cast<const float*>(C->val), nmajor, thresh, new_ptr, s));
-  SPG_TRY_HIP(launch_scan_inplace(new_ptr + 1, nmajor, static_cast<int64_t*>(ws), s));
-  int64_t total = 0;
-  SPG_TRY_HIP(hipMemcpyAsync(&total, new_ptr + nmajor, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  SPG_TRY_HIP(hipStreamSynchronize(s));
-  *new_nnz = total;
-  return SPG_OK;
+  if (nmajor > SPG_NOALLOC_MAX_SLICES) return SPG_E_NOMEM;
+  int64_t* partials = nullptr;
+  if ((st = scratch_address(&partials)) != SPG_OK) return st;
+  return prune_count(C, thresh, partials, static_cast<hipStream_t>(stream), new_ptr, new_nnz);
 }
 
 spg_status spg_inflate_f32(const spg_matrix* C, float r, float* val_out, void* stream) {

@@ -74,3 +74,16 @@ def test_plan_create_rejects_bad_descriptors_without_gpu(lib):
     o = B.make_options(hash_max_flops=1 << 20)
     assert L.spg_plan_create(ctypes.byref(A), ctypes.byref(Bm), 4, ctypes.byref(o), None,
                              ctypes.byref(plan)) == 1
+
+
+def test_noalloc_prune_count_refuses_oversize_on_host(lib):
+    """More slices than the no-allocation scratch serves: SPG_E_NOMEM before
+    any HIP call (the descriptor's arrays are never read)."""
+    from paper_2106_14402_amd import binding as B
+
+    L = B.load(LIB)
+    dummy = ctypes.c_void_p(0x1000)
+    C = B.spg_matrix(4, B.SPG_NOALLOC_MAX_SLICES + 1, 0, B.SPG_CSC, dummy.value, dummy.value, dummy.value)
+    nnz = ctypes.c_int64(-1)
+    st = L.spg_prune_count_f32_noalloc(ctypes.byref(C), ctypes.c_float(1e-4), None, dummy, ctypes.byref(nnz))
+    assert st == 5 and nnz.value == -1
