@@ -166,6 +166,17 @@ typedef struct spg_options {
                               changed since: its device check is skipped and
                               no room is held to sort it.  For a resident
                               operand shared by many plans. */
+  int32_t sym_windows;     /* symbolic phase of the rows past hash_max_flops:
+                              0 or 1 (default) = one bitmap per row
+                              (sym_panel_log2 wide, panel after panel); N > 1
+                              = N column windows, each (row, window) a work
+                              item of its own, the workgroups of one XCD taking
+                              the items of one window first (more L2 reuse of
+                              B, more work per item) */
+  int32_t win_threads;     /* workgroup size of the windowed kernels
+                              (default 256) */
+  int32_t win_wgs;         /* workgroups per compute unit of the windowed
+                              kernels (default 8) */
 } spg_options;
 
 /* Phases reported by spg_plan_timings, in milliseconds. */

@@ -69,6 +69,9 @@ class spg_options(ctypes.Structure):
         ("rank_shapes", ctypes.c_int32),
         ("unsorted", ctypes.c_int32),
         ("b_checked", ctypes.c_int32),
+        ("sym_windows", ctypes.c_int32),
+        ("win_threads", ctypes.c_int32),
+        ("win_wgs", ctypes.c_int32),
     ]
 
 

@@ -31,6 +31,8 @@ struct spg_plan {
   spg_options opt;
   BinParams bp;
   int sym_wlog2, sym_P, num_wlog2, num_P;
+  bool sym_win;                  // dense symbolic rows as (row, window) items
+  size_t off_itemcnt, off_slotflag;
   // workspace layout (byte offsets)
   size_t off_ctr, off_flops, off_rows_sym, off_rows_num, off_scan, off_psym, off_pnum, ws_bytes;
   bool split;                    // heavy rows go to the numeric phase as (row, panel) pieces
@@ -102,7 +104,9 @@ constexpr int kCtrNum = kNumBins;          // [64] numeric bin counts
 constexpr int kCtrCursor = 2 * kNumBins;   // [64] scatter cursors
 constexpr int kCtrMisc = 3 * kNumBins;     // [0] total flops, [1] validation error bits
 constexpr int kCtrSub = 4 * kNumBins;      // [64] (row, panel) piece bin counts
-constexpr int kCtrWords = 5 * kNumBins;
+constexpr int kCtrWin = 5 * kNumBins;      // [64] window queues (uint32 each) of the windowed symbolic
+constexpr int kCtrWords = 6 * kNumBins;
+constexpr int kMaxWindows = 2 * kNumBins;
 
 spg_status from_hip(hipError_t e) { return e == hipSuccess ? SPG_OK : SPG_E_DEVICE; }
 
@@ -151,6 +155,8 @@ void resolve_options(const spg_options* in, spg_options* o, int sr) {
   if (o->seg_mib <= 0) o->seg_mib = 16384;
   if (o->rank_dense_div <= 0) o->rank_dense_div = 1;
   if (o->rank_shapes <= 0 || o->rank_shapes > kRankShapes) o->rank_shapes = kRankShapes;
+  if (o->win_threads <= 0) o->win_threads = 256;
+  if (o->win_wgs <= 0) o->win_wgs = 8;
 }
 
 spg_status check_options(const spg_options& o, int sr) {
@@ -158,6 +164,8 @@ spg_status check_options(const spg_options& o, int sr) {
   if (o.hash_max_nnz < 32 || o.hash_max_nnz > 8192) return SPG_E_INVALID;
   if (o.dense_threads % kWave != 0 || o.dense_threads > 1024) return SPG_E_INVALID;
   if (o.sym_panel_log2 < 7 || o.sym_panel_log2 > 20) return SPG_E_INVALID;
+  if (o.sym_windows < 0 || o.sym_windows > kMaxWindows) return SPG_E_INVALID;
+  if (o.win_threads % kWave != 0 || o.win_threads > 1024 || o.win_wgs > 32) return SPG_E_INVALID;
   // hash tables must fit in LDS
   const int csym = hash_class(o.hash_max_flops);
   if (hash_sym_lds(hash_table_size(csym), hash_threads(csym)) > static_cast<size_t>(max_lds_bytes()))
@@ -211,7 +219,21 @@ static spg_status plan_init(spg_plan* p, const spg_options* opt_in) {
   while (p->sym_wlog2 > 7 && dense_sym_lds(p->sym_wlog2, nt) > static_cast<size_t>(max_lds_bytes()))
     --p->sym_wlog2;
   const int64_t kk = std::max<int64_t>(1, p->op.k);
+  // Column windows of the dense symbolic rows (off unless asked for: the
+  // per-item work of eight windows costs more than their L2 reuse saves).
+  {
+    const int nwin = p->opt.sym_windows > 0 ? p->opt.sym_windows : 1;
+    p->sym_win = false;
+    if (nwin > 1 && p->opt.split_panels <= 0) {
+      const int wl = std::max(7, ilog2_ceil((kk + nwin - 1) / nwin));
+      if (wl < kbits && dense_sym_lds(wl, p->opt.win_threads) <= static_cast<size_t>(max_lds_bytes())) {
+        p->sym_win = true;
+        p->sym_wlog2 = wl;
+      }
+    }
+  }
   p->sym_P = static_cast<int>((kk + (int64_t(1) << p->sym_wlog2) - 1) >> p->sym_wlog2);
+  if (p->sym_P <= 1 || p->sym_P > kMaxWindows) p->sym_win = false;
   p->num_P = static_cast<int>((kk + (int64_t(1) << p->num_wlog2) - 1) >> p->num_wlog2);
   p->split = p->opt.split_panels > 0 && p->sr != 7 && p->num_P > 1 && p->sym_wlog2 >= p->num_wlog2 &&
              static_cast<int64_t>(p->op.m) * p->num_P < (int64_t(1) << 31);
@@ -288,7 +310,7 @@ static spg_status plan_init(spg_plan* p, const spg_options* opt_in) {
   // Kept bitmaps: pattern-only rows are expanded from them, rank-panel rows
   // read their pattern from them, instead of walking B's column ids once
   // more; worth it for rows with at least one product per bitmap word.
-  p->keep = (p->sr == 7 || p->rank) && p->sym_P == 1 && p->opt.bitmap_mib > 0 && p->op.k > 0;
+  p->keep = (p->sr == 7 || p->rank) && (p->sym_P == 1 || p->sym_win) && p->opt.bitmap_mib > 0 && p->op.k > 0;
   p->keep_nwords = (static_cast<int64_t>(p->op.k) + 31) / 32;
   p->keep_stride = (p->keep_nwords + 3) & ~int64_t(3);
   p->keep_min_flops = p->keep_nwords;
@@ -320,6 +342,13 @@ static spg_status plan_init(spg_plan* p, const spg_options* opt_in) {
     const int64_t budget = (static_cast<int64_t>(p->opt.seg_mib) << 20) / static_cast<int64_t>(seg_desc_bytes());
     p->seg_cap = std::min(bound, budget);
     off = align_up(off + static_cast<size_t>(p->seg_cap) * seg_desc_bytes());
+  }
+  // windowed symbolic: a count per (row, window) item and the slot flags
+  p->off_itemcnt = p->off_slotflag = off;
+  if (p->sym_win) {
+    off = align_up(off + static_cast<size_t>(m) * p->sym_P * sizeof(int32_t));
+    p->off_slotflag = off;
+    if (p->keep) off = align_up(off + static_cast<size_t>(m + 1) * sizeof(int64_t));
   }
   p->off_rcnt = off;
   if (p->rank) off = align_up(off + static_cast<size_t>(m) * p->rank_NC * sizeof(int32_t));
@@ -700,6 +729,22 @@ spg_status spg_symbolic(spg_plan* p, void* ws, int64_t* c_ptr, int64_t* c_nnz) {
       PhaseTimer tp(p, SPG_PHASE_SYM_PANELS);
       SPG_TRY_HIP(launch_panel_index(op.b_ptr, op.b_idx, op.n, p->sym_wlog2, p->sym_P, psym, s));
     }
+    PhaseTimer t(p, SPG_PHASE_SYM_DENSE);
+    if (p->sym_win) {
+      const int32_t* dense_rows = rows_sym + so.v[kDenseBinBase];
+      auto* row_slot = reinterpret_cast<int32_t*>(w + p->off_rowslot);
+      if (p->keep)
+        SPG_TRY_HIP(launch_keep_slots(dense_rows, ndense, flops, p->keep_min_flops, p->keep_cap,
+                                      reinterpret_cast<int64_t*>(w + p->off_slotflag), scan, row_slot, s));
+      SPG_TRY_HIP(launch_dense_sym_win(
+          op, dense_rows, ndense, p->sym_wlog2, p->sym_P, psym, p->opt.win_threads, p->opt.short_seg,
+          reinterpret_cast<int32_t*>(w + p->off_itemcnt), reinterpret_cast<unsigned int*>(ctr + kCtrWin), c_ptr,
+          p->rank ? p->rank_cw : 0, p->rank ? p->rank_NC : 0,
+          p->rank ? reinterpret_cast<int32_t*>(w + p->off_rcnt) : nullptr, p->keep ? row_slot : nullptr,
+          p->keep ? reinterpret_cast<uint32_t*>(w + p->off_store) : nullptr, p->keep_stride, p->opt.win_wgs, s));
+    }
+  }
+  if (ndense > 0 && !p->sym_win) {
     PhaseTimer t(p, SPG_PHASE_SYM_DENSE);
     KeepBitmaps kb{};
     if (p->keep) {

@@ -694,6 +694,130 @@ __global__ __launch_bounds__(1024) void k_dense_sym_b(const BatchDesc* __restric
   }
 }
 
+// ---------------------------------------------------------------------------
+// Windowed dense symbolic rows.  The columns are cut into P windows and the
+// work items are (row, window) pairs, taken from one queue per window.  A
+// workgroup starts on the queue of the XCD it runs on: the workgroups of one
+// XCD then gather from one column window of B, so the segments of the most
+// shared rows of B in that window stay in that XCD's L2 instead of every L2
+// holding all of them; a workgroup whose queue is empty takes items from the
+// other queues, so every item is done whatever the placement.  Per item: the
+// window's bitmap in LDS, its count, the counts of its rank chunks and its
+// words of the kept bitmap.
+// ---------------------------------------------------------------------------
+// XCD of the running wave (hardware register XCC_ID, bits 3:0).
+__device__ __forceinline__ int xcc_id() {
+  return static_cast<int>(__builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 7u);
+}
+
+// Next (list index, window) item for a workgroup, or it = -1 when every
+// queue is exhausted.  Thread 0 only; w and tried carry over between calls.
+__device__ __forceinline__ int64_t take_item(unsigned int* __restrict__ queue, int64_t nitems, int P, int& w,
+                                             int& tried) {
+  while (tried < P) {
+    const unsigned int v = atomicAdd(&queue[w], 1u);
+    if (static_cast<int64_t>(v) < nitems) return static_cast<int64_t>(v);
+    w = w + 1 == P ? 0 : w + 1;
+    ++tried;
+  }
+  return -1;
+}
+
+__global__ __launch_bounds__(1024) void k_dense_sym_win(Operands op, const int32_t* __restrict__ rows,
+                                                        int64_t nrows, int wlog2, int P,
+                                                        const int32_t* __restrict__ pidx, int short_seg,
+                                                        int32_t* __restrict__ item_cnt,
+                                                        unsigned int* __restrict__ queue, int sub_wlog2,
+                                                        int subP, int32_t* __restrict__ sub_cnt,
+                                                        const int32_t* __restrict__ keep_slot,
+                                                        uint32_t* __restrict__ keep_store, int64_t keep_nwords) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int64_t item_s;
+  __shared__ int win_s;
+  const int nt = blockDim.x;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x >> 6;
+  const int nw = nt >> 6;
+  auto q = PatQueue::carve(smem, nt);
+  uint32_t* bits = reinterpret_cast<uint32_t*>(smem + PatQueue::bytes(nt));
+  int w = xcc_id() % P, tried = 0;  // thread 0's queue cursor
+  for (;;) {
+    if (threadIdx.x == 0) {
+      item_s = take_item(queue, nrows, P, w, tried);
+      win_s = w;
+    }
+    __syncthreads();
+    const int64_t it = item_s;
+    const int p = win_s;
+    __syncthreads();  // item_s is rewritten by the next take
+    if (it < 0) break;
+    const int32_t row = uniform(rows[it]);
+    const int64_t a_lo = op.a_ptr[row], a_hi = op.a_ptr[row + 1];
+    const int32_t c0 = p << wlog2;
+    const int32_t wcols = min(1 << wlog2, op.k - c0);
+    const int nwords = (wcols + 31) >> 5;
+    for (int t = threadIdx.x; t < nwords; t += nt) bits[t] = 0u;
+    __syncthreads();
+    BitmapSink sink{bits};
+    enumerate_row<SrPattern>(op, a_lo, a_hi, P > 1, pidx, P, p, c0, short_seg, q, sink);
+    if (sub_cnt) {
+      // counts of the rank chunks (2^sub_wlog2 columns, nested in the window)
+      const int wps = 1 << (sub_wlog2 - 5);
+      const int s0 = c0 >> sub_wlog2;
+      const int nsub = (wcols + (1 << sub_wlog2) - 1) >> sub_wlog2;
+      for (int j = wid; j < nsub; j += nw) {
+        int c = 0;
+        for (int t = j * wps + lane; t < min((j + 1) * wps, nwords); t += kWave) c += __popc(bits[t]);
+        c = wave_sum(c);
+        if (lane == 0) sub_cnt[it * subP + s0 + j] = c;
+      }
+    }
+    uint32_t* keep = nullptr;
+    if (keep_slot) {
+      const int32_t sl = uniform(keep_slot[row]);
+      if (sl >= 0) keep = keep_store + static_cast<int64_t>(sl) * keep_nwords + (c0 >> 5);
+    }
+    int cnt = 0;
+    for (int t = threadIdx.x; t < nwords; t += nt) {
+      const uint32_t x = bits[t];
+      cnt += __popc(x);
+      if (keep) keep[t] = x;
+    }
+    const int total = block_sum(cnt, q.ctr + 2);
+    if (threadIdx.x == 0) item_cnt[it * P + p] = total;
+    __syncthreads();
+  }
+}
+
+// c_ptr[row + 1] = sum of the row's window counts.
+__global__ void k_sum_items(const int32_t* __restrict__ rows, int64_t nrows, int P,
+                            const int32_t* __restrict__ item_cnt, int64_t* __restrict__ c_ptr) {
+  const int64_t it = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (it >= nrows) return;
+  int64_t t = 0;
+  for (int p = 0; p < P; ++p) t += item_cnt[it * P + p];
+  c_ptr[rows[it] + 1] = t;
+}
+
+// Kept-bitmap slots in list order (the heaviest rows first): flag[it + 1] =
+// 1 for rows with at least min_flops products, then after an exclusive scan
+// of the flags (flag[it] = eligible rows before it) a row takes slot flag[it]
+// while slots are left.
+__global__ void k_slot_flags(const int32_t* __restrict__ rows, int64_t nrows, const int64_t* __restrict__ flops,
+                             int64_t min_flops, int64_t* __restrict__ flag) {
+  const int64_t it = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (it < nrows) flag[it + 1] = flops[rows[it]] >= min_flops ? 1 : 0;
+}
+__global__ void k_slot_assign(const int32_t* __restrict__ rows, int64_t nrows, const int64_t* __restrict__ flops,
+                              int64_t min_flops, const int64_t* __restrict__ pfx, int64_t capacity,
+                              int32_t* __restrict__ row_slot) {
+  const int64_t it = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (it >= nrows) return;
+  const int32_t row = rows[it];
+  const int64_t sl = pfx[it];
+  row_slot[row] = (flops[row] >= min_flops && sl < capacity) ? static_cast<int32_t>(sl) : -1;
+}
+
 static unsigned grid_for(int64_t items, int64_t cap) {
   return static_cast<unsigned>(cap > 0 && items > cap ? cap : items);
 }
@@ -712,6 +836,41 @@ hipError_t launch_dense_sym(const Operands& op, const int32_t* rows, int64_t nro
   if (nrows <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_dense_sym, dim3(grid_for(nrows, 0)), dim3(nt), dense_sym_lds(wlog2, nt), s, op,
                      rows, nrows, wlog2, P, pidx, short_seg, c_ptr, sub_wlog2, subP, sub_cnt, kb);
+  return hipGetLastError();
+}
+
+hipError_t launch_keep_slots(const int32_t* rows, int64_t nrows, const int64_t* flops, int64_t min_flops,
+                             int64_t capacity, int64_t* flag, int64_t* partials, int32_t* row_slot, hipStream_t s) {
+  if (nrows <= 0) return hipSuccess;
+  const unsigned nb = static_cast<unsigned>((nrows + 255) / 256);
+  hipLaunchKernelGGL(k_slot_flags, dim3(nb), dim3(256), 0, s, rows, nrows, flops, min_flops, flag);
+  hipError_t e = launch_scan_inplace(flag + 1, nrows, partials, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_slot_assign, dim3(nb), dim3(256), 0, s, rows, nrows, flops, min_flops, flag, capacity,
+                     row_slot);
+  return hipGetLastError();
+}
+
+hipError_t launch_dense_sym_win(const Operands& op, const int32_t* rows, int64_t nrows, int wlog2, int P,
+                                const int32_t* pidx, int nt, int short_seg, int32_t* item_cnt,
+                                unsigned int* queue, int64_t* c_ptr, int sub_wlog2, int subP, int32_t* sub_cnt,
+                                const int32_t* keep_slot, uint32_t* keep_store, int64_t keep_nwords,
+                                int wg_per_cu, hipStream_t s) {
+  if (nrows <= 0) return hipSuccess;
+  hipError_t e = launch_fill_u64(reinterpret_cast<uint64_t*>(queue), (P + 1) / 2, 0, s);
+  if (e != hipSuccess) return e;
+  int dev = 0, ncu = 256;
+  if (hipGetDevice(&dev) == hipSuccess)
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  const int64_t items = nrows * P;
+  const int64_t grid = std::min<int64_t>(items, static_cast<int64_t>(ncu) * std::max(1, wg_per_cu));
+  hipLaunchKernelGGL(k_dense_sym_win, dim3(static_cast<unsigned>(grid)), dim3(nt), dense_sym_lds(wlog2, nt), s,
+                     op, rows, nrows, wlog2, P, pidx, short_seg, item_cnt, queue, sub_wlog2, subP, sub_cnt,
+                     keep_slot, keep_store, keep_nwords);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_sum_items, dim3(static_cast<unsigned>((nrows + 255) / 256)), dim3(256), 0, s, rows, nrows,
+                     P, item_cnt, c_ptr);
   return hipGetLastError();
 }
 

@@ -145,6 +145,23 @@ hipError_t launch_dense_sym(const Operands& op, const int32_t* rows, int64_t nro
                             const int32_t* pidx, int nt, int short_seg, int64_t* c_ptr,
                             hipStream_t s, int sub_wlog2 = 0, int subP = 0, int32_t* sub_cnt = nullptr,
                             KeepBitmaps kb = KeepBitmaps{});
+// Windowed dense symbolic rows: (row, window) items over P windows of
+// 2^wlog2 columns, one queue per window (queue: P uint32, zeroed here), a
+// workgroup starting on its XCD's window; item_cnt[it * P + w] per item,
+// then c_ptr[row + 1] = the row's total.  sub_cnt (optional): counts of the
+// rank chunks of 2^sub_wlog2 columns, subP per row.  keep_slot (optional):
+// per row a kept-bitmap slot or -1, slots of keep_nwords words.  The grid is
+// wg_per_cu workgroups per compute unit.
+hipError_t launch_dense_sym_win(const Operands& op, const int32_t* rows, int64_t nrows, int wlog2, int P,
+                                const int32_t* pidx, int nt, int short_seg, int32_t* item_cnt,
+                                unsigned int* queue, int64_t* c_ptr, int sub_wlog2, int subP, int32_t* sub_cnt,
+                                const int32_t* keep_slot, uint32_t* keep_store, int64_t keep_nwords,
+                                int wg_per_cu, hipStream_t s);
+// Kept-bitmap slots for the rows of a list in list order: rows with at least
+// min_flops products take slots 0, 1, ... while capacity lasts, the others
+// -1.  flag: int64[nrows + 1] scratch; partials: scan partials.
+hipError_t launch_keep_slots(const int32_t* rows, int64_t nrows, const int64_t* flops, int64_t min_flops,
+                             int64_t capacity, int64_t* flag, int64_t* partials, int32_t* row_slot, hipStream_t s);
 hipError_t launch_expand_rows(const int32_t* rows, int64_t nrows, int nwords, int64_t stride, const uint32_t* store,
                               const int32_t* row_slot, const int64_t* c_ptr, int32_t* c_idx, int nt,
                               hipStream_t s);
