@@ -1,13 +1,16 @@
 """Parity at the full workload sizes, in the launch configurations that
 bench.py times.
 
-The outputs are too large for the oracle to recompute whole (R-MAT scale 20
-squared has 2.4e10 entries), so each test compares a seeded sample of output
-slices with the oracle computed for exactly those slices (its row/column
-selection), and checks properties that hold at any size over the whole
-output on the device: every slice sorted strictly ascending, ids in range,
-the two R-MAT semirings giving one pattern, value bounds, column sums of a
-column-stochastic square, prune counts.
+The outputs are too large for the oracle to hand over whole (R-MAT scale 20
+squared has 2.4e10 entries).  For the R-MAT square every output slice is
+compared through digests: the oracle formed every slice once, hashed it and
+stored the digests of blocks of 1024 slices (tests/golden), and the device
+result is hashed the same way here.  Each test also compares a seeded sample
+of output slices with the oracle computed for exactly those slices (its
+row/column selection), and checks properties that hold at any size over the
+whole output on the device: every slice sorted strictly ascending, ids in
+range, the two R-MAT semirings giving one pattern, value bounds, column sums
+of a column-stochastic square, prune counts.
 """
 import os
 
@@ -81,6 +84,53 @@ def rmat20():
     return A, oracle.flops(A, A)
 
 
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "rmat20_digests.json")
+
+
+def _golden(sr):
+    """Block digests of the whole R-MAT scale-20 square written by the
+    oracle (tests/golden/make_rmat20_digests.py), or None if absent."""
+    import json
+    if not os.path.exists(GOLDEN):
+        return None
+    with open(GOLDEN) as f:
+        rec = json.load(f)
+    g = rec["semirings"].get(sr)
+    if g is None:
+        return None
+    bh = np.array([int(x, 16) for x in g["block_hash"]], dtype=np.uint64)
+    return rec["block"], np.asarray(g["block_nnz"], np.int64), bh
+
+
+def _check_every_row(C, M, sr, nrows):
+    """Every output slice against the oracle: block digests of the device
+    result equal the oracle's; on a mismatch the first differing slice is
+    found and compared with the oracle's own computation of it."""
+    from tests import digest_util as D
+    g = _golden(sr)
+    if g is None:
+        return False
+    block, want_n, want_h = g
+    got_n, got_h = D.block_digests(C.ptr, C.idx, C.val, nrows, block=block)
+    assert got_n.size == want_n.size
+    bad = np.nonzero((got_n != want_n) | (got_h != want_h))[0]
+    if bad.size:
+        b = int(bad[0])
+        rows = np.arange(b * block, min(nrows, (b + 1) * block))
+        n, h = D.slice_digests(C.ptr, C.idx, C.val, int(rows[0]), int(rows[-1]) + 1)
+        on, oh = oracle.digest(M, M, sr, select=rows, nthreads=NTHREADS)
+        diff = np.nonzero((n.cpu().numpy() != on) | (h.cpu().numpy().view(np.uint64) != oh))[0]
+        r = int(rows[diff[0]]) if diff.size else -1
+        detail = ""
+        if r >= 0:
+            want = oracle.spgemm(M, M, sr, select=[r], nthreads=NTHREADS)
+            got = _fetch(C, np.array([r]))
+            detail = (f"; slice {r}: {got[1].size} entries on the device, {want[1].size} in the oracle, "
+                      f"ids equal: {np.array_equal(got[1], want[1])}")
+        raise AssertionError(f"{bad.size} of {want_n.size} blocks differ (first block {b}){detail}")
+    return True
+
+
 def test_rmat20_bool_and_min_plus(rmat20):
     import torch
 
@@ -101,6 +151,8 @@ def test_rmat20_bool_and_min_plus(rmat20):
     ptr_bool = C.ptr.cpu().numpy()
     got = _fetch(C, rows)
     _check_sorted_in_range(C, A.ncols)
+    full_b = _check_every_row(C, Hpat, "or_and_bool", A.nrows)
+    print(f"[fullsize] (OR,AND) every slice against the oracle's digests: {full_b}", flush=True)
     p.close()
     del C, p
     torch.cuda.empty_cache()
@@ -119,6 +171,8 @@ def test_rmat20_bool_and_min_plus(rmat20):
         assert int(v.min()) >= 2 and int(v.max()) <= 510
     got = _fetch(C, rows)
     _check_sorted_in_range(C, A.ncols)
+    full_m = _check_every_row(C, A, "min_plus_i32", A.nrows)
+    print(f"[fullsize] (min,+) every slice against the oracle's digests: {full_m}", flush=True)
     p.close()
     del C, p
     torch.cuda.empty_cache()
