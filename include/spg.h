@@ -377,6 +377,28 @@ spg_status spg_prune_apply_f32(const spg_matrix* C, float thresh, void* ws, void
 spg_status spg_prune_count_f32_noalloc(const spg_matrix* C, float thresh, void* stream, int64_t* new_ptr,
                                        int64_t* new_nnz);
 
+/* Selection (the Markov-clustering step that, with the prune, bounds the
+ * entries kept per column; paper Sec. 7.5: HipMCL iterates expansion,
+ * pruning and inflation, and keeps the output sparse around each
+ * expansion): every slice with more than S entries keeps the S with the
+ * largest values, ties going to the smaller id, values compared in float32
+ * with -0 < +0; shorter slices are kept whole; the kept entries stay in id
+ * order.  Two phases like the prune, with the same workspace
+ * (spg_prune_workspace_size).
+ *   C          float32 matrix in device memory (either layout), slices sorted
+ *              by id with no duplicates (the product's outputs are)
+ *   S          entries kept per slice, >= 0
+ *   new_ptr    device int64[nslices+1], written by the count phase
+ *   new_nnz    host, receives the kept count (synchronises the stream)
+ *   new_idx/new_val  device outputs of new_nnz entries
+ * Errors: SPG_E_INVALID (NULL outputs or workspace, S < 0, bad
+ * descriptor), SPG_E_SEMIRING (no values), SPG_E_DEVICE (a launch or the
+ * copy failed).  NaN values are undefined. */
+spg_status spg_select_count_f32(const spg_matrix* C, int64_t S, void* ws, void* stream, int64_t* new_ptr,
+                                int64_t* new_nnz);
+spg_status spg_select_apply_f32(const spg_matrix* C, int64_t S, void* ws, void* stream, const int64_t* new_ptr,
+                                int32_t* new_idx, float* new_val);
+
 /* Inflation (the Markov-clustering step after pruning, paper Sec. 7.5: the
  * HipMCL iteration is expansion, pruning, inflation): every slice's values
  * raised to the power r and divided by their sum, so each slice sums to 1

@@ -136,6 +136,10 @@ def load(path: str = LIB_PATH):
     L.spg_prune_count_f32.argtypes = [pm, ctypes.c_float, vp, vp, vp, ctypes.POINTER(i64)]
     L.spg_prune_apply_f32.restype = st
     L.spg_prune_apply_f32.argtypes = [pm, ctypes.c_float, vp, vp, vp, vp, vp]
+    L.spg_select_count_f32.restype = st
+    L.spg_select_count_f32.argtypes = [pm, i64, vp, vp, vp, ctypes.POINTER(i64)]
+    L.spg_select_apply_f32.restype = st
+    L.spg_select_apply_f32.argtypes = [pm, i64, vp, vp, vp, vp, vp]
     L.spg_prune_count_f32_noalloc.restype = st
     L.spg_prune_count_f32_noalloc.argtypes = [pm, ctypes.c_float, vp, vp, ctypes.POINTER(i64)]
     _declare_batch(L)
@@ -335,6 +339,18 @@ def spg_prune_count_f32_noalloc(C: spg_matrix, thresh: float, new_ptr, stream=No
     _check(load().spg_prune_count_f32_noalloc(ctypes.byref(C), float(thresh), _stream(stream), _addr(new_ptr),
                                               ctypes.byref(nnz)), "spg_prune_count_f32_noalloc")
     return int(nnz.value)
+
+
+def spg_select_count_f32(C: spg_matrix, S: int, ws, new_ptr, stream=None) -> int:
+    nnz = ctypes.c_int64()
+    _check(load().spg_select_count_f32(ctypes.byref(C), int(S), _addr(ws), _stream(stream), _addr(new_ptr),
+                                       ctypes.byref(nnz)), "spg_select_count_f32")
+    return int(nnz.value)
+
+
+def spg_select_apply_f32(C: spg_matrix, S: int, ws, new_ptr, new_idx, new_val, stream=None) -> None:
+    _check(load().spg_select_apply_f32(ctypes.byref(C), int(S), _addr(ws), _stream(stream), _addr(new_ptr),
+                                       _addr(new_idx), _addr(new_val)), "spg_select_apply_f32")
 
 
 def spg_prune_apply_f32(C: spg_matrix, thresh: float, ws, new_ptr, new_idx, new_val, stream=None) -> None:

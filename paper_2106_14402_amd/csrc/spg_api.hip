@@ -1103,6 +1103,36 @@ spg_status spg_prune_count_f32_noalloc(const spg_matrix* C, float thresh, void* 
   return prune_count(C, thresh, partials, static_cast<hipStream_t>(stream), new_ptr, new_nnz);
 }
 
+spg_status spg_select_count_f32(const spg_matrix* C, int64_t S, void* ws, void* stream, int64_t* new_ptr,
+                                int64_t* new_nnz) {
+  spg_status st = check_matrix(C);
+  if (st != SPG_OK) return st;
+  if (!new_ptr || !new_nnz || !ws || S < 0) return SPG_E_INVALID;
+  if (C->nnz > 0 && !C->val) return SPG_E_SEMIRING;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int64_t nmajor = C->layout == SPG_CSR ? C->nrows : C->ncols;
+  SPG_TRY_HIP(launch_select_count(C->ptr, nmajor, S, new_ptr, s));
+  SPG_TRY_HIP(launch_scan_inplace(new_ptr + 1, nmajor, static_cast<int64_t*>(ws), s));
+  int64_t total = 0;
+  SPG_TRY_HIP(hipMemcpyAsync(&total, new_ptr + nmajor, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  SPG_TRY_HIP(hipStreamSynchronize(s));
+  *new_nnz = total;
+  return SPG_OK;
+}
+
+spg_status spg_select_apply_f32(const spg_matrix* C, int64_t S, void* ws, void* stream, const int64_t* new_ptr,
+                                int32_t* new_idx, float* new_val) {
+  spg_status st = check_matrix(C);
+  if (st != SPG_OK) return st;
+  (void)ws;
+  if (!new_ptr || S < 0) return SPG_E_INVALID;
+  if (C->nnz > 0 && !C->val) return SPG_E_SEMIRING;
+  const int64_t nmajor = C->layout == SPG_CSR ? C->nrows : C->ncols;
+  SPG_TRY_HIP(launch_select_apply(C->ptr, C->idx, static_cast<const float*>(C->val), nmajor, S, new_ptr, new_idx,
+                                  new_val, static_cast<hipStream_t>(stream)));
+  return SPG_OK;
+}
+
 spg_status spg_inflate_f32(const spg_matrix* C, float r, float* val_out, void* stream) {
   spg_status st = check_matrix(C);
   if (st != SPG_OK) return st;

@@ -2171,6 +2171,130 @@ hipError_t launch_inflate(const int64_t* ptr, const float* val, int64_t nmajor, 
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Selection (the Markov-clustering step that bounds the entries kept per
+// column, paper Sec. 7.5): a slice longer than S keeps the S entries with the
+// largest values, ties going to the smaller id, in id order.  The order is
+// that of the 64-bit key (total-order key of the float32 value, -0 < +0) << 32
+// | (2^32 - 1 - id), unique within a slice.  The S-th largest key is found by
+// a radix select (eight passes of 8 bits over the slice, a histogram in LDS,
+// one workgroup per slice); the entries whose key is at least that large are
+// exactly the S kept ones, placed in order by a block scan of keep flags.
+// ---------------------------------------------------------------------------
+__global__ void k_select_count(const int64_t* __restrict__ ptr, int64_t nmajor, int64_t S,
+                               int64_t* __restrict__ cnt) {
+  const int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (s < nmajor) cnt[s] = min(ptr[s + 1] - ptr[s], S);
+}
+
+__device__ __forceinline__ uint64_t select_key(float v, int32_t id) {
+  return (static_cast<uint64_t>(f32_key(v)) << 32) | static_cast<uint64_t>(~static_cast<uint32_t>(id));
+}
+
+constexpr int kSelectThreads = 256;
+
+__global__ __launch_bounds__(kSelectThreads) void k_select_apply(const int64_t* __restrict__ ptr,
+                                                                 const int32_t* __restrict__ idx,
+                                                                 const float* __restrict__ val, int64_t nmajor,
+                                                                 int64_t S, const int64_t* __restrict__ new_ptr,
+                                                                 int32_t* __restrict__ new_idx,
+                                                                 float* __restrict__ new_val) {
+  __shared__ unsigned int hist[256];
+  __shared__ uint64_t prefix_s;
+  __shared__ int64_t need_s;
+  __shared__ int64_t tmp[16];
+  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & (kWave - 1);
+  for (int64_t s = blockIdx.x; s < nmajor; s += gridDim.x) {
+    const int64_t lo = ptr[s], hi = ptr[s + 1];
+    const int64_t out = new_ptr[s];
+    if (hi - lo <= S) {  // kept whole
+      for (int64_t p = lo + tid; p < hi; p += nt) {
+        new_idx[out + p - lo] = idx[p];
+        new_val[out + p - lo] = val[p];
+      }
+      continue;
+    }
+    if (S <= 0) continue;
+    // radix select of the S-th largest key, 8 bits per pass from the top
+    uint64_t prefix = 0;
+    int64_t need = S;  // rank, from the top, among the keys that match prefix
+    for (int shift = 56; shift >= 0; shift -= 8) {
+      for (int t = tid; t < 256; t += nt) hist[t] = 0u;
+      __syncthreads();
+      const uint64_t hmask = shift == 56 ? 0ull : (~0ull << (shift + 8));
+      for (int64_t p = lo + tid; p < hi; p += nt) {
+        const uint64_t k = select_key(val[p], idx[p]);
+        if ((k & hmask) == prefix) atomicAdd(&hist[(k >> shift) & 255u], 1u);
+      }
+      __syncthreads();
+      if (tid < kWave) {
+        // lane l holds digits 4l..4l+3; the digit of the need-th largest key
+        // lies in the lane whose digits' keys, with all keys of higher
+        // digits, first reach need
+        int64_t c = 0;
+        for (int j = 0; j < 4; ++j) c += hist[4 * lane + j];
+        const int64_t incl = wave_inclusive_scan(c);
+        const int64_t total = __shfl(incl, kWave - 1, kWave);
+        const int64_t above = total - incl;  // keys in higher lanes' digits
+        const bool here = above < need && need <= above + c;
+        const unsigned long long b = __ballot(here);
+        const int L = __ffsll(b) - 1;
+        if (lane == L) {
+          int64_t acc = above;
+          int d = 4 * lane + 3;
+          for (; d > 4 * lane; --d) {
+            if (acc + hist[d] >= need) break;
+            acc += hist[d];
+          }
+          prefix_s = prefix | (static_cast<uint64_t>(d) << shift);
+          need_s = need - acc;
+        }
+      }
+      __syncthreads();
+      prefix = prefix_s;
+      need = need_s;
+      __syncthreads();  // prefix_s and hist are rewritten by the next pass
+    }
+    // the S keys >= prefix, in slice order
+    int64_t base = out;
+    for (int64_t p0 = lo; p0 < hi; p0 += nt) {
+      const int64_t p = p0 + tid;
+      int64_t keep = 0;
+      int32_t id = 0;
+      float v = 0.0f;
+      if (p < hi) {
+        id = idx[p];
+        v = val[p];
+        keep = select_key(v, id) >= prefix ? 1 : 0;
+      }
+      int64_t tot;
+      const int64_t off = block_exclusive_scan(keep, tmp, &tot);
+      if (keep) {
+        new_idx[base + off] = id;
+        new_val[base + off] = v;
+      }
+      base += tot;
+    }
+  }
+}
+
+hipError_t launch_select_count(const int64_t* ptr, int64_t nmajor, int64_t S, int64_t* new_ptr, hipStream_t s) {
+  if (nmajor <= 0) return hipSuccess;
+  const int nt = 256;
+  hipLaunchKernelGGL(k_select_count, dim3(static_cast<unsigned>((nmajor + nt - 1) / nt)), dim3(nt), 0, s, ptr,
+                     nmajor, S, new_ptr + 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_select_apply(const int64_t* ptr, const int32_t* idx, const float* val, int64_t nmajor, int64_t S,
+                               const int64_t* new_ptr, int32_t* new_idx, float* new_val, hipStream_t s) {
+  if (nmajor <= 0) return hipSuccess;
+  const unsigned nb = static_cast<unsigned>(std::min<int64_t>(nmajor, 65536));
+  hipLaunchKernelGGL(k_select_apply, dim3(nb), dim3(kSelectThreads), 0, s, ptr, idx, val, nmajor, S, new_ptr,
+                     new_idx, new_val);
+  return hipGetLastError();
+}
+
 hipError_t launch_prune_count(const int64_t* ptr, const float* val, int64_t nmajor, float thresh,
                               int64_t* new_ptr, hipStream_t s) {
   if (nmajor <= 0) return hipSuccess;

@@ -240,6 +240,11 @@ size_t dense_sym_lds(int wlog2, int nt);
 size_t hash_sym_lds(int T, int nt);
 int max_lds_bytes();
 
+// Selection: new_ptr[s + 1] = min(nnz of slice s, S) (count), then the kept
+// entries of every slice (apply; new_ptr scanned).
+hipError_t launch_select_count(const int64_t* ptr, int64_t nmajor, int64_t S, int64_t* new_ptr, hipStream_t s);
+hipError_t launch_select_apply(const int64_t* ptr, const int32_t* idx, const float* val, int64_t nmajor, int64_t S,
+                               const int64_t* new_ptr, int32_t* new_idx, float* new_val, hipStream_t s);
 hipError_t launch_prune_count(const int64_t* ptr, const float* val, int64_t nmajor, float thresh,
                               int64_t* new_ptr, hipStream_t s);
 hipError_t launch_prune_apply(const int64_t* ptr, const int32_t* idx, const float* val,

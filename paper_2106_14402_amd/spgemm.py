@@ -244,3 +244,19 @@ def prune_f32(C: DeviceMatrix, thresh: float, stream=None) -> DeviceMatrix:
     new_val = torch.empty(nnz, dtype=torch.float32, device=dev)
     B_.spg_prune_apply_f32(d, thresh, ws, new_ptr, new_idx, new_val, stream)
     return DeviceMatrix(C.nrows, C.ncols, C.layout, new_ptr, new_idx, new_val)
+
+
+def select_f32(C: DeviceMatrix, S: int, stream=None) -> DeviceMatrix:
+    """Keep at most S entries per slice of a float32 matrix: the largest
+    values, ties to the smaller id, in id order."""
+    stream = stream if stream is not None else torch.cuda.current_stream(C.ptr.device)
+    d = C.descriptor()
+    dev = C.ptr.device
+    ws = torch.empty(max(1, B_.spg_prune_workspace_size(d)), dtype=torch.uint8, device=dev)
+    nmajor = C.nrows if C.layout == "csr" else C.ncols
+    new_ptr = torch.empty(nmajor + 1, dtype=torch.int64, device=dev)
+    nnz = B_.spg_select_count_f32(d, S, ws, new_ptr, stream)
+    new_idx = torch.empty(nnz, dtype=torch.int32, device=dev)
+    new_val = torch.empty(nnz, dtype=torch.float32, device=dev)
+    B_.spg_select_apply_f32(d, S, ws, new_ptr, new_idx, new_val, stream)
+    return DeviceMatrix(C.nrows, C.ncols, C.layout, new_ptr, new_idx, new_val)
