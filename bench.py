@@ -40,7 +40,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target host time of the oracle sample (0 disables)")
     ap.add_argument("--semirings", default="or_and_bool,min_plus_i32")
-    ap.add_argument("--workload", default="rmat", choices=["rmat", "er", "mcl", "batched", "served", "merge", "outbatch"],
+    ap.add_argument("--workload", default="rmat",
+                    choices=["rmat", "er", "mcl", "batched", "served", "merge", "outbatch", "calib", "counters"],
                     help="rmat (default) is the named benchmark workload; the others are the "
                          "remaining configurations, printed in the same JSON form")
     ap.add_argument("--batches", type=int, default=4, help="outbatch: output budget = nnz(C) / batches")
@@ -54,6 +55,13 @@ def parse():
                     help="workspace for symbolic bitmaps kept for the pattern-only numeric phase")
     ap.add_argument("--bitmap-mib-valued", type=int, default=28672,
                     help="workspace for symbolic bitmaps kept for the rank passes of the (min,+) product")
+    ap.add_argument("--select", type=int, default=1100, help="mcl: entries kept per column by the selection")
+    ap.add_argument("--counter-dirs", default="",
+                    help="counters: read-pass and write-pass rocprofv3 output directories of the workload, "
+                         "then those of the calibration run (comma separated)")
+    ap.add_argument("--counter-out", default=None, help="counters: summary JSON to write")
+    ap.add_argument("--counter-workload", default="rmat20", help="counters: workload name of the summary")
+    ap.add_argument("--counter-command", default="", help="counters: the profiled command, for the record")
     return ap.parse_args()
 
 
@@ -76,9 +84,8 @@ def kernel_sources_digest():
 
 def measured_traffic(kernel, workload):
     """HBM bytes per launch of ``kernel`` from the committed rocprofv3 counter
-    summary (FETCH_SIZE and WRITE_SIZE runs, each scaled by the same counter's
-    reading on a plain copy of known size), or None when there is no summary
-    for it or the kernel sources changed since it was taken."""
+    summary (request counts by size, see run_counters), or None when there is
+    no summary for it or the kernel sources changed since it was taken."""
     path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.json")
     try:
         with open(path) as f:
@@ -87,10 +94,180 @@ def measured_traffic(kernel, workload):
         return None
     if rec.get("sources_sha256") != kernel_sources_digest():
         return None
-    k = rec.get("kernels", {}).get(kernel)
+    ks = rec.get("kernels", {})
+    k = ks.get(kernel) or ks.get(kernel.split("<")[0])
     if not k:
         return None
-    return int(round(k["fetch_kib"] * 1024 / rec["fetch_factor"] + k["write_kib"] * 1024 / rec["write_factor"]))
+    return int(round(k["read_bytes"] + k["write_bytes"]))
+
+
+# Counters of the L2-to-memory requests (TCC_EA0_*), one rocprofv3 pass for
+# reads and one for writes (a pass holds at most four TCC counters).
+READ_COUNTERS = ["TCC_EA0_RDREQ_sum", "TCC_EA0_RDREQ_32B_sum", "TCC_EA0_RDREQ_64B_sum", "TCC_EA0_RDREQ_128B_sum"]
+WRITE_COUNTERS = ["TCC_EA0_WRREQ_sum", "TCC_EA0_WRREQ_64B_sum"]
+
+
+def request_bytes(c):
+    """HBM bytes of one dispatch from its request counts by size: read
+    requests of 32, 64 and 128 bytes (any remainder of RDREQ counted as 64),
+    write requests of 64 bytes (WRREQ_64B) and 32 bytes (the rest)."""
+    r, r32, r64, r128 = (c["TCC_EA0_RDREQ_sum"], c["TCC_EA0_RDREQ_32B_sum"], c["TCC_EA0_RDREQ_64B_sum"],
+                         c["TCC_EA0_RDREQ_128B_sum"])
+    w, w64 = c["TCC_EA0_WRREQ_sum"], c["TCC_EA0_WRREQ_64B_sum"]
+    rest = max(0.0, r - r32 - r64 - r128)
+    return 32 * r32 + 64 * (r64 + rest) + 128 * r128, 64 * w64 + 32 * (w - w64)
+
+
+def _counter_dispatches(dirs, short):
+    """Per kernel (short name), its dispatches in launch order, each a dict of
+    counter values plus 'ms', from the rocprofv3 counter-collection CSVs
+    under ``dirs`` (one profiled run per directory)."""
+    import csv
+    import glob
+    out = {}
+    for d in dirs:
+        per = {}
+        for path in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            with open(path) as f:
+                for r in csv.DictReader(f):
+                    k = short(r["Kernel_Name"])
+                    if k is None:
+                        continue
+                    e = per.setdefault(k, {}).setdefault(int(r["Dispatch_Id"]), {})
+                    e[r["Counter_Name"]] = float(r["Counter_Value"])
+                    e["ms"] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6
+        for k, ds in per.items():
+            lst = [ds[i] for i in sorted(ds)]
+            prev = out.setdefault(k, [])
+            if not prev:
+                prev.extend(dict(x) for x in lst)
+            else:  # the same dispatches in the other pass: merge counters in launch order
+                for x, y in zip(prev, lst):
+                    x.update({c: v for c, v in y.items() if c != "ms"})
+    return out
+
+
+def _mean_counters(dispatches):
+    keys = set().union(*[d.keys() for d in dispatches])
+    return {c: float(np.mean([d[c] for d in dispatches if c in d])) for c in keys}
+
+
+def _short_kernel_name(name):
+    """k_rank_num<min_plus_i32> style names for the library's kernels, the
+    calibration kernels by role, None for others."""
+    sr = {"SrMinPlusI32": "min_plus_i32", "SrPattern": "or_and_bool", "SrOrAndBool": "or_and_bool",
+          "SrPlusTimesF32": "plus_times_f32", "SrPlusTimesF64": "plus_times_f64", "SrMinPlusF32": "min_plus_f32",
+          "SrMaxTimesF64": "max_times_f64", "SrMaxTimesF32": "max_times_f32"}
+    if "spg::" in name:
+        base = name.split("spg::", 1)[1].split("(")[0].split("<")[0].strip()
+        for tag, nm in sr.items():
+            if tag in name:
+                fixed = base == "k_rank_num" and ", true>" in name
+                return f"{base}{'_fixed' if fixed else ''}<{nm}>"
+        return base
+    low = name.lower()
+    if "neg" in low:
+        return "calib_stream"
+    if "gather" in low or "index" in low:
+        return "calib_gather"
+    return None
+
+
+CALIB_WIDTHS = (32, 64, 128, 4096)
+
+
+def calib_rows(width):
+    """Rows gathered per dispatch: 2^22, at most 1 GiB of them."""
+    return min(1 << 22, (1 << 30) // width)
+
+
+def calib_known():
+    """Bytes per dispatch of the calibration kernels (run_calib): what they
+    must move, each gathered row read once with its int64 id."""
+    n = (1 << 30) // 4
+    known = {"calib_stream": {"read_bytes": 4 * n, "write_bytes": 4 * n}}
+    for w in CALIB_WIDTHS:
+        known[f"calib_gather{w}"] = {"read_bytes": calib_rows(w) * (w + 8), "write_bytes": calib_rows(w) * w}
+    return known
+
+
+def run_counters(args):
+    """Summary of two rocprofv3 counter runs of a workload (READ_COUNTERS,
+    then WRITE_COUNTERS) and of the same two runs over the calibration
+    workload: bytes per dispatch from request sizes, checked on the
+    calibration kernels against their known bytes."""
+    dirs = [d for d in args.counter_dirs.split(",") if d]
+    if len(dirs) != 4:
+        raise SystemExit("--counter-dirs needs: workload read dir, workload write dir, calib read dir, calib write dir")
+    need = READ_COUNTERS + WRITE_COUNTERS
+    kernels = {}
+    for k, ds in _counter_dispatches(dirs[:2], _short_kernel_name).items():
+        c = _mean_counters(ds)
+        if not all(x in c for x in need):
+            continue
+        rb, wb = request_bytes(c)
+        kernels[k] = {"read_bytes": rb, "write_bytes": wb, "avg_ms": round(c["ms"], 3), "dispatches": len(ds),
+                      **{x: c[x] for x in need}}
+    known = calib_known()
+    calib = {}
+    cal = _counter_dispatches(dirs[2:], _short_kernel_name)
+    groups = {"calib_stream": cal.get("calib_stream", [])}
+    g = cal.get("calib_gather", [])
+    per = len(g) // len(CALIB_WIDTHS) if g else 0
+    for j, w in enumerate(CALIB_WIDTHS):
+        groups[f"calib_gather{w}"] = g[j * per:(j + 1) * per]
+    for k, ds in groups.items():
+        if not ds:
+            continue
+        c = _mean_counters(ds)
+        if not all(x in c for x in need):
+            continue
+        rb, wb = request_bytes(c)
+        calib[k] = {"read_bytes": rb, "write_bytes": wb,
+                    "read_ratio": round(rb / known[k]["read_bytes"], 4),
+                    "write_ratio": round(wb / known[k]["write_bytes"], 4), **{x: c[x] for x in need}}
+    rec = {"workload": args.counter_workload, "command": args.counter_command,
+           "sources_sha256": kernel_sources_digest(),
+           "bytes": "read 32*RDREQ_32B + 64*RDREQ_64B + 128*RDREQ_128B (+ 64 per other RDREQ); "
+                    "write 64*WRREQ_64B + 32*(WRREQ - WRREQ_64B); per dispatch, mean over dispatches",
+           "calibration_known": known, "calibration_measured": calib, "kernels": kernels}
+    if args.counter_out:
+        with open(args.counter_out, "w") as f:
+            json.dump(rec, f, indent=1)
+    return rec
+
+
+def run_calib(args):
+    """Calibration kernels of known HBM bytes for the counter summaries: a
+    streaming float32 negation of 1 GiB (reads 1 GiB, writes 1 GiB), then row
+    gathers from a 4 GiB table (far larger than the caches) of random rows of
+    32, 64, 128 and 4096 bytes (2^22 rows, at most 1 GiB of them; reads the
+    rows and the int64 row ids, writes the rows), each launched ``--steps``
+    times."""
+    import torch
+    dev = torch.device("cuda:0")
+    reps = max(1, args.steps)
+    n = (1 << 30) // 4
+    x = torch.ones(n, dtype=torch.float32, device=dev)
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        torch.neg(x, out=y)
+    torch.cuda.synchronize()
+    del x, y
+    g = torch.Generator(device="cpu").manual_seed(5)
+    for width in CALIB_WIDTHS:
+        cols = width // 4
+        table = torch.zeros(((4 << 30) // width, cols), dtype=torch.float32, device=dev)
+        ids = torch.randint(0, table.shape[0], (calib_rows(width),), generator=g).to(dev)
+        out = torch.empty((calib_rows(width), cols), dtype=torch.float32, device=dev)
+        torch.cuda.synchronize()
+        for _ in range(reps):
+            torch.index_select(table, 0, ids, out=out)
+        torch.cuda.synchronize()
+        del table, ids, out
+        torch.cuda.empty_cache()
+    return {"workload": "calibration kernels of known bytes", "reps": reps, "known": calib_known()}
 
 
 def alg_bytes_dense(A, nnz_dense_rows_A, ndense_rows, nnz_c_dense, s_in, s_out, symbolic):
@@ -112,7 +289,8 @@ def main():
               f"(the product is a single-GPU kernel path)", file=sys.stderr)
         sys.exit(2)
     run = {"rmat": run_rmat, "er": run_er, "mcl": run_mcl, "batched": run_batched,
-           "served": run_served, "merge": run_merge, "outbatch": run_outbatch}[args.workload]
+           "served": run_served, "merge": run_merge, "outbatch": run_outbatch, "calib": run_calib,
+           "counters": run_counters}[args.workload]
     out = run(args)
     print(json.dumps(out), flush=True)
 
@@ -121,6 +299,61 @@ def base_record(args, value, unit, ms_per_step, dtype, config, higher=True):
     return {"metric": METRIC, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": higher,
             "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config}
+
+
+def row_flops(H):
+    """Products per output slice of H*H (oriented CSR arrays), from the host
+    copy of the operand (bookkeeping for the algorithmic bytes only)."""
+    deg = np.diff(H.ptr)
+    return np.bincount(np.repeat(np.arange(deg.size), deg), weights=deg[H.idx].astype(np.float64),
+                       minlength=deg.size), deg
+
+
+def dominant_kernel(H, phase, rownnz, p, s_in, s_out, sr):
+    """The longest launch of one product H*H among the library's kernels,
+    with its algorithmic HBM bytes: A's rows it covers and B read once, C's
+    entries of those rows written once (numeric) or the row sizes
+    (symbolic).  phase: the plan's phase times; rownnz: entries per slice."""
+    fl, deg = row_flops(H)
+    sym_dense_rows = fl > p.hash_max_flops()
+    hmn = p.hash_max_nnz()
+    ranked = phase.get("num_rank", 0.0) > 0
+    heavy = sym_dense_rows & (rownnz > hmn)
+    fixed_rows = heavy & (rownnz * p.rank_dense_div() >= H.ncols)
+    rank_rows = heavy & ~fixed_rows if ranked else np.zeros_like(sym_dense_rows)
+    # pattern-only products expand the rows whose symbolic bitmap was kept
+    # (at least one product per bitmap word; the budget is taken as enough)
+    kept = sym_dense_rows & (fl >= -(-H.ncols // 32)) if sr == "or_and_bool" and not ranked \
+        else np.zeros_like(sym_dense_rows)
+    num_dense_rows = (rownnz > hmn) & ~rank_rows & ~kept
+    hash_rows = (rownnz > 0) & (rownnz <= hmn) & ~kept
+
+    def num_bytes(rows):
+        return alg_bytes_dense(H, int(deg[rows].sum()), int(rows.sum()), int(rownnz[rows].sum()), s_in, s_out,
+                               False)
+    cands = {
+        "k_expand_rows": (phase.get("num_expand", 0.0), num_bytes(kept)),
+        "k_hash_num": (phase.get("num_hash", 0.0), num_bytes(hash_rows)),
+        "k_dense_num": (phase.get("num_dense", 0.0), num_bytes(num_dense_rows)),
+        "k_rank_num": (phase.get("num_rank", 0.0), num_bytes(rank_rows)),
+        "k_dense_sym": (phase.get("sym_dense", 0.0), alg_bytes_dense(
+            H, int(deg[sym_dense_rows].sum()), int(sym_dense_rows.sum()), 0, s_in, 0, True)),
+        "k_hash_sym": (phase.get("sym_hash", 0.0), alg_bytes_dense(
+            H, int(deg[~sym_dense_rows].sum()), int((~sym_dense_rows).sum()), 0, s_in, 0, True)),
+    }
+    dom = None
+    for name, (ms, by) in cands.items():
+        if ms > 0 and (dom is None or ms > dom["ms"]):
+            dom = {"kernel": name, "semiring": sr, "ms": ms, "bytes": by}
+    return dom
+
+
+def roofline_record(dom, workload):
+    achieved = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9
+    name = f"{dom['kernel']}<{dom['semiring']}>"
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(name, workload),
+            "kernel": name, "kernel_ms": round(dom["ms"], 3), "alg_bytes": int(dom["bytes"])}
 
 
 def run_rmat(args):
@@ -182,45 +415,14 @@ def run_rmat(args):
 
     # phase means and the dominant kernel
     phase_ms = {sr: {k: float(np.mean([r[k] for r in recs])) for k in recs[0]} for sr, recs in record.items()}
-    # per-row info for algorithmic bytes of dense launches
-    ptr_h = H.ptr
-    deg = np.diff(ptr_h)
     dom = None
     for sr, p in prods.items():
         p.symbolic(c_ptr)
-        sym_bins, num_bins = p.bins()
         rownnz = torch.diff(c_ptr).cpu().numpy()
-        # flops per row from the host copy of the operand (bookkeeping only)
-        fl = np.bincount(np.repeat(np.arange(H.nrows), deg), weights=deg[H.idx].astype(np.float64),
-                         minlength=H.nrows)
-        sym_dense_rows = fl > p.hash_max_flops()
-        ranked = phase_ms[sr].get("num_rank", 0.0) > 0
-        hmn = p.hash_max_nnz()
-        heavy = sym_dense_rows & (rownnz > hmn)
-        fixed_rows = heavy & (rownnz * p.rank_dense_div() >= H.ncols)
-        rank_rows = heavy & ~fixed_rows if ranked else np.zeros_like(sym_dense_rows)
-        num_dense_rows = (rownnz > hmn) & ~rank_rows
-
-        def dense_bytes(rows):
-            return alg_bytes_dense(H, int(deg[rows].sum()), int(rows.sum()), int(rownnz[rows].sum()),
-                                   s_in[sr], s_out[sr], False)
-        cands = {
-            "k_expand_rows": (phase_ms[sr].get("num_expand", 0.0), 0),
-            "k_hash_num": (phase_ms[sr].get("num_hash", 0.0), 0),
-            "k_dense_num": (phase_ms[sr].get("num_dense", 0.0), dense_bytes(num_dense_rows)),
-            "k_rank_num": (phase_ms[sr].get("num_rank", 0.0), dense_bytes(rank_rows)),
-            "k_dense_sym": (phase_ms[sr]["sym_dense"], alg_bytes_dense(
-                H, int(deg[sym_dense_rows].sum()), int(sym_dense_rows.sum()), 0, s_in[sr], 0, True)),
-        }
-        for name, (ms, by) in cands.items():
-            if dom is None or ms > dom["ms"]:
-                dom = {"kernel": name, "semiring": sr, "ms": ms, "bytes": by}
-    achieved = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(f"{dom['kernel']}<{dom['semiring']}>", f"rmat{args.scale}"),
-                "kernel": f"{dom['kernel']}<{dom['semiring']}>",
-                "kernel_ms": round(dom["ms"], 3), "alg_bytes": int(dom["bytes"])}
+        d = dominant_kernel(H, phase_ms[sr], rownnz, p, s_in[sr], s_out[sr], sr)
+        if dom is None or d["ms"] > dom["ms"]:
+            dom = d
+    roofline = roofline_record(dom, f"rmat{args.scale}")
     # whole-step compulsory bytes (two-phase, B cached): per product
     bmin = 0
     for sr in prods:
@@ -370,15 +572,21 @@ def run_mcl(args):
     ms = timed(step, args.steps, args.warmup)
     kept = state["P"].nnz
 
-    def iteration():  # the whole Markov-clustering iteration: expansion, prune, inflation (r = 2)
+    phase = {k: v for k, v in p.timings().items()}
+    rownnz = torch.diff(p.c_ptr).cpu().numpy()
+
+    def iteration():  # the whole Markov-clustering iteration: expansion, prune, selection, inflation (r = 2)
         step()
-        S.inflate_f32(state["P"], 2.0)
+        state["Q"] = S.select_f32(state["P"], args.select)
+        S.inflate_f32(state["Q"], 2.0)
     ms_it = timed(iteration, max(1, args.steps // 2), 1)
     out = base_record(args, round(2.0 * flops / (ms * 1e-3) / 1e9, 2), "GFLOP/s", ms, "f32",
                       {"workload": "MCL expansion n=2^20, lognormal column degree mean 48 (sigma 1), "
                                    "column-stochastic float32 CSC, C=A*A over (+,x) float32, prune < 1e-4",
-                       "n": A.ncols, "nnz_A": A.nnz, "flops": flops, "nnz_C": nnz, "nnz_pruned": kept})
-    out["phase_ms"] = {k: round(v, 3) for k, v in p.timings().items() if v > 0}
+                       "n": A.ncols, "nnz_A": A.nnz, "flops": flops, "nnz_C": nnz, "nnz_pruned": kept,
+                       "select": args.select, "nnz_selected": state["Q"].nnz})
+    out["roofline"] = roofline_record(dominant_kernel(A, phase, rownnz, p, 4, 4, "plus_times_f32"), "mcl")
+    out["phase_ms"] = {k: round(v, 3) for k, v in phase.items() if v > 0}
     out["iteration_ms"] = round(ms_it, 3)
     if args.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline_generic(A, "plus_times_f32", args.cpu_seconds)
