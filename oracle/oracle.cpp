@@ -122,6 +122,7 @@ struct Result : ResultBase {
     auto* v = static_cast<typename S::T*>(val);
     for (size_t r = 0; r < keys.size(); ++r) {
       if (ptr) ptr[r] = off;
+      if (keys[r].empty()) continue;  // memcpy takes no null pointer, even for 0 bytes
       if (idx) std::memcpy(idx + off, keys[r].data(), keys[r].size() * sizeof(int32_t));
       if (v) std::memcpy(v + off, vals[r].data(), vals[r].size() * sizeof(typename S::T));
       off += static_cast<int64_t>(keys[r].size());
