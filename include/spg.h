@@ -177,6 +177,12 @@ typedef struct spg_options {
                               (default 256) */
   int32_t win_wgs;         /* workgroups per compute unit of the windowed
                               kernels (default 8) */
+  int32_t pack_b;          /* (min,+) int32 rank passes: 0 (default) read B
+                              through one 32-bit word per entry (value <<
+                              bits | column) when every value of B lies in
+                              [0, 2^(32 - bits)) with bits = ceil(log2
+                              columns), else through 8-byte (column, value)
+                              pairs; -1 always through pairs */
 } spg_options;
 
 /* Phases reported by spg_plan_timings, in milliseconds. */

@@ -72,6 +72,7 @@ class spg_options(ctypes.Structure):
         ("sym_windows", ctypes.c_int32),
         ("win_threads", ctypes.c_int32),
         ("win_wgs", ctypes.c_int32),
+        ("pack_b", ctypes.c_int32),
     ]
 
 

@@ -105,7 +105,8 @@ constexpr int kCtrCursor = 2 * kNumBins;   // [64] scatter cursors
 constexpr int kCtrMisc = 3 * kNumBins;     // [0] total flops, [1] validation error bits
 constexpr int kCtrSub = 4 * kNumBins;      // [64] (row, panel) piece bin counts
 constexpr int kCtrWin = 5 * kNumBins;      // [64] window queues (uint32 each) of the windowed symbolic
-constexpr int kCtrWords = 6 * kNumBins;
+constexpr int kCtrRange = 6 * kNumBins;    // [0] smallest and largest int32 value of B (numeric)
+constexpr int kCtrWords = 7 * kNumBins;
 constexpr int kMaxWindows = 2 * kNumBins;
 
 spg_status from_hip(hipError_t e) { return e == hipSuccess ? SPG_OK : SPG_E_DEVICE; }
@@ -946,7 +947,27 @@ static spg_status numeric_range(spg_plan* p, void* ws, int32_t rb, int32_t re, i
   if (ranked) {
     PhaseTimer tp(p, SPG_PHASE_NUM_PANELS);
     SPG_TRY_HIP(launch_panel_index(op.b_ptr, op.b_idx, op.n, p->rank_cw, p->rank_NC, pchunk, s));
-    if (p->pair) {
+    bool packed = false;
+    if (p->pair && p->sr == SPG_MIN_PLUS_I32 && p->opt.pack_b >= 0 && p->b_nnz > 0) {
+      // int32 values that fit beside the column id in one word: half the
+      // bytes per product (the pair area holds the words)
+      const int bits = std::max(1, ilog2_ceil(op.k));
+      if (bits < 31) {
+        auto* mm = reinterpret_cast<int32_t*>(w + p->off_ctr) + 2 * kCtrRange;
+        int32_t hmm[2] = {0, 0};
+        SPG_TRY_HIP(launch_value_range(static_cast<const int32_t*>(op.b_val), p->b_nnz, mm, s));
+        SPG_TRY_HIP(hipMemcpyAsync(hmm, mm, sizeof(hmm), hipMemcpyDeviceToHost, s));
+        SPG_TRY_HIP(hipStreamSynchronize(s));
+        if (hmm[0] >= 0 && static_cast<int64_t>(hmm[1]) < (int64_t(1) << (32 - bits))) {
+          auto* bw = reinterpret_cast<uint32_t*>(w + p->off_bpair);
+          SPG_TRY_HIP(launch_pack_b(op, p->b_nnz, bits, bw, s));
+          opr.b_packed = bw;
+          opr.pack_bits = bits;
+          packed = true;
+        }
+      }
+    }
+    if (p->pair && !packed) {
       auto* bp = reinterpret_cast<int2*>(w + p->off_bpair);
       SPG_TRY_HIP(launch_interleave_b(op, p->b_nnz, bp, s));
       opr.b_pair = bp;

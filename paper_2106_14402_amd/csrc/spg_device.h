@@ -149,6 +149,12 @@ struct Operands {
   // Optional copy of B with (column id, value bits) side by side, for
   // 4-byte values: one load per product instead of two.  NULL: unused.
   const int2* b_pair;
+  // Optional copy of B with each int32 value and column id in one 32-bit
+  // word, value << pack_bits | column, for values in [0, 2^(32 - pack_bits))
+  // and fewer than 2^pack_bits columns: half the bytes of b_pair per
+  // product.  NULL: unused.
+  const uint32_t* b_packed;
+  int32_t pack_bits;
 };
 
 // ---------------------------------------------------------------------------
@@ -353,16 +359,48 @@ struct IsPairedB<SR, decltype(void(SR::kPairedB))> {
   static constexpr bool value = SR::kPairedB;
 };
 
+// A semiring whose kernels read B through Operands::b_packed (int32 values
+// that fit beside the column id in one word).
+template <class SR>
+struct PackedB : SR {
+  static_assert(!SR::kPattern && sizeof(typename SR::In) == 4, "packed words hold small int32 values");
+  static constexpr bool kPackedB = true;
+};
+template <class SR, class = void>
+struct IsPackedB {
+  static constexpr bool value = false;
+};
+template <class SR>
+struct IsPackedB<SR, decltype(void(SR::kPackedB))> {
+  static constexpr bool value = SR::kPackedB;
+};
+
 // Column id and value of B entry q.
 template <class SR>
 __device__ __forceinline__ void load_b(const Operands& op, int64_t q, int32_t& col, typename SR::In& v) {
-  if constexpr (IsPairedB<SR>::value) {
+  if constexpr (IsPackedB<SR>::value) {
+    // the raw word; decode_b splits it where the product is combined, so
+    // the load is not waited for where it is issued
+    col = static_cast<int32_t>(op.b_packed[q]);
+    v = 0;
+  } else if constexpr (IsPairedB<SR>::value) {
     const int2 pr = op.b_pair[q];
     col = pr.x;
     v = __builtin_bit_cast(typename SR::In, pr.y);
   } else {
     col = op.b_idx[q];
     v = load_val<SR>(op.b_val, q);
+  }
+}
+
+// Column id and value of a loaded B entry (load_b's registers), at the
+// point of use: splits a packed word, nothing for the other forms.
+template <class SR>
+__device__ __forceinline__ void decode_b(const Operands& op, int32_t& col, typename SR::In& v) {
+  if constexpr (IsPackedB<SR>::value) {
+    const uint32_t x = static_cast<uint32_t>(col);
+    col = static_cast<int32_t>(x & ((1u << op.pack_bits) - 1u));
+    v = static_cast<typename SR::In>(x >> op.pack_bits);
   }
 }
 
@@ -453,7 +491,10 @@ __device__ void enumerate_src(const Operands& op, const Src& src, int32_t c0, in
             if (es[u] >= 0) load_b<SR>(op, q.lo[es[u]] + (j0 + u * nt + tid - q.pfx[es[u]]), cols[u], bv[u]);
 #pragma unroll
           for (int u = 0; u < kFU; ++u)
-            if (es[u] >= 0) sink.add(cols[u] - c0, SR::mul(q.a[es[u]], bv[u]));
+            if (es[u] >= 0) {
+              decode_b<SR>(op, cols[u], bv[u]);
+              sink.add(cols[u] - c0, SR::mul(q.a[es[u]], bv[u]));
+            }
         }
         __syncthreads();  // the queue arrays are rewritten by the next round
         continue;
@@ -477,7 +518,10 @@ __device__ void enumerate_src(const Operands& op, const Src& src, int32_t c0, in
         }
 #pragma unroll
         for (int u = 0; u < kShortUnroll; ++u)
-          if (t + u < len) sink.add(cols[u] - c0, SR::mul(a, bv[u]));
+          if (t + u < len) {
+            decode_b<SR>(op, cols[u], bv[u]);
+            sink.add(cols[u] - c0, SR::mul(a, bv[u]));
+          }
       }
     }
     __syncthreads();
@@ -523,7 +567,12 @@ __device__ void enumerate_src(const Operands& op, const Src& src, int32_t c0, in
 #pragma unroll
         for (int r = 0; r < kPU; ++r) {
           const int64_t qq = b.s0 + r * kWave + lane;
-          if (qq < b.s1) sink.add(b.cols[r] - c0, SR::mul(b.ae, b.bv[r]));
+          if (qq < b.s1) {
+            int32_t c = b.cols[r];
+            In v = b.bv[r];
+            decode_b<SR>(op, c, v);
+            sink.add(c - c0, SR::mul(b.ae, v));
+          }
         }
       };
       if constexpr (kBufs == 1) {
@@ -555,7 +604,10 @@ __device__ void enumerate_src(const Operands& op, const Src& src, int32_t c0, in
 #pragma unroll
           for (int r = 0; r < kPU; ++r) {
             const int64_t qq = s0 + r * kWave + lane;
-            if (qq < s1) sink.add(cols[r] - c0, SR::mul(ae, bv[r]));
+            if (qq < s1) {
+              decode_b<SR>(op, cols[r], bv[r]);
+              sink.add(cols[r] - c0, SR::mul(ae, bv[r]));
+            }
           }
         }
       } else if (const int u0 = take(); u0 < ptotal) {

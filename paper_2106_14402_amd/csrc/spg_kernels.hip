@@ -18,6 +18,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <type_traits>
 
 #include "spg_launch.h"
 #include "spg_rowlogic.h"
@@ -369,6 +370,55 @@ hipError_t launch_interleave_b(const Operands& op, int64_t nnz, int2* out, hipSt
   const int64_t nb = std::min<int64_t>((nnz + 255) / 256, 65536);
   hipLaunchKernelGGL(k_interleave_b, dim3(static_cast<unsigned>(nb)), dim3(256), 0, s, op.b_idx,
                      static_cast<const uint32_t*>(op.b_val), nnz, out);
+  return hipGetLastError();
+}
+
+// Smallest and largest of n int32 values into mm[0], mm[1] (initialised by
+// the caller to INT32_MAX and INT32_MIN).
+__global__ void k_value_range(const int32_t* __restrict__ v, int64_t n, int32_t* mm) {
+  int32_t lo = INT32_MAX, hi = INT32_MIN;
+  for (int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; q < n;
+       q += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int32_t x = v[q];
+    lo = min(lo, x);
+    hi = max(hi, x);
+  }
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) {
+    lo = min(lo, __shfl_xor(lo, d, kWave));
+    hi = max(hi, __shfl_xor(hi, d, kWave));
+  }
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    atomicMin(&mm[0], lo);
+    atomicMax(&mm[1], hi);
+  }
+}
+
+__global__ void k_mm_init(int32_t* mm) {
+  mm[0] = INT32_MAX;
+  mm[1] = INT32_MIN;
+}
+
+hipError_t launch_value_range(const int32_t* v, int64_t n, int32_t* mm, hipStream_t s) {
+  hipLaunchKernelGGL(k_mm_init, dim3(1), dim3(1), 0, s, mm);
+  if (n > 0) {
+    const unsigned nb = static_cast<unsigned>(std::min<int64_t>((n + 255) / 256, 4096));
+    hipLaunchKernelGGL(k_value_range, dim3(nb), dim3(256), 0, s, v, n, mm);
+  }
+  return hipGetLastError();
+}
+
+// One word per entry of B: value << bits | column id (values checked to fit).
+__global__ void k_pack_b(const int32_t* __restrict__ idx, const int32_t* __restrict__ val, int64_t n, int bits,
+                         uint32_t* __restrict__ out) {
+  const int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q < n) out[q] = (static_cast<uint32_t>(val[q]) << bits) | static_cast<uint32_t>(idx[q]);
+}
+
+hipError_t launch_pack_b(const Operands& op, int64_t nnz, int bits, uint32_t* out, hipStream_t s) {
+  if (nnz <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pack_b, dim3(static_cast<unsigned>((nnz + 255) / 256)), dim3(256), 0, s, op.b_idx,
+                     static_cast<const int32_t*>(op.b_val), nnz, bits, out);
   return hipGetLastError();
 }
 
@@ -1904,7 +1954,19 @@ static hipError_t rank_num_t(bool fixed, const Operands& op, const int32_t* rows
   if (nrows <= 0) return hipSuccess;
   if constexpr (SR::kPattern) {
     return hipErrorInvalidValue;  // pattern-only rows use the bitmap paths
-  } else if constexpr (sizeof(typename SR::In) == 4 && !IsPairedB<SR>::value) {
+  } else if constexpr (std::is_same<SR, SrMinPlusI32>::value) {
+    if (op.b_packed)  // B is read through one word per entry (small values)
+      return rank_num_t<PackedB<SR>>(fixed, op, rows, nrows, rb, re, cw, NC, sh, pchunk, rcnt, nnz_lo,
+                                     nnz_hi, wlog2, P, nt, short_seg, keep_store, keep_slot, keep_nwords,
+                                     c_ptr, c_idx, c_val, s);
+    if (op.b_pair)
+      return rank_num_t<PairedB<SR>>(fixed, op, rows, nrows, rb, re, cw, NC, sh, pchunk, rcnt, nnz_lo,
+                                     nnz_hi, wlog2, P, nt, short_seg, keep_store, keep_slot, keep_nwords,
+                                     c_ptr, c_idx, c_val, s);
+    return rank_num_launch<SR>(fixed, op, rows, nrows, rb, re, cw, NC, sh, pchunk, rcnt, nnz_lo,
+                               nnz_hi, wlog2, P, nt, short_seg, keep_store, keep_slot, keep_nwords, c_ptr,
+                               c_idx, c_val, s);
+  } else if constexpr (sizeof(typename SR::In) == 4 && !IsPairedB<SR>::value && !IsPackedB<SR>::value) {
     if (op.b_pair)  // B is read through its (column id, value) pairs
       return rank_num_t<PairedB<SR>>(fixed, op, rows, nrows, rb, re, cw, NC, sh, pchunk, rcnt, nnz_lo,
                                      nnz_hi, wlog2, P, nt, short_seg, keep_store, keep_slot, keep_nwords,

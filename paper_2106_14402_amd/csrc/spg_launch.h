@@ -135,6 +135,10 @@ hipError_t launch_inflate(const int64_t* ptr, const float* val, int64_t nmajor, 
 hipError_t launch_selector(int32_t m, int k, int64_t* ptr, int32_t* idx, void* val, int sr, hipStream_t s);
 // (column id, value bits) pairs of B's entries, for 4-byte values.
 hipError_t launch_interleave_b(const Operands& op, int64_t nnz, int2* out, hipStream_t s);
+// Smallest and largest of n int32 values into mm[0..1] (device).
+hipError_t launch_value_range(const int32_t* v, int64_t n, int32_t* mm, hipStream_t s);
+// One word per entry of B (int32 values): value << bits | column id.
+hipError_t launch_pack_b(const Operands& op, int64_t nnz, int bits, uint32_t* out, hipStream_t s);
 // In-place inclusive scan of x[0..len); then x[-1] = 0 (x points one past a
 // leading slot).  partials: ceil(len / kScanTile) + 1 int64.
 hipError_t launch_scan_inplace(int64_t* x, int64_t len, int64_t* partials, hipStream_t s);

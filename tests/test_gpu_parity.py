@@ -323,3 +323,26 @@ def test_error_codes():
     C = S.spgemm(dA, dA, "min_plus_i32", options=opts(validate=1))  # valid input passes validation
     torch.cuda.synchronize()
     assert C.nnz > 0
+
+
+@pytest.mark.parametrize("case", ["packed_at_limit", "pairs_past_limit", "pairs_negative", "pairs_forced"])
+def test_rank_passes_packed_words_and_pairs(case):
+    """(min,+) int32 rank passes read B through one 32-bit word per entry
+    when every value fits beside the column id (5000 columns: 13 id bits,
+    values below 2^19), else through 8-byte pairs; both give the oracle's
+    product."""
+    rng = np.random.default_rng(41)
+    A = _skewed(5000, 10, 4)
+    v = rng.integers(0, 1 << 19, size=A.nnz).astype(np.int32)
+    if case == "packed_at_limit":
+        v[rng.integers(0, A.nnz, 20)] = (1 << 19) - 1
+    elif case == "pairs_past_limit":
+        v[rng.integers(0, A.nnz, 3)] = 1 << 19
+    elif case == "pairs_negative":
+        v[rng.integers(0, A.nnz, 3)] = -5
+    A = A.with_values(v)
+    o = dict(hash_max_flops=32, hash_max_nnz=32, lds_budget=1024, dense_threads=256, bitmap_mib=1)
+    if case == "pairs_forced":
+        o["pack_b"] = -1
+    got = run_gpu(A, A, "min_plus_i32", opts(**o))
+    assert_parity(A, A, "min_plus_i32", got)
