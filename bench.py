@@ -326,7 +326,9 @@ def dominant_kernel(H, phase, rownnz, p, s_in, s_out, sr):
     kept = sym_dense_rows & (fl >= -(-H.ncols // 32)) if sr == "or_and_bool" and not ranked \
         else np.zeros_like(sym_dense_rows)
     num_dense_rows = (rownnz > hmn) & ~rank_rows & ~kept
-    hash_rows = (rownnz > 0) & (rownnz <= hmn) & ~kept
+    o = p.options()
+    esc_rows = (rownnz > 0) & ~kept & (fl <= max(0, o.esc_max_flops)) & (16 * fl <= o.esc_ratio_x16 * rownnz)
+    hash_rows = (rownnz > 0) & (rownnz <= hmn) & ~kept & ~esc_rows
 
     def num_bytes(rows):
         return alg_bytes_dense(H, int(deg[rows].sum()), int(rows.sum()), int(rownnz[rows].sum()), s_in, s_out,
@@ -334,6 +336,7 @@ def dominant_kernel(H, phase, rownnz, p, s_in, s_out, sr):
     cands = {
         "k_expand_rows": (phase.get("num_expand", 0.0), num_bytes(kept)),
         "k_hash_num": (phase.get("num_hash", 0.0), num_bytes(hash_rows)),
+        "k_esc_num": (phase.get("num_esc", 0.0), num_bytes(esc_rows)),
         "k_dense_num": (phase.get("num_dense", 0.0), num_bytes(num_dense_rows)),
         "k_rank_num": (phase.get("num_rank", 0.0), num_bytes(rank_rows)),
         "k_dense_sym": (phase.get("sym_dense", 0.0), alg_bytes_dense(

@@ -183,6 +183,12 @@ typedef struct spg_options {
                               [0, 2^(32 - bits)) with bits = ceil(log2
                               columns), else through 8-byte (column, value)
                               pairs; -1 always through pairs */
+  int32_t esc_max_flops;   /* numeric phase: rows of at most this many
+                              products (up to 4096; 0 = 4096, -1 = never)
+                              whose compression ratio flops / nnz is at most
+                              esc_ratio_x16 / 16 are expanded, sorted and
+                              compressed in LDS instead of hashed */
+  int32_t esc_ratio_x16;   /* 16 x that compression ratio (default 20: 1.25) */
 } spg_options;
 
 /* Phases reported by spg_plan_timings, in milliseconds. */
@@ -200,7 +206,8 @@ enum {
   SPG_PHASE_SEG_COUNT = 10,  /* symbolic, segment counts of (row, panel) pieces */
   SPG_PHASE_SEG_WRITE = 11,  /* numeric, segment lists of (row, panel) pieces */
   SPG_PHASE_NUM_RANK = 12,   /* numeric, heavy valued rows by rank-compressed panels */
-  SPG_NUM_PHASES = 13
+  SPG_PHASE_NUM_ESC = 13,    /* numeric, expand-sort-compress rows */
+  SPG_NUM_PHASES = 14
 };
 
 typedef struct spg_plan spg_plan;

@@ -73,6 +73,8 @@ class spg_options(ctypes.Structure):
         ("win_threads", ctypes.c_int32),
         ("win_wgs", ctypes.c_int32),
         ("pack_b", ctypes.c_int32),
+        ("esc_max_flops", ctypes.c_int32),
+        ("esc_ratio_x16", ctypes.c_int32),
     ]
 
 
@@ -262,7 +264,7 @@ def spg_plan_stats(plan):
 
 
 PHASES = ["validate", "flops_bin", "sym_hash", "sym_dense", "scan", "num_hash", "num_dense",
-          "sym_panels", "num_panels", "num_expand", "seg_count", "seg_write", "num_rank"]
+          "sym_panels", "num_panels", "num_expand", "seg_count", "seg_write", "num_rank", "num_esc"]
 
 
 def spg_plan_timings(plan) -> dict:

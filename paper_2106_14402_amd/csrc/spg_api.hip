@@ -158,6 +158,8 @@ void resolve_options(const spg_options* in, spg_options* o, int sr) {
   if (o->rank_shapes <= 0 || o->rank_shapes > kRankShapes) o->rank_shapes = kRankShapes;
   if (o->win_threads <= 0) o->win_threads = 256;
   if (o->win_wgs <= 0) o->win_wgs = 8;
+  if (o->esc_max_flops == 0) o->esc_max_flops = kEscMaxFlops;
+  if (o->esc_ratio_x16 <= 0) o->esc_ratio_x16 = 20;
 }
 
 spg_status check_options(const spg_options& o, int sr) {
@@ -167,6 +169,7 @@ spg_status check_options(const spg_options& o, int sr) {
   if (o.sym_panel_log2 < 7 || o.sym_panel_log2 > 20) return SPG_E_INVALID;
   if (o.sym_windows < 0 || o.sym_windows > kMaxWindows) return SPG_E_INVALID;
   if (o.win_threads % kWave != 0 || o.win_threads > 1024 || o.win_wgs > 32) return SPG_E_INVALID;
+  if (o.esc_max_flops > kEscMaxFlops) return SPG_E_INVALID;
   // hash tables must fit in LDS
   const int csym = hash_class(o.hash_max_flops);
   if (hash_sym_lds(hash_table_size(csym), hash_threads(csym)) > static_cast<size_t>(max_lds_bytes()))
@@ -239,6 +242,10 @@ static spg_status plan_init(spg_plan* p, const spg_options* opt_in) {
   p->split = p->opt.split_panels > 0 && p->sr != 7 && p->num_P > 1 && p->sym_wlog2 >= p->num_wlog2 &&
              static_cast<int64_t>(p->op.m) * p->num_P < (int64_t(1) << 31);
   p->bp.split_heavy = p->split ? 1 : 0;
+  // Expand-sort-compress for rows of at most esc_max_flops products whose
+  // compression ratio flops/nnz is at most esc_ratio_x16 / 16.
+  p->bp.esc_max_flops = (p->split || p->opt.esc_max_flops < 0) ? 0 : p->opt.esc_max_flops;
+  p->bp.esc_ratio_x16 = p->opt.esc_ratio_x16;
 
   // Rank-compressed panels: chunks of 2^cw columns, with 2^cw value slots
   // (half the LDS budget, at most 64 KiB) and a bitmap of as many chunks as
@@ -880,9 +887,9 @@ static spg_status numeric_range(spg_plan* p, void* ws, int32_t rb, int32_t re, i
   const Operands& op = p->op;
   const BinOffsets no = offsets_of(p->num_counts);
   int64_t ndense = 0;
-  for (int b = kDenseBinBase; b < kNumBins; ++b) ndense += static_cast<int64_t>(p->num_counts[b]);
+  for (int b = kDenseBinBase; b < kEscBinBase; ++b) ndense += static_cast<int64_t>(p->num_counts[b]);
   p->ran[SPG_PHASE_NUM_HASH] = p->ran[SPG_PHASE_NUM_DENSE] = p->ran[SPG_PHASE_NUM_PANELS] = false;
-  p->ran[SPG_PHASE_NUM_EXPAND] = p->ran[SPG_PHASE_NUM_RANK] = false;
+  p->ran[SPG_PHASE_NUM_EXPAND] = p->ran[SPG_PHASE_NUM_RANK] = p->ran[SPG_PHASE_NUM_ESC] = false;
   const bool sub = p->split && p->n_dense_sym > 0;
   const BinOffsets sbo = offsets_of(p->sub_counts);
   int64_t nsub_dense = 0;
@@ -931,6 +938,14 @@ static spg_status numeric_range(spg_plan* p, void* ws, int32_t rb, int32_t re, i
                                           hash_threads_num(c, p->sr), p->opt.short_seg, p->num_P, p->num_wlog2, pnum,
                                           subcnt, suboff, wend, p->c_ptr, c_idx, c_val, s));
       }
+    }
+  }
+  if (p->bp.esc_max_flops > 0) {
+    PhaseTimer t(p, SPG_PHASE_NUM_ESC);
+    for (int b = kEscBinBase; b < kNumBins; ++b) {
+      if (!p->num_counts[b]) continue;
+      SPG_TRY_HIP(launch_esc_num(p->sr, op, rows_num + no.v[b], static_cast<int64_t>(p->num_counts[b]),
+                                 32 << (b - kEscBinBase), p->c_ptr, c_idx, c_val, s));
     }
   }
   if (p->num_counts[kExpandBin]) {

@@ -344,6 +344,8 @@ spg_status spg_batch_plan_create(int nprod, const spg_matrix* A, const spg_matri
   p->bp.hash_max_flops = p->opt.hash_max_flops;
   p->bp.hash_max_nnz = p->opt.hash_max_nnz;
   p->bp.split_heavy = 0;
+  p->bp.esc_max_flops = 0;  // no expand-sort-compress classes in the batched kernels
+  p->bp.esc_ratio_x16 = 0;
   p->desc.resize(nprod);
   p->slot_of.resize(nprod);
   p->row_off.assign(nprod + 1, 0);

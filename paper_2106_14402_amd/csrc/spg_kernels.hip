@@ -1259,6 +1259,104 @@ __device__ void bitonic_sort(int32_t* keys, S* vals, int N, bool with_vals) {
   __syncthreads();
 }
 
+// Bitonic sort of N = 4 * blockDim.x (key, value) pairs held four per thread
+// in registers (element e = 4 * thread + r): the compare-exchanges at
+// distance 1 and 2 stay inside a thread, those at distance 4 to 128 inside a
+// wave (cross-lane shuffles), and only those at distance 256 and more go
+// through LDS with a workgroup barrier.  keys/vals: the N pairs in LDS on
+// entry (after a barrier) and, sorted ascending by key, on exit.
+template <class S, bool kVals>
+__device__ void bitonic_sort_reg4(int32_t* keys, S* vals, int N) {
+  const int tid = threadIdx.x;
+  const int e0 = 4 * tid;
+  int32_t k[4];
+  S v[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    k[r] = keys[e0 + r];
+    if constexpr (kVals) v[r] = vals[e0 + r];
+  }
+  for (int kk = 2; kk <= N; kk <<= 1) {
+    int j = kk >> 1;
+    if (j >= 256) {
+      __syncthreads();  // the previous reads of keys/vals are done
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        keys[e0 + r] = k[r];
+        if constexpr (kVals) vals[e0 + r] = v[r];
+      }
+      __syncthreads();
+      for (; j >= 256; j >>= 1) {
+        if ((e0 & j) == 0) {  // this thread's four elements are the lower ends of their pairs
+          const bool up = (e0 & kk) == 0;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int a = e0 + r, b = a + j;
+            const int32_t ka = keys[a], kb = keys[b];
+            if ((ka > kb) == up) {
+              keys[a] = kb;
+              keys[b] = ka;
+              if constexpr (kVals) {
+                const S t = vals[a];
+                vals[a] = vals[b];
+                vals[b] = t;
+              }
+            }
+          }
+        }
+        __syncthreads();
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        k[r] = keys[e0 + r];
+        if constexpr (kVals) v[r] = vals[e0 + r];
+      }
+    }
+    const bool up = (e0 & kk) == 0;  // the same for the four elements (kk >= 2... see below)
+    for (; j >= 4; j >>= 1) {
+      const int lm = j >> 2;
+      const bool lower = (e0 & j) == 0;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int32_t pk = __shfl_xor(k[r], lm, kWave);
+        S pv{};
+        if constexpr (kVals) pv = __shfl_xor(v[r], lm, kWave);
+        const int32_t klo = lower ? k[r] : pk, khi = lower ? pk : k[r];
+        if ((klo > khi) == up) {
+          k[r] = pk;
+          if constexpr (kVals) v[r] = pv;
+        }
+      }
+    }
+    for (; j >= 1; j >>= 1) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if ((r & j) == 0) {
+          const int r2 = r | j;
+          const bool upr = ((e0 + r) & kk) == 0;
+          if ((k[r] > k[r2]) == upr) {
+            const int32_t t = k[r];
+            k[r] = k[r2];
+            k[r2] = t;
+            if constexpr (kVals) {
+              const S tv = v[r];
+              v[r] = v[r2];
+              v[r2] = tv;
+            }
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    keys[e0 + r] = k[r];
+    if constexpr (kVals) vals[e0 + r] = v[r];
+  }
+  __syncthreads();
+}
+
 constexpr int kMaxSlotsPerThread = 16;
 
 // LDS hash accumulator for one row, then compaction, bitonic sort and
@@ -1451,6 +1549,159 @@ __global__ __launch_bounds__(1024) void k_hash_num(Operands op, const int32_t* _
   for (int64_t it = blockIdx.x; it < nrows; it += gridDim.x) {
     const int32_t row = uniform(rows[it]);
     hash_num_row<SR, true>(op, row, T, short_seg, c_ptr[row], c_ptr[row + 1], c_idx, c_val, smem);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Expand-sort-compress (ESC) numeric rows: for a row whose products are
+// almost all distinct entries (flops close to nnz, the low compression ratio
+// for which the paper's hybrid picks a heap over a hash table, Sec. 4.1),
+// every product is written to its own LDS position (product j to position j,
+// consecutive products to consecutive positions: no hashing, no atomics),
+// the (column, value) pairs are sorted by column with the bitonic network,
+// and runs of one column are combined.  Products are dealt flat: product j
+// of a block of A entries goes to thread j mod blockDim, its B row found by a
+// binary search over the block's prefix of B-row lengths.
+// ---------------------------------------------------------------------------
+constexpr int kEscUnroll = 4;      // products per thread per batch of loads
+constexpr int kEscMaxPerThread = 16;
+
+inline int esc_threads(int N) { return std::max(64, std::min(1024, N / 4)); }
+
+template <class SR>
+__host__ __device__ inline size_t esc_lds_bytes(int N, int nt) {
+  return RowQueue<typename SR::In>::bytes(nt) + static_cast<size_t>(N) * (4 + sizeof(typename SR::S));
+}
+
+template <class SR>
+__global__ __launch_bounds__(1024) void k_esc_num(Operands op, const int32_t* __restrict__ rows, int64_t nrows,
+                                                  int N, const int64_t* __restrict__ c_ptr,
+                                                  int32_t* __restrict__ c_idx,
+                                                  typename SR::Out* __restrict__ c_val) {
+  using S = typename SR::S;
+  using In = typename SR::In;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int nt = blockDim.x, tid = threadIdx.x;
+  auto q = RowQueue<In>::carve(smem, nt);
+  int32_t* keys = reinterpret_cast<int32_t*>(smem + RowQueue<In>::bytes(nt));
+  S* vals = reinterpret_cast<S*>(keys + N);
+  for (int64_t it = blockIdx.x; it < nrows; it += gridDim.x) {
+    const int32_t row = uniform(rows[it]);
+    const int64_t a_lo = op.a_ptr[row], a_hi = op.a_ptr[row + 1];
+    const int64_t out = c_ptr[row], out_end = c_ptr[row + 1];
+    // 1. expand
+    int base = 0;
+    for (int64_t r0 = a_lo; r0 < a_hi; r0 += nt) {
+      int64_t lo = 0;
+      int32_t len = 0;
+      In a = In(1);
+      if (r0 + tid < a_hi) {
+        const int32_t kk = op.a_idx[r0 + tid];
+        a = load_val<SR>(op.a_val, r0 + tid);
+        lo = op.b_ptr[kk];
+        len = static_cast<int32_t>(op.b_ptr[kk + 1] - lo);
+      }
+      int E;
+      const int off = block_exclusive_scan(len, q.ctr + 2, &E);
+      q.lo[tid] = lo;
+      q.a[tid] = a;
+      q.pfx[tid] = off;  // threads past the row's entries have len 0
+      if (tid == 0) q.pfx[nt] = E;
+      __syncthreads();
+      E = min(E, N - base);  // the class bound holds the row's products; never write past it
+      for (int j0 = 0; j0 < E; j0 += kEscUnroll * nt) {
+        int es[kEscUnroll];
+#pragma unroll
+        for (int u = 0; u < kEscUnroll; ++u) {
+          const int j = j0 + u * nt + tid;
+          int e_lo = -1;
+          if (j < E) {
+            e_lo = 0;
+            int e_hi = nt;
+            while (e_hi - e_lo > 1) {
+              const int mid = (e_lo + e_hi) >> 1;
+              if (q.pfx[mid] <= j)
+                e_lo = mid;
+              else
+                e_hi = mid;
+            }
+          }
+          es[u] = e_lo;
+        }
+        int32_t cols[kEscUnroll];
+        In bv[kEscUnroll];
+#pragma unroll
+        for (int u = 0; u < kEscUnroll; ++u)
+          if (es[u] >= 0) load_b<SR>(op, q.lo[es[u]] + (j0 + u * nt + tid - q.pfx[es[u]]), cols[u], bv[u]);
+#pragma unroll
+        for (int u = 0; u < kEscUnroll; ++u)
+          if (es[u] >= 0) {
+            const int j = base + j0 + u * nt + tid;
+            keys[j] = cols[u];
+            if constexpr (!SR::kPattern) vals[j] = SR::mul(q.a[es[u]], bv[u]);
+          }
+      }
+      base += E;
+      __syncthreads();  // the queue arrays are rewritten by the next block of entries
+    }
+    for (int t = base + tid; t < N; t += nt) keys[t] = INT32_MAX;
+    __syncthreads();
+    // 2. sort by column
+    if (N == 4 * nt)
+      bitonic_sort_reg4<S, !SR::kPattern>(keys, vals, N);
+    else
+      bitonic_sort<S>(keys, vals, N, !SR::kPattern);
+    // 3. compress: each thread a contiguous run of positions; the first
+    //    entry of every column keeps its place in the output, the others are
+    //    combined into it (few: the rows here have almost no repeats)
+    const int ch = (base + nt - 1) / nt;
+    const int e0 = min(base, tid * ch), e1 = min(base, e0 + ch);
+    int32_t kr[kEscMaxPerThread];
+    S vr[kEscMaxPerThread];
+    bool head[kEscMaxPerThread];
+    int cnt = 0;
+#pragma unroll
+    for (int r = 0; r < kEscMaxPerThread; ++r) {
+      const int e = e0 + r;
+      head[r] = false;
+      if (e < e1) {
+        kr[r] = keys[e];
+        if constexpr (!SR::kPattern) vr[r] = vals[e];
+        head[r] = e == 0 || keys[e - 1] != kr[r];
+        cnt += head[r] ? 1 : 0;
+      }
+    }
+    int nnz;
+    int pos = block_exclusive_scan(cnt, q.ctr + 2, &nnz);  // ends with a barrier: keys may be rewritten
+#pragma unroll
+    for (int r = 0; r < kEscMaxPerThread; ++r) {
+      if (e0 + r < e1 && head[r]) {
+        keys[pos] = kr[r];
+        if constexpr (!SR::kPattern) vals[pos] = vr[r];
+        ++pos;
+      }
+    }
+    __syncthreads();
+    if constexpr (!SR::kPattern) {
+      pos = block_exclusive_scan(cnt, q.ctr + 2, &nnz);  // first head position of this thread's run
+#pragma unroll
+      for (int r = 0; r < kEscMaxPerThread; ++r) {
+        if (e0 + r < e1) {
+          if (head[r])
+            ++pos;
+          else
+            SR::combine(&vals[pos - 1], vr[r]);  // the column's first entry is at pos - 1
+        }
+      }
+      __syncthreads();
+    }
+    // the symbolic count and this one agree; the clamp keeps writes inside the row
+    const int lim = static_cast<int>(min(static_cast<int64_t>(nnz), out_end - out));
+    for (int e = tid; e < lim; e += nt) {
+      c_idx[out + e] = keys[e];
+      if constexpr (!SR::kPattern) c_val[out + e] = SR::out(vals[e]);
+    }
+    __syncthreads();
   }
 }
 
@@ -1895,6 +2146,17 @@ static hipError_t hash_num_t(const Operands& op, const int32_t* rows, int64_t nr
 }
 
 template <class SR>
+static hipError_t esc_num_t(const Operands& op, const int32_t* rows, int64_t nrows, int N, const int64_t* c_ptr,
+                            int32_t* c_idx, void* c_val, hipStream_t s) {
+  if (nrows <= 0) return hipSuccess;
+  const int nt = esc_threads(N);
+  if (N / nt > kEscMaxPerThread || N > kEscMaxFlops) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_esc_num<SR>, dim3(grid_for(nrows, 0)), dim3(nt), esc_lds_bytes<SR>(N, nt), s, op, rows,
+                     nrows, N, c_ptr, c_idx, static_cast<typename SR::Out*>(c_val));
+  return hipGetLastError();
+}
+
+template <class SR>
 static hipError_t dense_num_t(const Operands& op, const int32_t* rows, int64_t nrows, int wlog2,
                               int P, const int32_t* pidx, int nt, int short_seg,
                               const int64_t* c_ptr, int32_t* c_idx, void* c_val, hipStream_t s) {
@@ -2071,6 +2333,11 @@ hipError_t launch_hash_num(int sr, const Operands& op, const int32_t* rows, int6
                            int nt, int short_seg, const int64_t* c_ptr, int32_t* c_idx,
                            void* c_val, hipStream_t s) {
   SPG_DISPATCH(sr, hash_num_t, op, rows, nrows, T, nt, short_seg, c_ptr, c_idx, c_val, s)
+}
+
+hipError_t launch_esc_num(int sr, const Operands& op, const int32_t* rows, int64_t nrows, int N,
+                          const int64_t* c_ptr, int32_t* c_idx, void* c_val, hipStream_t s) {
+  SPG_DISPATCH(sr, esc_num_t, op, rows, nrows, N, c_ptr, c_idx, c_val, s)
 }
 
 hipError_t launch_dense_num(int sr, const Operands& op, const int32_t* rows, int64_t nrows,

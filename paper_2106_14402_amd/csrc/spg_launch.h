@@ -27,8 +27,14 @@ struct BinParams {
   const int32_t* row_slot; // numeric: rows with a kept bitmap (slot >= 0) are expanded
   int64_t rank_heavy;      // numeric: rows past hash_max_flops with more than
                            // hash_max_nnz entries go to the rank-panel kernel
+  int64_t esc_max_flops;   // numeric: expand-sort-compress for rows with at most
+  int64_t esc_ratio_x16;   // this many products and 16 * flops <= esc_ratio_x16 * nnz
 };
 constexpr int kExpandBin = 15;  // numeric bin of rows whose bitmap was kept
+// Numeric bins kEscBinBase.. hold the expand-sort-compress classes of
+// 32 << (bin - kEscBinBase) products (up to 4096); dense bins stay below.
+constexpr int kEscBinBase = 56;
+constexpr int kEscMaxFlops = 32 << (kNumBins - 1 - kEscBinBase);
 
 // Pass shapes of the rank kernel: value slots and chunks per pass.
 constexpr int kRankShapes = 5;
@@ -70,7 +76,12 @@ __host__ __device__ inline int ceil_log2_u64(uint64_t x) {
 __host__ __device__ inline int dense_bin(int64_t flops) {
   int fl = floor_log2_u64(static_cast<uint64_t>(flops));
   fl = fl > 47 ? 47 : fl;
+  fl = fl < 8 ? 8 : fl;  // below the expand-sort-compress bins
   return kDenseBinBase + (47 - fl);
+}
+__host__ __device__ inline int esc_bin(int64_t flops) {
+  const int c = ceil_log2_u64(static_cast<uint64_t>(flops));
+  return kEscBinBase + (c < 5 ? 0 : c - 5);
 }
 __host__ __device__ inline int hash_class(int64_t bound) {
   const int c = ceil_log2_u64(static_cast<uint64_t>(bound));
@@ -83,6 +94,8 @@ __host__ __device__ inline int sym_bin(int64_t flops, const BinParams& bp) {
 }
 __host__ __device__ inline int num_bin(int64_t nnz, int64_t flops, const BinParams& bp) {
   if (nnz <= 0) return 0;
+  if (bp.esc_max_flops > 0 && flops <= bp.esc_max_flops && 16 * flops <= bp.esc_ratio_x16 * nnz)
+    return esc_bin(flops);
   if (nnz <= bp.hash_max_nnz) return hash_class(nnz);
   return dense_bin(flops);
 }
@@ -184,6 +197,11 @@ hipError_t launch_dense_num_sub(int sr, const Operands& op, const int32_t* rows,
                                 int64_t nitems, int nt, int short_seg, int subP, int sub_wlog2,
                                 const int32_t* pidx, const int32_t* cnt, const int32_t* off,
                                 const int64_t* c_ptr, int32_t* c_idx, void* c_val, hipStream_t s);
+// Expand-sort-compress rows of one class (N = 32 << class products at most):
+// every product at its own LDS position, a bitonic sort by column, equal
+// columns combined.  sr as for launch_hash_num.
+hipError_t launch_esc_num(int sr, const Operands& op, const int32_t* rows, int64_t nrows, int N,
+                          const int64_t* c_ptr, int32_t* c_idx, void* c_val, hipStream_t s);
 // sr: semiring code 0..6, or 7 for the pattern-only boolean product.
 hipError_t launch_hash_num(int sr, const Operands& op, const int32_t* rows, int64_t nrows, int T,
                            int nt, int short_seg, const int64_t* c_ptr, int32_t* c_idx,
