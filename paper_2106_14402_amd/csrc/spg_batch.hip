@@ -44,43 +44,47 @@ __device__ __forceinline__ int find_segment(const int64_t* __restrict__ off, int
 }
 
 // Operand check of every product (the checks of k_validate, error bits into
-// *err): global waves [0, mtot) take the A slices, [mtot, mtot + ntot) the B
-// slices.
+// *err): global slices [0, mtot) are the A slices, [mtot, mtot + ntot) the
+// B slices; each wave takes slices g = its index, + all waves, ... (a grid
+// of a few workgroups per compute unit, not one per slice).
 __global__ void kb_validate(const BatchDesc* __restrict__ d, const int64_t* __restrict__ row_off,
                             const int64_t* __restrict__ brow_off, int nprod, int64_t mtot, int64_t ntot,
                             int* err) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int64_t g = static_cast<int64_t>(blockIdx.x) * (blockDim.x / kWave) + (threadIdx.x >> 6);
-  if (g >= mtot + ntot) return;
-  const bool is_a = g < mtot;
-  const int b = is_a ? find_segment(row_off, nprod, g) : find_segment(brow_off, nprod, g - mtot);
-  const Operands& op = d[b].op;
-  const int64_t s = is_a ? g - row_off[b] : g - mtot - brow_off[b];
-  const int64_t nmajor = is_a ? op.m : op.n;
-  const int64_t nnz = is_a ? d[b].a_nnz : d[b].b_nnz;
-  const int32_t nminor = is_a ? op.n : op.k;
-  const int64_t* ptr = is_a ? op.a_ptr : op.b_ptr;
-  const int32_t* idx = is_a ? op.a_idx : op.b_idx;
+  const int64_t waves = static_cast<int64_t>(gridDim.x) * (blockDim.x / kWave);
   int e = 0;
-  if (lane == 0) {
-    if (s == 0 && ptr[0] != 0) e |= kCheckEnds;
-    if (s == nmajor - 1 && ptr[nmajor] != nnz) e |= kCheckEnds;
-  }
-  const int64_t lo = ptr[s], hi = ptr[s + 1];
-  if (lo < 0 || hi > nnz || hi < lo) {
-    e |= kCheckOffsets;
-  } else {
-    for (int64_t q = lo + lane; q < hi; q += kWave) {
-      const int32_t c = idx[q];
-      if (c < 0 || c >= nminor) e |= kCheckRange;
-      if (q > lo && idx[q - 1] >= c) e |= idx[q - 1] > c ? kCheckUnsorted : kCheckDuplicate;
+  for (int64_t g = static_cast<int64_t>(blockIdx.x) * (blockDim.x / kWave) + (threadIdx.x >> 6);
+       g < mtot + ntot; g += waves) {
+    const bool is_a = g < mtot;
+    const int b = is_a ? find_segment(row_off, nprod, g) : find_segment(brow_off, nprod, g - mtot);
+    const Operands& op = d[b].op;
+    const int64_t s = is_a ? g - row_off[b] : g - mtot - brow_off[b];
+    const int64_t nmajor = is_a ? op.m : op.n;
+    const int64_t nnz = is_a ? d[b].a_nnz : d[b].b_nnz;
+    const int32_t nminor = is_a ? op.n : op.k;
+    const int64_t* ptr = is_a ? op.a_ptr : op.b_ptr;
+    const int32_t* idx = is_a ? op.a_idx : op.b_idx;
+    if (lane == 0) {
+      if (s == 0 && ptr[0] != 0) e |= kCheckEnds;
+      if (s == nmajor - 1 && ptr[nmajor] != nnz) e |= kCheckEnds;
+    }
+    const int64_t lo = ptr[s], hi = ptr[s + 1];
+    if (lo < 0 || hi > nnz || hi < lo) {
+      e |= kCheckOffsets;
+    } else {
+      for (int64_t q = lo + lane; q < hi; q += kWave) {
+        const int32_t c = idx[q];
+        if (c < 0 || c >= nminor) e |= kCheckRange;
+        if (q > lo && idx[q - 1] >= c) e |= idx[q - 1] > c ? kCheckUnsorted : kCheckDuplicate;
+      }
     }
   }
   e = wave_or(e);
   if (lane == 0 && e) atomicOr(err, e);
 }
 
-// flops per global row, symbolic bin counts, zero nnz for empty rows.
+// flops per global row, symbolic bin counts, zero nnz for empty rows; a
+// wave per row, rows strided over a grid of a few workgroups per compute unit.
 __global__ void kb_flops_bin(const BatchDesc* __restrict__ d, const int64_t* __restrict__ row_off,
                              int nprod, int64_t mtot, BinParams bp, int64_t* __restrict__ flops,
                              unsigned long long* counts, unsigned long long* total) {
@@ -91,8 +95,8 @@ __global__ void kb_flops_bin(const BatchDesc* __restrict__ d, const int64_t* __r
   if (tid < kNumBins) lc[tid] = 0;
   if (tid == 0) ltot = 0;
   __syncthreads();
-  const int64_t r = static_cast<int64_t>(blockIdx.x) * (blockDim.x / kWave) + (tid >> 6);
-  if (r < mtot) {
+  const int64_t waves = static_cast<int64_t>(gridDim.x) * (blockDim.x / kWave);
+  for (int64_t r = static_cast<int64_t>(blockIdx.x) * (blockDim.x / kWave) + (tid >> 6); r < mtot; r += waves) {
     const int b = find_segment(row_off, nprod, r);
     const Operands& op = d[b].op;
     const int64_t i = r - row_off[b];
@@ -272,6 +276,10 @@ std::vector<int64_t> offsets_of(const unsigned long long* counts, int n) {
   }
   return o;
 }
+
+// Grid of the preparation kernels: 8 workgroups of 256 threads per compute
+// unit, each wave striding over rows.
+int64_t prep_grid(const spg_batch_plan* p) { return std::max<int64_t>(1, p->grid_cap_per_thread / 256); }
 
 int64_t grid_cap(const spg_batch_plan* p, int nt) {
   const int64_t c = p->grid_cap_per_thread / nt;
@@ -530,16 +538,16 @@ spg_status spg_batch_symbolic(spg_batch_plan* p, void* ws, int64_t* c_ptr_pool, 
   // Operand check of every product before any kernel indexes with their ids.
   if (p->mtot + p->ntot > 0) {
     int* err = reinterpret_cast<int*>(ctr + kCtrMisc + 1);
-    hipLaunchKernelGGL(kb_validate, dim3(blocks(p->mtot + p->ntot, 4)), dim3(256), 0, s, d, row_off, brow_off,
-                       nprod, p->mtot, p->ntot, err);
+    hipLaunchKernelGGL(kb_validate, dim3(std::min<int64_t>(blocks(p->mtot + p->ntot, 4), prep_grid(p))), dim3(256),
+                       0, s, d, row_off, brow_off, nprod, p->mtot, p->ntot, err);
     int herr = 0;
     SPG_TRY_HIP(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, s));
     SPG_TRY_HIP(hipStreamSynchronize(s));
     if (herr) return SPG_E_INVALID;
   }
   if (p->mtot > 0)
-    hipLaunchKernelGGL(kb_flops_bin, dim3(blocks(p->mtot, 4)), dim3(256), 0, s, d, row_off, nprod, p->mtot,
-                       p->bp, flops, ctr + kCtrSym, ctr + kCtrMisc);
+    hipLaunchKernelGGL(kb_flops_bin, dim3(std::min<int64_t>(blocks(p->mtot, 4), prep_grid(p))), dim3(256), 0, s,
+                       d, row_off, nprod, p->mtot, p->bp, flops, ctr + kCtrSym, ctr + kCtrMisc);
   unsigned long long h[kNumBins + 1];
   SPG_TRY_HIP(hipMemcpyAsync(h, ctr + kCtrSym, sizeof(uint64_t) * kNumBins, hipMemcpyDeviceToHost, s));
   SPG_TRY_HIP(hipMemcpyAsync(&h[kNumBins], ctr + kCtrMisc, sizeof(uint64_t), hipMemcpyDeviceToHost, s));

@@ -41,6 +41,21 @@ hipError_t launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Workgroups for the row-striding preparation kernels: 8 of 256 threads per
+// compute unit (one workgroup per row would spend the time in dispatch).
+static int64_t prep_blocks() {
+  static int ncu = 0;
+  if (ncu == 0) {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) ==
+                                                hipSuccess && v > 0)
+      ncu = v;
+    else
+      ncu = 256;
+  }
+  return static_cast<int64_t>(ncu) * 8;
+}
+
 // Operand check: ptr[0] == 0, ptr non-decreasing within [0, nnz],
 // ptr[nmajor] == nnz, ids in [0, nminor), and the order of the ids of each
 // slice.  Error bits (kCheck*): bad endpoints, bad offsets, an id out of
@@ -50,24 +65,26 @@ hipError_t launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s) {
 __global__ void k_validate(const int64_t* __restrict__ ptr, const int32_t* __restrict__ idx,
                            int64_t nmajor, int64_t nnz, int32_t nminor, int* err) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int64_t s = static_cast<int64_t>(blockIdx.x) * (blockDim.x / kWave) + (threadIdx.x >> 6);
-  if (s >= nmajor) return;
+  const int64_t waves = static_cast<int64_t>(gridDim.x) * (blockDim.x / kWave);
   int e = 0;
-  if (lane == 0) {
-    if (s == 0 && ptr[0] != 0) e |= kCheckEnds;
-    if (s == nmajor - 1 && ptr[nmajor] != nnz) e |= kCheckEnds;
-  }
-  const int64_t lo = ptr[s], hi = ptr[s + 1];
-  if (lo < 0 || hi > nnz || hi < lo) {
-    e |= kCheckOffsets;
-  } else {
-    for (int64_t q = lo + lane; q < hi; q += kWave) {
-      const int32_t c = idx[q];
-      if (c < 0 || c >= nminor) e |= kCheckRange;
-      if (q > lo) {
-        const int32_t b = idx[q - 1];
-        if (b > c) e |= kCheckUnsorted;
-        if (b == c) e |= kCheckDuplicate;
+  for (int64_t s = static_cast<int64_t>(blockIdx.x) * (blockDim.x / kWave) + (threadIdx.x >> 6); s < nmajor;
+       s += waves) {
+    if (lane == 0) {
+      if (s == 0 && ptr[0] != 0) e |= kCheckEnds;
+      if (s == nmajor - 1 && ptr[nmajor] != nnz) e |= kCheckEnds;
+    }
+    const int64_t lo = ptr[s], hi = ptr[s + 1];
+    if (lo < 0 || hi > nnz || hi < lo) {
+      e |= kCheckOffsets;
+    } else {
+      for (int64_t q = lo + lane; q < hi; q += kWave) {
+        const int32_t c = idx[q];
+        if (c < 0 || c >= nminor) e |= kCheckRange;
+        if (q > lo) {
+          const int32_t b = idx[q - 1];
+          if (b > c) e |= kCheckUnsorted;
+          if (b == c) e |= kCheckDuplicate;
+        }
       }
     }
   }
@@ -79,7 +96,7 @@ hipError_t launch_validate(const int64_t* ptr, const int32_t* idx, int64_t nmajo
                            int32_t nminor, int* err, hipStream_t s) {
   if (nmajor <= 0) return hipSuccess;
   const int nt = 256;
-  const int64_t nb = (nmajor + nt / kWave - 1) / (nt / kWave);
+  const int64_t nb = std::min<int64_t>((nmajor + nt / kWave - 1) / (nt / kWave), prep_blocks());
   hipLaunchKernelGGL(k_validate, dim3(static_cast<unsigned>(nb)), dim3(nt), 0, s, ptr, idx, nmajor,
                      nnz, nminor, err);
   return hipGetLastError();
@@ -192,8 +209,8 @@ __global__ void k_flops_bin(Operands op, int64_t a_nnz, BinParams bp, int64_t* _
   if (tid < kNumBins) lc[tid] = 0;
   if (tid == 0) ltot = 0;
   __syncthreads();
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * (blockDim.x / kWave) + (tid >> 6);
-  if (i < op.m) {
+  const int64_t waves = static_cast<int64_t>(gridDim.x) * (blockDim.x / kWave);
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * (blockDim.x / kWave) + (tid >> 6); i < op.m; i += waves) {
     int e = 0;
     int64_t f = 0;
     const int64_t lo = op.a_ptr[i], hi = op.a_ptr[i + 1];
@@ -237,7 +254,7 @@ hipError_t launch_flops_bin(const Operands& op, int64_t a_nnz, BinParams bp, int
                             unsigned long long* counts, unsigned long long* total, int* err, hipStream_t s) {
   if (op.m <= 0) return hipSuccess;
   const int nt = 256;
-  const int64_t nb = (static_cast<int64_t>(op.m) + nt / kWave - 1) / (nt / kWave);
+  const int64_t nb = std::min<int64_t>((static_cast<int64_t>(op.m) + nt / kWave - 1) / (nt / kWave), prep_blocks());
   hipLaunchKernelGGL(k_flops_bin, dim3(static_cast<unsigned>(nb)), dim3(nt), 0, s, op, a_nnz, bp, flops,
                      c_ptr, counts, total, err);
   return hipGetLastError();
@@ -2108,19 +2125,90 @@ __global__ __launch_bounds__(1024) void k_hash_num_b(const BatchDesc* __restrict
   }
 }
 
+// One rank pass over all k columns of a row (k small enough for the whole
+// bitmap, the row's entries few enough for the value slots): the pattern by
+// a walk over B's column ids, a prefix count per 64-bit word, the values
+// combined at their columns' ranks, then written in column order.  The
+// batched heavy rows of small products take it instead of one fixed panel
+// after another.
+template <class SR>
+__device__ void rank_row_whole(const Operands& op, int64_t a_lo, int64_t a_hi, int slots, int short_seg,
+                               int64_t out, int64_t out_end, int32_t* __restrict__ c_idx,
+                               typename SR::Out* __restrict__ c_val, unsigned char* smem) {
+  using S = typename SR::S;
+  const int nt = blockDim.x;
+  const int tid = threadIdx.x;
+  auto q = RowQueue<typename SR::In>::carve(smem, nt);
+  auto pq = RowQueue<SrPattern::In>::carve(smem, nt);
+  unsigned char* p0 = smem + rank_queue_bytes<SR>(nt);
+  S* vals = reinterpret_cast<S*>(p0);
+  uint32_t* bits = reinterpret_cast<uint32_t*>(p0 + sizeof(S) * static_cast<size_t>(slots));
+  const int nwords = (op.k + 31) >> 5;
+  const int nw64 = (nwords + 1) >> 1;
+  uint16_t* pre = reinterpret_cast<uint16_t*>(bits + 2 * nw64);
+  const uint64_t* bits64 = reinterpret_cast<const uint64_t*>(bits);
+  const int total = static_cast<int>(out_end - out);  // <= slots (the caller checked)
+  for (int t = tid; t < total; t += nt) vals[t] = SR::identity();
+  for (int t = tid; t < 2 * nw64; t += nt) bits[t] = 0u;
+  __syncthreads();
+  BitmapSink bs{bits};
+  RowSource<SrPattern> ps{&op, a_lo, a_hi, false, nullptr, 1, 0, 1};
+  enumerate_src<SrPattern, 2>(op, ps, 0, short_seg, pq, bs);
+  const int wpt = (nw64 + nt - 1) / nt;
+  const int w0 = min(nw64, tid * wpt), w1 = min(nw64, w0 + wpt);
+  int local = 0;
+  for (int w = w0; w < w1; ++w) local += __popcll(bits64[w]);
+  int ptotal;
+  int run = block_exclusive_scan(local, q.ctr + 2, &ptotal);
+  for (int w = w0; w < w1; ++w) {
+    pre[w] = static_cast<uint16_t>(run);
+    run += __popcll(bits64[w]);
+  }
+  __syncthreads();
+  RankSink<SR> rs{bits64, pre, vals};
+  RowSource<SR> vs{&op, a_lo, a_hi, false, nullptr, 1, 0, 1};
+  enumerate_src<SR, 2>(op, vs, 0, short_seg, q, rs);
+  const int lim = min(total, ptotal);
+  for (int r = tid; r < lim; r += nt) c_val[out + r] = SR::out(vals[r]);
+  __syncthreads();
+  int32_t* ids = reinterpret_cast<int32_t*>(vals);
+  static_assert(sizeof(S) >= sizeof(int32_t), "ids are staged over the value slots");
+  for (int w = tid; w < nw64; w += nt) {
+    uint64_t x = bits64[w];
+    int qi = pre[w];
+    while (x) {
+      ids[qi++] = (w << 6) + __ffsll(static_cast<unsigned long long>(x)) - 1;
+      x &= x - 1;
+    }
+  }
+  __syncthreads();
+  for (int r = tid; r < lim; r += nt) c_idx[out + r] = ids[r];
+  __syncthreads();
+}
+
+// Heavy rows of a batch: one whole-row rank pass when the product has at
+// most kcap columns and the row at most slots entries, else fixed panels.
 template <class SR>
 __global__ __launch_bounds__(1024) void k_dense_num_b(const BatchDesc* __restrict__ descs,
                                                       const int64_t* __restrict__ row_off, int nprod,
                                                       const int32_t* __restrict__ items, int64_t nitems,
-                                                      int short_seg) {
+                                                      int short_seg, int kcap, int slots) {
   extern __shared__ __align__(16) unsigned char smem[];
   for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
     const int64_t r = uniform(items[it]);
     const int b = uniform(batch_product(row_off, nprod, r));
     const BatchDesc d = descs[b];  // uniform: held in scalar registers
     const int32_t row = uniform(static_cast<int32_t>(r - row_off[b]));
-    dense_num_row<SR>(d.op, row, d.num_wlog2, d.num_P, d.pnum, short_seg, d.c_ptr[row],
-                      d.c_ptr[row + 1], d.c_idx, static_cast<typename SR::Out*>(d.c_val), smem);
+    const int64_t out = uniform64(d.c_ptr[row]), out_end = uniform64(d.c_ptr[row + 1]);
+    if constexpr (!SR::kPattern) {
+      if (d.op.k <= kcap && out_end - out <= slots) {
+        rank_row_whole<SR>(d.op, d.op.a_ptr[row], d.op.a_ptr[row + 1], slots, short_seg, out, out_end, d.c_idx,
+                           static_cast<typename SR::Out*>(d.c_val), smem);
+        continue;
+      }
+    }
+    dense_num_row<SR>(d.op, row, d.num_wlog2, d.num_P, d.pnum, short_seg, out, out_end, d.c_idx,
+                      static_cast<typename SR::Out*>(d.c_val), smem);
   }
 }
 
@@ -2258,9 +2346,23 @@ static hipError_t dense_num_b_t(const BatchDesc* descs, const int64_t* row_off, 
                                 const int32_t* items, int64_t nitems, int wlog2_max, int nt,
                                 int short_seg, int64_t grid_cap, hipStream_t s) {
   if (nitems <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_dense_num_b<SR>, dim3(grid_for(nitems, grid_cap)), dim3(nt),
-                     dense_num_lds_t<SR>(wlog2_max, nt), s, descs, row_off, nprod, items, nitems,
-                     short_seg);
+  // whole-row rank passes in the same LDS: up to 2^16 columns (bitmap and
+  // word ranks), the rest of it value slots
+  const size_t lds = dense_num_lds_t<SR>(wlog2_max, nt);
+  int kcap = 0, slots = 0;
+  if constexpr (!SR::kPattern) {
+    const int kc = 1 << 16;
+    const size_t fixed = rank_queue_bytes<SR>(nt) + kc / 8 + (kc / 64) * 2;
+    if (lds > fixed) {
+      const size_t sl = std::min<size_t>((lds - fixed) / sizeof(typename SR::S), 65535) & ~size_t(63);
+      if (sl >= 1024) {
+        kcap = kc;
+        slots = static_cast<int>(sl);
+      }
+    }
+  }
+  hipLaunchKernelGGL(k_dense_num_b<SR>, dim3(grid_for(nitems, grid_cap)), dim3(nt), lds, s, descs, row_off, nprod,
+                     items, nitems, short_seg, kcap, slots);
   return hipGetLastError();
 }
 

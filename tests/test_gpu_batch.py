@@ -136,3 +136,17 @@ def test_autotuned_batch_matches_oracle_and_uses_cache(tmp_path):
     for b, it in enumerate(items):
         assert_parity(it.A, it.A, it.semiring, _host(bp.result(b)))
     bp.close()
+
+
+@pytest.mark.parametrize("budget", [8192, 65536, 131072])
+def test_whole_row_rank_passes_in_batch(budget):
+    """Heavy rows of small products take one rank pass over all their
+    columns when their entries fit the value slots (more of them with a
+    larger LDS budget), else fixed panels; both against the oracle."""
+    items = _batch(12, n_lo=3000, n_hi=60000, d_lo=8, d_hi=24)
+    from paper_2106_14402_amd import binding
+    o = binding.make_options(hash_max_flops=64, hash_max_nnz=64, lds_budget=budget, dense_threads=512)
+    bp = _run_batch(items, options=o)
+    for b, it in enumerate(items):
+        assert_parity(it.A, it.A, it.semiring, _host(bp.result(b)))
+    bp.close()
