@@ -2542,33 +2542,54 @@ int max_lds_bytes() { return 160 * 1024; }
 __global__ void k_prune_count(const int64_t* __restrict__ ptr, const float* __restrict__ val,
                               int64_t nmajor, float thresh, int64_t* __restrict__ cnt) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int64_t s = static_cast<int64_t>(blockIdx.x) * (blockDim.x / kWave) + (threadIdx.x >> 6);
-  if (s >= nmajor) return;
-  int64_t c = 0;
-  for (int64_t p = ptr[s] + lane; p < ptr[s + 1]; p += kWave) c += val[p] >= thresh;
-  c = wave_sum(c);
-  if (lane == 0) cnt[s] = c;
+  const int64_t waves = static_cast<int64_t>(gridDim.x) * (blockDim.x / kWave);
+  for (int64_t s = static_cast<int64_t>(blockIdx.x) * (blockDim.x / kWave) + (threadIdx.x >> 6); s < nmajor;
+       s += waves) {
+    int64_t c = 0;
+    for (int64_t p = ptr[s] + lane; p < ptr[s + 1]; p += kWave) c += val[p] >= thresh;
+    c = wave_sum(c);
+    if (lane == 0) cnt[s] = c;
+  }
 }
 
+// Kept entries of a slice in order: four groups of 64 entries are loaded
+// before their keep masks place them, so a wave has four loads in flight.
 __global__ void k_prune_apply(const int64_t* __restrict__ ptr, const int32_t* __restrict__ idx,
                               const float* __restrict__ val, int64_t nmajor, float thresh,
                               const int64_t* __restrict__ new_ptr, int32_t* __restrict__ new_idx,
                               float* __restrict__ new_val) {
+  constexpr int U = 4;
   const int lane = threadIdx.x & (kWave - 1);
-  const int64_t s = static_cast<int64_t>(blockIdx.x) * (blockDim.x / kWave) + (threadIdx.x >> 6);
-  if (s >= nmajor) return;
-  int64_t o = new_ptr[s];
-  const int64_t hi = ptr[s + 1];
-  for (int64_t b = ptr[s]; b < hi; b += kWave) {
-    const int64_t p = b + lane;
-    const bool keep = p < hi && val[p] >= thresh;
-    const unsigned long long m = __ballot(keep);
-    if (keep) {
-      const int before = __popcll(m & ((1ull << lane) - 1ull));
-      new_idx[o + before] = idx[p];
-      new_val[o + before] = val[p];
+  const int64_t waves = static_cast<int64_t>(gridDim.x) * (blockDim.x / kWave);
+  for (int64_t s = static_cast<int64_t>(blockIdx.x) * (blockDim.x / kWave) + (threadIdx.x >> 6); s < nmajor;
+       s += waves) {
+    int64_t o = new_ptr[s];
+    const int64_t hi = ptr[s + 1];
+    for (int64_t b = ptr[s]; b < hi; b += U * kWave) {
+      float v[U];
+      int32_t c[U];
+      bool keep[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t p = b + u * kWave + lane;
+        keep[u] = false;
+        if (p < hi) {
+          v[u] = val[p];
+          c[u] = idx[p];
+          keep[u] = v[u] >= thresh;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const unsigned long long m = __ballot(keep[u]);
+        if (keep[u]) {
+          const int before = __popcll(m & ((1ull << lane) - 1ull));
+          new_idx[o + before] = c[u];
+          new_val[o + before] = v[u];
+        }
+        o += __popcll(m);
+      }
     }
-    o += __popcll(m);
   }
 }
 
@@ -2578,26 +2599,28 @@ __global__ void k_prune_apply(const int64_t* __restrict__ ptr, const int32_t* __
 __global__ void k_inflate(const int64_t* __restrict__ ptr, const float* val, int64_t nmajor, float r,
                           float* val_out) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int64_t s = static_cast<int64_t>(blockIdx.x) * (blockDim.x / kWave) + (threadIdx.x >> 6);
-  if (s >= nmajor) return;
-  const int64_t lo = ptr[s], hi = ptr[s + 1];
-  double sum = 0.0;
-  for (int64_t p = lo + lane; p < hi; p += kWave) sum += static_cast<double>(powf(val[p], r));
-  sum = wave_sum(sum);
-  if (sum == 0.0) {  // the slice is left as it is
-    for (int64_t p = lo + lane; p < hi; p += kWave) val_out[p] = val[p];
-    return;
+  const int64_t waves = static_cast<int64_t>(gridDim.x) * (blockDim.x / kWave);
+  for (int64_t s = static_cast<int64_t>(blockIdx.x) * (blockDim.x / kWave) + (threadIdx.x >> 6); s < nmajor;
+       s += waves) {
+    const int64_t lo = ptr[s], hi = ptr[s + 1];
+    double sum = 0.0;
+    for (int64_t p = lo + lane; p < hi; p += kWave) sum += static_cast<double>(powf(val[p], r));
+    sum = wave_sum(sum);
+    if (sum == 0.0) {  // the slice is left as it is
+      for (int64_t p = lo + lane; p < hi; p += kWave) val_out[p] = val[p];
+      continue;
+    }
+    const double inv = 1.0 / sum;
+    for (int64_t p = lo + lane; p < hi; p += kWave)
+      val_out[p] = static_cast<float>(static_cast<double>(powf(val[p], r)) * inv);
   }
-  const double inv = 1.0 / sum;
-  for (int64_t p = lo + lane; p < hi; p += kWave)
-    val_out[p] = static_cast<float>(static_cast<double>(powf(val[p], r)) * inv);
 }
 
 hipError_t launch_inflate(const int64_t* ptr, const float* val, int64_t nmajor, float r, float* val_out,
                           hipStream_t s) {
   if (nmajor <= 0) return hipSuccess;
   const int nt = 256;
-  const int64_t nb = (nmajor + nt / kWave - 1) / (nt / kWave);
+  const int64_t nb = std::min<int64_t>((nmajor + nt / kWave - 1) / (nt / kWave), prep_blocks());
   hipLaunchKernelGGL(k_inflate, dim3(static_cast<unsigned>(nb)), dim3(nt), 0, s, ptr, val, nmajor, r, val_out);
   return hipGetLastError();
 }
@@ -2730,7 +2753,7 @@ hipError_t launch_prune_count(const int64_t* ptr, const float* val, int64_t nmaj
                               int64_t* new_ptr, hipStream_t s) {
   if (nmajor <= 0) return hipSuccess;
   const int nt = 256;
-  const int64_t nb = (nmajor + nt / kWave - 1) / (nt / kWave);
+  const int64_t nb = std::min<int64_t>((nmajor + nt / kWave - 1) / (nt / kWave), prep_blocks());
   hipLaunchKernelGGL(k_prune_count, dim3(static_cast<unsigned>(nb)), dim3(nt), 0, s, ptr, val,
                      nmajor, thresh, new_ptr + 1);
   return hipGetLastError();
@@ -2741,7 +2764,7 @@ hipError_t launch_prune_apply(const int64_t* ptr, const int32_t* idx, const floa
                               int32_t* new_idx, float* new_val, hipStream_t s) {
   if (nmajor <= 0) return hipSuccess;
   const int nt = 256;
-  const int64_t nb = (nmajor + nt / kWave - 1) / (nt / kWave);
+  const int64_t nb = std::min<int64_t>((nmajor + nt / kWave - 1) / (nt / kWave), prep_blocks());
   hipLaunchKernelGGL(k_prune_apply, dim3(static_cast<unsigned>(nb)), dim3(nt), 0, s, ptr, idx, val,
                      nmajor, thresh, new_ptr, new_idx, new_val);
   return hipGetLastError();
