@@ -285,7 +285,7 @@ def alg_bytes_dense(A, nnz_dense_rows_A, ndense_rows, nnz_c_dense, s_in, s_out, 
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported by this build "
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported "
               f"(the product is a single-GPU kernel path)", file=sys.stderr)
         sys.exit(2)
     run = {"rmat": run_rmat, "er": run_er, "mcl": run_mcl, "batched": run_batched,
@@ -616,15 +616,21 @@ def run_batched(args):
     cache = os.path.join(ROOT, "gpurun_out", "autotune.json") if args.autotune_cache is None else args.autotune_cache
     tuning = AT.tune_batch(mats, mats, srs, cache, log=log)
     log(f"[bench] autotuned {tuning}")
-    bp = BT.BatchProduct(mats, mats, srs, AT.make_options(tuning["knobs"]))
+    bopt = AT.make_options(tuning["knobs"])
+    bopt.timing = 1
+    bp = BT.BatchProduct(mats, mats, srs, bopt)
     bp.symbolic()
     bp.allocate()
     flops = bp.stats()[0]
+    record = []
 
     def batched_full():
         bp.symbolic()
         bp.numeric()
+        record.append(bp.timings())
     ms_b = timed(batched_full, args.steps, args.warmup)
+    phase_ms = {k: float(np.mean([r[k] for r in record[args.warmup:]])) for k in record[0]}
+    roofline = roofline_record(batched_dominant(items, bp, phase_ms, tuning["knobs"]), "batched")
     bp.capture()
     ms_br = timed(bp.replay, args.steps, args.warmup)
     singles = [S.Product(m, m, sr) for m, sr in zip(mats, srs)]
@@ -658,8 +664,39 @@ def run_batched(args):
     out["speedup"] = {"full_step": round(ms_s / ms_b, 3), "numeric": round(ms_sn / ms_br, 3)}
     out["autotune"] = {"knobs": tuning["knobs"], "tuned_ms": tuning["ms"], "default_ms": tuning["default_ms"],
                        "from_cache": tuning["from_cache"]}
+    out["roofline"] = roofline
+    out["phase_ms"] = {k: round(v, 3) for k, v in phase_ms.items()}
     bp.close()
     return out
+
+
+def batched_dominant(items, bp, phase_ms, knobs):
+    """The longest phase of a batched step (its launches cover every
+    product's rows of one accumulator family) with its algorithmic bytes,
+    summed over the products: for each, its covered A rows and B read once,
+    C's entries of those rows written once (numeric) or the row sizes
+    (symbolic)."""
+    hmn = int(knobs.get("hash_max_nnz", 2048))
+    hmf = int(knobs.get("hash_max_flops", 8192))
+    byts = {k: 0 for k in phase_ms}
+    for b, it in enumerate(items):
+        s_io = 8 if it.semiring == "plus_times_f64" else 4
+        fl, deg = row_flops(it.A)
+        rownnz = np.diff(bp.c_ptr[bp.pool_off[b]:bp.pool_off[b + 1]].cpu().numpy())
+        dense = rownnz > hmn
+        hashed = (rownnz > 0) & ~dense
+        heavy = fl > hmf
+        light = (fl > 0) & ~heavy
+        for name, rows, sym in (("num_dense", dense, False), ("num_hash", hashed, False),
+                                ("sym_dense", heavy, True), ("sym_hash", light, True)):
+            if rows.any():
+                byts[name] += alg_bytes_dense(it.A, int(deg[rows].sum()), int(rows.sum()),
+                                              int(rownnz[rows].sum()), s_io, s_io, sym)
+    kern = {"num_dense": "k_dense_num_b", "num_hash": "k_hash_num_b", "sym_dense": "k_dense_sym_b",
+            "sym_hash": "k_hash_sym_b"}
+    name = max(phase_ms, key=lambda k: phase_ms[k])
+    return {"kernel": kern[name], "semiring": "plus_times_f64+min_plus_i32", "ms": phase_ms[name],
+            "bytes": byts[name]}
 
 
 def run_served(args):

@@ -469,6 +469,22 @@ spg_status spg_batch_graph_launch(spg_batch_plan* plan);
 
 /* Total products and rows of the batch after the symbolic phase. */
 spg_status spg_batch_stats(const spg_batch_plan* plan, int64_t* flops, int64_t* rows);
+
+/* Phases reported by spg_batch_timings, in milliseconds: the launches of
+ * every product's rows in one accumulator family (paper Sec. 4.1 phases (2)
+ * and (3); per-stage timing of Sec. 7). */
+#define SPG_BATCH_PHASE_SYM_HASH 0
+#define SPG_BATCH_PHASE_SYM_DENSE 1
+#define SPG_BATCH_PHASE_NUM_HASH 2
+#define SPG_BATCH_PHASE_NUM_DENSE 3
+#define SPG_BATCH_NUM_PHASES 4
+
+/* Device time of each phase of the last eager spg_batch_symbolic /
+ * spg_batch_numeric call (graph replays are not timed) into
+ * ms[SPG_BATCH_NUM_PHASES]; 0 for a phase that launched nothing.  Needs
+ * options.timing = 1 at plan creation (else SPG_E_STATE); synchronises the
+ * plan's stream. */
+spg_status spg_batch_timings(spg_batch_plan* plan, float* ms);
 spg_status spg_batch_plan_destroy(spg_batch_plan* plan);
 
 #ifdef __cplusplus

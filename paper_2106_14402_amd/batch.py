@@ -75,6 +75,10 @@ class BatchProduct:
     def stats(self):
         return B_.spg_batch_stats(self.plan)
 
+    def timings(self) -> dict:
+        """Phase times (ms) of the last eager call; needs options.timing."""
+        return B_.spg_batch_timings(self.plan)
+
     def result(self, b: int) -> DeviceMatrix:
         """Views of product b's output inside the pools."""
         sr = self.semirings[b]

@@ -171,6 +171,8 @@ def _declare_batch(L):
     L.spg_batch_graph_launch.argtypes = [vp]
     L.spg_batch_stats.restype = st
     L.spg_batch_stats.argtypes = [vp, pi64, pi64]
+    L.spg_batch_timings.restype = st
+    L.spg_batch_timings.argtypes = [vp, ctypes.POINTER(ctypes.c_float)]
     L.spg_batch_plan_destroy.restype = st
     L.spg_batch_plan_destroy.argtypes = [vp]
 
@@ -412,6 +414,15 @@ def spg_batch_stats(plan):
     f, r = ctypes.c_int64(), ctypes.c_int64()
     _check(load().spg_batch_stats(plan, ctypes.byref(f), ctypes.byref(r)), "spg_batch_stats")
     return int(f.value), int(r.value)
+
+
+BATCH_PHASES = ["sym_hash", "sym_dense", "num_hash", "num_dense"]
+
+
+def spg_batch_timings(plan) -> dict:
+    ms = (ctypes.c_float * len(BATCH_PHASES))()
+    _check(load().spg_batch_timings(plan, ms), "spg_batch_timings")
+    return {name: float(ms[i]) for i, name in enumerate(BATCH_PHASES)}
 
 
 def spg_batch_plan_destroy(plan) -> None:

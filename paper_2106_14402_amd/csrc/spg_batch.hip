@@ -247,6 +247,11 @@ struct spg_batch_plan {
   hipGraph_t graph;
   hipGraphExec_t graph_exec;
   bool has_graph;
+  // phase timing (options.timing): an event pair per batch phase, recorded
+  // by eager calls only (never inside a capture)
+  hipEvent_t ev[2 * SPG_BATCH_NUM_PHASES];
+  bool ev_made, capturing;
+  bool ran[SPG_BATCH_NUM_PHASES];
 };
 
 namespace {
@@ -256,6 +261,22 @@ constexpr int kCtrNum = kNumBins;
 constexpr int kCtrCursor = kNumBins + kBatchBins;
 constexpr int kCtrMisc = kNumBins + 2 * kBatchBins;
 constexpr int kCtrWords = kCtrMisc + 8;
+
+struct BatchPhaseTimer {
+  spg_batch_plan* p;
+  int phase;
+  bool on;
+  BatchPhaseTimer(spg_batch_plan* plan, int ph)
+      : p(plan), phase(ph), on(plan->ev_made && !plan->capturing) {
+    if (on) {
+      (void)hipEventRecord(p->ev[2 * phase], p->stream);
+      p->ran[phase] = true;
+    }
+  }
+  ~BatchPhaseTimer() {
+    if (on) (void)hipEventRecord(p->ev[2 * phase + 1], p->stream);
+  }
+};
 
 spg_status check_one(const spg_matrix& M) {
   if (M.nrows < 0 || M.ncols < 0 || M.nnz < 0) return SPG_E_SHAPE;
@@ -299,22 +320,33 @@ spg_status enqueue_numeric(spg_batch_plan* p, unsigned char* w) {
                        p->ntot, 1);
   const std::vector<int64_t> no = offsets_of(p->num_counts, kBatchBins);
   const int nslots = static_cast<int>(p->slot_sr.size());
-  for (int sl = 0; sl < nslots; ++sl) {
-    const int sr = p->slot_sr[sl];
-    for (int c = 1; c < kDenseBinBase; ++c) {
-      const int bin = c + kNumBins * sl;
-      if (!p->num_counts[bin]) continue;
-      const int nt = hash_threads_num(c, sr);
-      SPG_TRY_HIP(launch_hash_num_b(sr, d, row_off, p->nprod, items + no[bin],
-                                    static_cast<int64_t>(p->num_counts[bin]), hash_table_size(c), nt,
-                                    p->opt.short_seg, grid_cap(p, nt), s));
+  {
+    // every slot's hash classes, then every slot's dense rows (independent
+    // rows: the order only groups the launches for timing)
+    BatchPhaseTimer t(p, SPG_BATCH_PHASE_NUM_HASH);
+    for (int sl = 0; sl < nslots; ++sl) {
+      const int sr = p->slot_sr[sl];
+      for (int c = 1; c < kDenseBinBase; ++c) {
+        const int bin = c + kNumBins * sl;
+        if (!p->num_counts[bin]) continue;
+        const int nt = hash_threads_num(c, sr);
+        SPG_TRY_HIP(launch_hash_num_b(sr, d, row_off, p->nprod, items + no[bin],
+                                      static_cast<int64_t>(p->num_counts[bin]), hash_table_size(c), nt,
+                                      p->opt.short_seg, grid_cap(p, nt), s));
+      }
     }
-    int64_t nd = 0;
-    for (int c = kDenseBinBase; c < kNumBins; ++c) nd += static_cast<int64_t>(p->num_counts[c + kNumBins * sl]);
-    if (nd > 0) {
-      const int nt = p->opt.dense_threads;
-      SPG_TRY_HIP(launch_dense_num_b(sr, d, row_off, p->nprod, items + no[kDenseBinBase + kNumBins * sl], nd,
-                                     p->num_wlog2_max[sl], nt, p->opt.short_seg, grid_cap(p, nt), s));
+  }
+  {
+    BatchPhaseTimer t(p, SPG_BATCH_PHASE_NUM_DENSE);
+    for (int sl = 0; sl < nslots; ++sl) {
+      const int sr = p->slot_sr[sl];
+      int64_t nd = 0;
+      for (int c = kDenseBinBase; c < kNumBins; ++c) nd += static_cast<int64_t>(p->num_counts[c + kNumBins * sl]);
+      if (nd > 0) {
+        const int nt = p->opt.dense_threads;
+        SPG_TRY_HIP(launch_dense_num_b(sr, d, row_off, p->nprod, items + no[kDenseBinBase + kNumBins * sl], nd,
+                                       p->num_wlog2_max[sl], nt, p->opt.short_seg, grid_cap(p, nt), s));
+      }
     }
   }
   SPG_TRY_HIP(hipGetLastError());
@@ -484,6 +516,19 @@ spg_status spg_batch_plan_create(int nprod, const spg_matrix* A, const spg_matri
   p->state = 0;
   p->c_ptr_pool = nullptr;
   p->has_graph = false;
+  p->ev_made = false;
+  p->capturing = false;
+  for (int i = 0; i < SPG_BATCH_NUM_PHASES; ++i) p->ran[i] = false;
+  if (p->opt.timing) {
+    int made = 0;
+    while (made < 2 * SPG_BATCH_NUM_PHASES && hipEventCreate(&p->ev[made]) == hipSuccess) ++made;
+    if (made < 2 * SPG_BATCH_NUM_PHASES) {
+      for (int i = 0; i < made; ++i) (void)hipEventDestroy(p->ev[i]);
+      delete p;
+      return SPG_E_DEVICE;
+    }
+    p->ev_made = true;
+  }
   *out = p;
   return SPG_OK;
 }
@@ -567,16 +612,20 @@ spg_status spg_batch_symbolic(spg_batch_plan* p, void* ws, int64_t* c_ptr_pool, 
     if (any_panels && p->ntot > 0)
       hipLaunchKernelGGL(kb_panel_index, dim3(blocks(p->ntot, 4)), dim3(256), 0, s, d, brow_off, nprod,
                          p->ntot, 0);
-    for (int c = 1; c < kDenseBinBase; ++c) {
-      if (!p->sym_counts[c]) continue;
-      const int nt = hash_threads(c);
-      SPG_TRY_HIP(launch_hash_sym_b(d, row_off, nprod, items_sym + so[c],
-                                    static_cast<int64_t>(p->sym_counts[c]), hash_table_size(c), nt,
-                                    p->opt.short_seg, grid_cap(p, nt), s));
+    {
+      BatchPhaseTimer t(p, SPG_BATCH_PHASE_SYM_HASH);
+      for (int c = 1; c < kDenseBinBase; ++c) {
+        if (!p->sym_counts[c]) continue;
+        const int nt = hash_threads(c);
+        SPG_TRY_HIP(launch_hash_sym_b(d, row_off, nprod, items_sym + so[c],
+                                      static_cast<int64_t>(p->sym_counts[c]), hash_table_size(c), nt,
+                                      p->opt.short_seg, grid_cap(p, nt), s));
+      }
     }
     int64_t nd = 0;
     for (int c = kDenseBinBase; c < kNumBins; ++c) nd += static_cast<int64_t>(p->sym_counts[c]);
     if (nd > 0) {
+      BatchPhaseTimer t(p, SPG_BATCH_PHASE_SYM_DENSE);
       const int nt = p->opt.dense_threads;
       SPG_TRY_HIP(launch_dense_sym_b(d, row_off, nprod, items_sym + so[kDenseBinBase], nd, p->sym_wlog2_max,
                                      nt, p->opt.short_seg, grid_cap(p, nt), s));
@@ -669,10 +718,12 @@ spg_status spg_batch_graph_capture(spg_batch_plan* p, void* ws, int32_t* c_idx, 
   SPG_TRY_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
   hipStream_t saved = p->stream;
   p->stream = cap;
+  p->capturing = true;
   hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) st = enqueue_numeric(p, static_cast<unsigned char*>(ws));
   hipGraph_t g = nullptr;
   if (e == hipSuccess) e = hipStreamEndCapture(cap, &g);
+  p->capturing = false;
   p->stream = saved;
   (void)hipStreamDestroy(cap);
   if (st != SPG_OK || e != hipSuccess || !g) {
@@ -703,12 +754,25 @@ spg_status spg_batch_stats(const spg_batch_plan* p, int64_t* flops, int64_t* row
   return SPG_OK;
 }
 
+spg_status spg_batch_timings(spg_batch_plan* p, float* ms) {
+  if (!p || !ms) return SPG_E_INVALID;
+  if (!p->ev_made) return SPG_E_STATE;
+  SPG_TRY_HIP(hipStreamSynchronize(p->stream));
+  for (int i = 0; i < SPG_BATCH_NUM_PHASES; ++i) {
+    ms[i] = 0.0f;
+    if (p->ran[i]) SPG_TRY_HIP(hipEventElapsedTime(&ms[i], p->ev[2 * i], p->ev[2 * i + 1]));
+  }
+  return SPG_OK;
+}
+
 spg_status spg_batch_plan_destroy(spg_batch_plan* p) {
   if (!p) return SPG_OK;
   if (p->has_graph) {
     (void)hipGraphExecDestroy(p->graph_exec);
     (void)hipGraphDestroy(p->graph);
   }
+  if (p->ev_made)
+    for (int i = 0; i < 2 * SPG_BATCH_NUM_PHASES; ++i) (void)hipEventDestroy(p->ev[i]);
   delete p;
   return SPG_OK;
 }

@@ -105,6 +105,35 @@ def test_graph_replay_matches_eager():
     bp.close()
 
 
+def test_batch_phase_timings_and_capture():
+    """Timed plans report every phase of an eager call; the capture made
+    with timing on replays to the eager result (no event inside the graph)."""
+    import torch
+
+    from paper_2106_14402_amd import binding
+    items = _batch(16, n_lo=2000, n_hi=9000, d_lo=8, d_hi=20)
+    o = binding.make_options(hash_max_flops=64, hash_max_nnz=64, timing=1)
+    bp = _run_batch(items, options=o)
+    t = bp.timings()
+    assert set(t) == {"sym_hash", "sym_dense", "num_hash", "num_dense"}
+    assert all(v >= 0 for v in t.values()) and t["num_dense"] > 0 and t["sym_dense"] > 0
+    eager_idx = bp.c_idx.clone()
+    bp.capture()
+    for _ in range(2):
+        bp.c_idx.fill_(-7)
+        torch.cuda.synchronize()
+        bp.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(bp.c_idx, eager_idx)
+    for b, it in enumerate(items):
+        assert_parity(it.A, it.A, it.semiring, _host(bp.result(b)))
+    bp.close()
+    untimed = _run_batch(items[:2])
+    with pytest.raises(binding.SpgError):
+        untimed.timings()
+    untimed.close()
+
+
 def test_empty_and_degenerate_products_in_batch():
     rng = np.random.default_rng(5)
     empty = spgen.from_pairs(30, 30, np.zeros(0, np.int64), np.zeros(0, np.int64), np.zeros(0, np.float64))
