@@ -153,8 +153,9 @@ typedef struct spg_options {
   int32_t rank_shapes;     /* pass shapes of the rank passes: 1 = the value
                               slots of one chunk width (2^cw) with the widest
                               bitmap; 2 to 5 add 1.25x, 1.5x, 1.75x and 2x the
-                              slots over fewer chunks; each row takes the
-                              shape that needs the fewest passes (default 5) */
+                              slots over fewer chunks; 6 adds 0.75x the slots
+                              over more chunks; each row takes the shape that
+                              needs the fewest passes (default 6) */
   int32_t unsorted;        /* operands whose slices are not sorted ascending:
                               0 (default) they are sorted into the workspace,
                               which holds room for sorted copies of both

@@ -250,7 +250,8 @@ static spg_status plan_init(spg_plan* p, const spg_options* opt_in) {
   // Rank-compressed panels: chunks of 2^cw columns, with 2^cw value slots
   // (half the LDS budget, at most 64 KiB) and a bitmap of as many chunks as
   // the rest of the LDS holds; further shapes trade bitmap for 1.25x to 2x the
-  // slots, for rows whose entries rather than columns bound their passes.
+  // slots, for rows whose entries rather than columns bound their passes, and
+  // slots for bitmap (0.75x), for rows whose columns bound them.
   p->rank = false;
   p->rank_cw = 0;
   p->rank_NC = 0;
@@ -280,13 +281,22 @@ static spg_status plan_init(spg_plan* p, const spg_options* opt_in) {
       sh.n = 1;
       sh.slots[0] = base;
       sh.maxc[0] = maxc;
-      const int more[kRankShapes - 1] = {base + base / 4, base + base / 2, base + 3 * base / 4, 2 * base};
+      const int more[kRankShapes - 2] = {base + base / 4, base + base / 2, base + 3 * base / 4, 2 * base};
       const int want = std::min(p->opt.rank_shapes, kRankShapes);
-      for (int j = 0; j < kRankShapes - 1 && sh.n < want; ++j) {
+      for (int j = 0; j < kRankShapes - 2 && sh.n < want; ++j) {
         const int c = chunks_for(more[j]);
         if (c < 2 || more[j] > 65536) break;  // ranks are 16-bit
         sh.slots[sh.n] = more[j];
         sh.maxc[sh.n] = c;
+        ++sh.n;
+      }
+      // and 0.75x the slots over more chunks: rows of few entries spread over
+      // all columns, whose passes the bitmap width bounds
+      const int narrow = base - base / 4;
+      const int cn = chunks_for(narrow);
+      if (want == kRankShapes && sh.n == kRankShapes - 1 && cn > maxc) {
+        sh.slots[sh.n] = narrow;
+        sh.maxc[sh.n] = cn;
         ++sh.n;
       }
     }

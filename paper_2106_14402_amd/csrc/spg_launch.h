@@ -37,7 +37,7 @@ constexpr int kEscBinBase = 56;
 constexpr int kEscMaxFlops = 32 << (kNumBins - 1 - kEscBinBase);
 
 // Pass shapes of the rank kernel: value slots and chunks per pass.
-constexpr int kRankShapes = 5;
+constexpr int kRankShapes = 6;
 struct RankShapes {
   int n;
   int slots[kRankShapes];
