@@ -185,6 +185,12 @@ __device__ __forceinline__ int wave_or(int x) {
   return x;
 }
 
+__device__ __forceinline__ int wave_max(int x) {
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) x = max(x, __shfl_xor(x, d, kWave));
+  return x;
+}
+
 template <class T>
 __device__ T block_exclusive_scan(T v, T* tmp, T* total) {
   const int lane = threadIdx.x & (kWave - 1);
@@ -300,6 +306,27 @@ struct RowSource {
     } else {
       lo = bs;
       len = static_cast<int32_t>(op->b_ptr[kk + 1] - bs);
+    }
+  }
+};
+
+// A row's segments in one column window whose first round (entries
+// [0, blockDim.x), one per thread) the caller has already loaded into
+// registers; later rounds are loaded as by RowSource.
+template <class SR>
+struct PassSource {
+  RowSource<SR> rest;
+  int64_t lo0;
+  int32_t len0;
+  typename SR::In a0;
+  __device__ int64_t count() const { return rest.count(); }
+  __device__ void load(int64_t t, int64_t& lo, int32_t& len, typename SR::In& a) const {
+    if (t < static_cast<int64_t>(blockDim.x)) {  // the first round: t is this thread's index
+      lo = lo0;
+      len = len0;
+      a = a0;
+    } else {
+      rest.load(t, lo, len, a);
     }
   }
 };

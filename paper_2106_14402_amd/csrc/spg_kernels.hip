@@ -966,6 +966,26 @@ __device__ __forceinline__ void load_words_lds(uint32_t* __restrict__ dst, const
   for (int i = (n4 << 2) + tid; i < n; i += nt) dst[i] = src[i];
 }
 
+// The same copy without registers: each lane of a wave moves 16 bytes from
+// global memory straight into LDS (global_load_lds_dwordx4: the LDS address
+// is the wave's base, here dst + 16 bytes * the wave's first group, plus 16
+// bytes per lane), so every load of the copy is in flight at once.  src and
+// dst 16-byte aligned; returns after the copy has landed (the caller still
+// synchronises the workgroup before other waves read dst).
+__device__ __forceinline__ void load_words_lds_direct(uint32_t* __restrict__ dst, const uint32_t* __restrict__ src,
+                                                      int n) {
+  const int nt = blockDim.x, tid = threadIdx.x, lane = tid & (kWave - 1);
+  const int n4 = n >> 2;
+  const uint4* s4 = reinterpret_cast<const uint4*>(src);
+  uint4* d4 = reinterpret_cast<uint4*>(dst);
+  for (int g = tid - lane; g < n4; g += nt) {  // g: the wave's first group, a multiple of 64
+    const int i = g + lane;
+    if (i < n4) __builtin_amdgcn_global_load_lds(s4 + i, d4 + g, 16, 0, 0);
+  }
+  for (int i = (n4 << 2) + tid; i < n; i += nt) dst[i] = src[i];
+  __builtin_amdgcn_s_waitcnt(0);  // every counter at zero: the copies are in LDS
+}
+
 // Output entries are written once and not read again by the product:
 // streaming stores keep them from displacing the operands in the caches.
 // Used where a workgroup writes long contiguous runs (whole cache lines);
@@ -1779,30 +1799,55 @@ __host__ __device__ inline size_t rank_num_lds_bytes(int cw, int slots, int max_
   return rank_queue_bytes<SR>(nt) + sizeof(typename SR::S) * static_cast<size_t>(slots) + cols / 8 + (cols / 64) * 2;
 }
 
+// cv: when NC <= 64, lane c of every wave holds the row's chunk count c
+// (with one-word B entries the passes are planned from these registers);
+// every chunk holds at most `slots` entries (the caller picks only such
+// shapes).
 template <class SR>
 __device__ void rank_num_row(const Operands& op, int64_t a_lo, int64_t a_hi, int cw, int slots, int NC,
                              int max_chunks, const int32_t* __restrict__ pchunk,
-                             const int32_t* __restrict__ cnt, const uint32_t* __restrict__ keep,
+                             const int32_t* __restrict__ cnt, int cv, const uint32_t* __restrict__ keep,
                              int short_seg, int64_t out, int64_t out_end,
                              int32_t* __restrict__ c_idx, typename SR::Out* __restrict__ c_val,
                              unsigned char* smem, int* info) {
   using S = typename SR::S;
+  using In = typename SR::In;
   const int nt = blockDim.x;
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
-  auto q = RowQueue<typename SR::In>::carve(smem, nt);
+  auto q = RowQueue<In>::carve(smem, nt);
   auto pq = RowQueue<SrPattern::In>::carve(smem, nt);  // same LDS, used by the pattern walk
   unsigned char* p0 = smem + rank_queue_bytes<SR>(nt);
   S* vals = reinterpret_cast<S*>(p0);
   uint32_t* bits = reinterpret_cast<uint32_t*>(p0 + sizeof(S) * static_cast<size_t>(slots));
   uint16_t* pre = reinterpret_cast<uint16_t*>(bits + (static_cast<size_t>(max_chunks) << (cw - 5)));
+  // This thread's entry of the row's first round, kept across the passes:
+  // each pass then loads only its two chunk offsets, issued with the
+  // bitmap loads.  Only one-word B entries leave the registers for it; the
+  // other forms load the round in each pass.
+  constexpr bool kCache = IsPackedB<SR>::value;
+  const bool mine = kCache && tid < a_hi - a_lo;
+  int32_t kk0 = 0;
+  In a0 = In(1);
+  int64_t bs0 = 0;
+  if (mine) {
+    kk0 = op.a_idx[a_lo + tid];
+    a0 = load_val<SR>(op.a_val, a_lo + tid);
+    bs0 = op.b_ptr[kk0];
+  }
   for (int c_lo = 0; c_lo < NC;) {
     if (tid < kWave) {
       // The pass: the longest run of at most max_chunks chunks from c_lo whose
-      // entries fit the slots (one chunk always fits: it has 2^cw columns).
+      // entries fit the slots (at least one: no chunk holds more).
       const int c = c_lo + lane;
       const bool in = lane < max_chunks && c < NC;
-      const int v = in ? cnt[c] : 0;
+      int v = 0;
+      if constexpr (kCache) {
+        const int vr = __shfl(cv, c & (kWave - 1), kWave);
+        v = in ? (NC <= kWave ? vr : cnt[c]) : 0;
+      } else {
+        v = in ? cnt[c] : 0;
+      }
       const int incl = wave_inclusive_scan(v);
       const unsigned long long fit = __ballot(in && incl <= slots);
       const int n = __popcll(fit);
@@ -1823,19 +1868,34 @@ __device__ void rank_num_row(const Operands& op, int64_t a_lo, int64_t a_hi, int
       const int nwords = (wcols + 31) >> 5;
       const int nw64 = (nwords + 1) >> 1;
       const uint64_t* bits64 = reinterpret_cast<const uint64_t*>(bits);
+      // this thread's first-round segment in the range, loaded with the bitmap
+      int32_t s0 = 0, s1 = 0;
+      if (mine) {
+        const int32_t* prow = pchunk + static_cast<int64_t>(kk0) * (NC + 1);
+        s0 = prow[c_lo];
+        s1 = prow[c_hi];
+      }
       for (int t = tid; t < total; t += nt) vals[t] = SR::identity();
       // 1. pattern of the column range: from the kept bitmap, or by a walk
       //    over B's column ids; an odd word count gets a zero word after it
       if (keep) {
-        load_words_lds<1>(bits, keep + (C0 >> 5), nwords);
+        if constexpr (kCache)
+          load_words_lds_direct(bits, keep + (C0 >> 5), nwords);
+        else
+          load_words_lds<1>(bits, keep + (C0 >> 5), nwords);
         if ((nwords & 1) && tid == 0) bits[nwords] = 0u;
         __syncthreads();
       } else {
         for (int t = tid; t < 2 * nw64; t += nt) bits[t] = 0u;
         __syncthreads();
         BitmapSink bs{bits};
-        RowSource<SrPattern> ps{&op, a_lo, a_hi, true, pchunk, NC, c_lo, c_hi};
-        enumerate_src<SrPattern, 2>(op, ps, C0, short_seg, pq, bs);
+        const RowSource<SrPattern> rp{&op, a_lo, a_hi, true, pchunk, NC, c_lo, c_hi};
+        if constexpr (kCache) {
+          const PassSource<SrPattern> ps{rp, bs0 + s0, s1 - s0, SrPattern::In(1)};
+          enumerate_src<SrPattern, 2>(op, ps, C0, short_seg, pq, bs);
+        } else {
+          enumerate_src<SrPattern, 2>(op, rp, C0, short_seg, pq, bs);
+        }
       }
       // 2. rank of the first entry of every 64-bit word (contiguous words per thread)
       const int wpt = (nw64 + nt - 1) / nt;
@@ -1851,8 +1911,13 @@ __device__ void rank_num_row(const Operands& op, int64_t a_lo, int64_t a_hi, int
       __syncthreads();
       // 3. values, combined at their ranks
       RankSink<SR> rs{bits64, pre, vals};
-      RowSource<SR> vs{&op, a_lo, a_hi, true, pchunk, NC, c_lo, c_hi};
-      enumerate_src<SR, 2>(op, vs, C0, short_seg, q, rs);
+      const RowSource<SR> rv{&op, a_lo, a_hi, true, pchunk, NC, c_lo, c_hi};
+      if constexpr (kCache) {
+        const PassSource<SR> vs{rv, bs0 + s0, s1 - s0, a0};
+        enumerate_src<SR, 2>(op, vs, C0, short_seg, q, rs);
+      } else {
+        enumerate_src<SR, 2>(op, rv, C0, short_seg, q, rs);
+      }
       // 4. write the range out: the values in slot order; then the column
       //    ids, placed at their ranks in LDS (over the value slots, 4 bytes
       //    each at most as wide as a slot) and written in order
@@ -1912,11 +1977,30 @@ __global__ __launch_bounds__(1024) void k_rank_num(Operands op, const int32_t* _
     } else {
       const int32_t slot = keep_slot ? uniform(keep_slot[row]) : -1;
       const uint32_t* keep = slot >= 0 ? keep_store + static_cast<int64_t>(slot) * keep_nwords : nullptr;
+      // the row's chunk counts (with one-word B entries: in registers when
+      // NC <= 64, and their largest; the other forms bound a chunk by the
+      // row's entries, which keeps their registers free)
+      const int32_t* rc = rcnt + it * NC;
+      int cv = 0;
+      int64_t cmax = nnz;
+      if constexpr (IsPackedB<SR>::value) {
+        const int lane = threadIdx.x & (kWave - 1);
+        int m = 0;
+        if (NC <= kWave) {
+          cv = lane < NC ? rc[lane] : 0;
+          m = cv;
+        } else {
+          for (int c = lane; c < NC; c += kWave) m = max(m, rc[c]);
+        }
+        cmax = wave_max(m);
+      }
       // the pass shape with the fewest passes for a row spread over all
-      // chunks: max(chunks / chunks per pass, entries / slots)
+      // chunks, max(chunks / chunks per pass, entries / slots), among those
+      // whose slots hold any chunk of the row (shape 0 holds any chunk)
       int k = 0;
       int64_t best = INT64_MAX;
       for (int j = 0; j < sh.n; ++j) {
+        if (sh.slots[j] < (1 << cw) && sh.slots[j] < cmax) continue;
         const int64_t pj = max(static_cast<int64_t>((NC + sh.maxc[j] - 1) / sh.maxc[j]),
                                (nnz + sh.slots[j] - 1) / sh.slots[j]);
         if (pj < best) {
@@ -1924,7 +2008,7 @@ __global__ __launch_bounds__(1024) void k_rank_num(Operands op, const int32_t* _
           k = j;
         }
       }
-      rank_num_row<SR>(op, a_lo, a_hi, cw, sh.slots[k], NC, sh.maxc[k], pchunk, rcnt + it * NC, keep, short_seg,
+      rank_num_row<SR>(op, a_lo, a_hi, cw, sh.slots[k], NC, sh.maxc[k], pchunk, rc, cv, keep, short_seg,
                        out, out_end, c_idx, c_val, smem, info);
     }
   }
