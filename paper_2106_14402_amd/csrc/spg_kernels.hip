@@ -1296,104 +1296,6 @@ __device__ void bitonic_sort(int32_t* keys, S* vals, int N, bool with_vals) {
   __syncthreads();
 }
 
-// Bitonic sort of N = 4 * blockDim.x (key, value) pairs held four per thread
-// in registers (element e = 4 * thread + r): the compare-exchanges at
-// distance 1 and 2 stay inside a thread, those at distance 4 to 128 inside a
-// wave (cross-lane shuffles), and only those at distance 256 and more go
-// through LDS with a workgroup barrier.  keys/vals: the N pairs in LDS on
-// entry (after a barrier) and, sorted ascending by key, on exit.
-template <class S, bool kVals>
-__device__ void bitonic_sort_reg4(int32_t* keys, S* vals, int N) {
-  const int tid = threadIdx.x;
-  const int e0 = 4 * tid;
-  int32_t k[4];
-  S v[4];
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    k[r] = keys[e0 + r];
-    if constexpr (kVals) v[r] = vals[e0 + r];
-  }
-  for (int kk = 2; kk <= N; kk <<= 1) {
-    int j = kk >> 1;
-    if (j >= 256) {
-      __syncthreads();  // the previous reads of keys/vals are done
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        keys[e0 + r] = k[r];
-        if constexpr (kVals) vals[e0 + r] = v[r];
-      }
-      __syncthreads();
-      for (; j >= 256; j >>= 1) {
-        if ((e0 & j) == 0) {  // this thread's four elements are the lower ends of their pairs
-          const bool up = (e0 & kk) == 0;
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int a = e0 + r, b = a + j;
-            const int32_t ka = keys[a], kb = keys[b];
-            if ((ka > kb) == up) {
-              keys[a] = kb;
-              keys[b] = ka;
-              if constexpr (kVals) {
-                const S t = vals[a];
-                vals[a] = vals[b];
-                vals[b] = t;
-              }
-            }
-          }
-        }
-        __syncthreads();
-      }
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        k[r] = keys[e0 + r];
-        if constexpr (kVals) v[r] = vals[e0 + r];
-      }
-    }
-    const bool up = (e0 & kk) == 0;  // the same for the four elements (kk >= 2... see below)
-    for (; j >= 4; j >>= 1) {
-      const int lm = j >> 2;
-      const bool lower = (e0 & j) == 0;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int32_t pk = __shfl_xor(k[r], lm, kWave);
-        S pv{};
-        if constexpr (kVals) pv = __shfl_xor(v[r], lm, kWave);
-        const int32_t klo = lower ? k[r] : pk, khi = lower ? pk : k[r];
-        if ((klo > khi) == up) {
-          k[r] = pk;
-          if constexpr (kVals) v[r] = pv;
-        }
-      }
-    }
-    for (; j >= 1; j >>= 1) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        if ((r & j) == 0) {
-          const int r2 = r | j;
-          const bool upr = ((e0 + r) & kk) == 0;
-          if ((k[r] > k[r2]) == upr) {
-            const int32_t t = k[r];
-            k[r] = k[r2];
-            k[r2] = t;
-            if constexpr (kVals) {
-              const S tv = v[r];
-              v[r] = v[r2];
-              v[r2] = tv;
-            }
-          }
-        }
-      }
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    keys[e0 + r] = k[r];
-    if constexpr (kVals) vals[e0 + r] = v[r];
-  }
-  __syncthreads();
-}
-
 constexpr int kMaxSlotsPerThread = 16;
 
 // LDS hash accumulator for one row, then compaction, bitonic sort and
@@ -1589,19 +1491,116 @@ __global__ __launch_bounds__(1024) void k_hash_num(Operands op, const int32_t* _
   }
 }
 
+// Sort of n <= kBucketPerThread * blockDim.x (key, value) pairs in LDS by key
+// (keys >= 0), by buckets of the row's own key range: every pair goes to one
+// of blockDim.x buckets by a monotone function of its key (so the buckets
+// are in key order), the buckets are laid out by a scan of their counts, and
+// every pair then finds its place inside its bucket by counting the smaller
+// keys there (equal keys by bucket position).  Buckets hold a few pairs each
+// when the keys are spread over their range; the cost per pair is that
+// bucket's size.  cnt: blockDim.x + 1 ints of LDS; red: 32 ints of LDS (scan
+// scratch).  keys/vals hold the pairs on entry (after a barrier) and, sorted,
+// on exit (after a barrier).
+constexpr int kBucketPerThread = 4;
+
+template <class S, bool kVals>
+__device__ void bucket_sort(int32_t* keys, S* vals, int n, int* cnt, int* red) {
+  constexpr int R = kBucketPerThread;
+  const int nt = blockDim.x, tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid >> 6;
+  const int e0 = R * tid;
+  int32_t k[R];
+  S v[R];
+  int kmin = INT32_MAX, kmax = 0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    k[r] = 0;
+    if (e0 + r < n) {
+      k[r] = keys[e0 + r];
+      if constexpr (kVals) v[r] = vals[e0 + r];
+      kmin = min(kmin, k[r]);
+      kmax = max(kmax, k[r]);
+    }
+  }
+  // the key range of the pairs
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) {
+    kmin = min(kmin, __shfl_xor(kmin, d, kWave));
+    kmax = max(kmax, __shfl_xor(kmax, d, kWave));
+  }
+  if (lane == 0) {
+    red[wid] = kmin;
+    red[16 + wid] = kmax;
+  }
+  cnt[tid] = 0;
+  __syncthreads();
+  const int nw = nt >> 6;
+  for (int w = 0; w < nw; ++w) {
+    kmin = min(kmin, red[w]);
+    kmax = max(kmax, red[16 + w]);
+  }
+  // bucket and position in it: (key - kmin) * scale is non-decreasing in the key
+  const float scale = static_cast<float>(nt) / (static_cast<float>(kmax - kmin) + 1.0f);
+  int g[R], p[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    g[r] = 0;
+    p[r] = 0;
+    if (e0 + r < n) {
+      g[r] = min(nt - 1, static_cast<int>(static_cast<float>(k[r] - kmin) * scale));
+      p[r] = atomicAdd(&cnt[g[r]], 1);
+    }
+  }
+  __syncthreads();
+  int total;
+  const int start = block_exclusive_scan(cnt[tid], red, &total);  // ends with a barrier
+  cnt[tid] = start;
+  if (tid == 0) cnt[nt] = n;
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    if (e0 + r < n) {
+      const int d = cnt[g[r]] + p[r];
+      keys[d] = k[r];
+      if constexpr (kVals) vals[d] = v[r];
+    }
+  __syncthreads();
+  int dst[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    dst[r] = 0;
+    if (e0 + r < n) {
+      const int b0 = cnt[g[r]], b1 = cnt[g[r] + 1], me = b0 + p[r];
+      int rank = 0;
+      for (int i = b0; i < b1; ++i) {
+        const int32_t ki = keys[i];
+        rank += (ki < k[r] || (ki == k[r] && i < me)) ? 1 : 0;
+      }
+      dst[r] = b0 + rank;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    if (e0 + r < n) {
+      keys[dst[r]] = k[r];
+      if constexpr (kVals) vals[dst[r]] = v[r];
+    }
+  __syncthreads();
+}
+
 // ---------------------------------------------------------------------------
 // Expand-sort-compress (ESC) numeric rows: for a row whose products are
 // almost all distinct entries (flops close to nnz, the low compression ratio
 // for which the paper's hybrid picks a heap over a hash table, Sec. 4.1),
 // every product is written to its own LDS position (product j to position j,
 // consecutive products to consecutive positions: no hashing, no atomics),
-// the (column, value) pairs are sorted by column with the bitonic network,
-// and runs of one column are combined.  Products are dealt flat: product j
+// the (column, value) pairs are sorted by column (bucket_sort), and runs of
+// one column are combined.  Products are dealt flat: product j
 // of a block of A entries goes to thread j mod blockDim, its B row found by a
 // binary search over the block's prefix of B-row lengths.
 // ---------------------------------------------------------------------------
 constexpr int kEscUnroll = 4;      // products per thread per batch of loads
-constexpr int kEscMaxPerThread = 16;
+constexpr int kEscMaxPerThread = kBucketPerThread;  // positions per thread in the compress step
 
 inline int esc_threads(int N) { return std::max(64, std::min(1024, N / 4)); }
 
@@ -1611,7 +1610,7 @@ __host__ __device__ inline size_t esc_lds_bytes(int N, int nt) {
 }
 
 template <class SR>
-__global__ __launch_bounds__(1024) void k_esc_num(Operands op, const int32_t* __restrict__ rows, int64_t nrows,
+__global__ __launch_bounds__(1024, sizeof(typename SR::S) > 4 ? 6 : 8) void k_esc_num(Operands op, const int32_t* __restrict__ rows, int64_t nrows,
                                                   int N, const int64_t* __restrict__ c_ptr,
                                                   int32_t* __restrict__ c_idx,
                                                   typename SR::Out* __restrict__ c_val) {
@@ -1681,13 +1680,9 @@ __global__ __launch_bounds__(1024) void k_esc_num(Operands op, const int32_t* __
       base += E;
       __syncthreads();  // the queue arrays are rewritten by the next block of entries
     }
-    for (int t = base + tid; t < N; t += nt) keys[t] = INT32_MAX;
     __syncthreads();
-    // 2. sort by column
-    if (N == 4 * nt)
-      bitonic_sort_reg4<S, !SR::kPattern>(keys, vals, N);
-    else
-      bitonic_sort<S>(keys, vals, N, !SR::kPattern);
+    // 2. sort by column (the class bound N is at most kBucketPerThread * nt)
+    bucket_sort<S, !SR::kPattern>(keys, vals, base, q.pfx, q.ctr + 2);
     // 3. compress: each thread a contiguous run of positions; the first
     //    entry of every column keeps its place in the output, the others are
     //    combined into it (few: the rows here have almost no repeats)
@@ -2322,7 +2317,7 @@ static hipError_t esc_num_t(const Operands& op, const int32_t* rows, int64_t nro
                             int32_t* c_idx, void* c_val, hipStream_t s) {
   if (nrows <= 0) return hipSuccess;
   const int nt = esc_threads(N);
-  if (N / nt > kEscMaxPerThread || N > kEscMaxFlops) return hipErrorInvalidValue;
+  if (N > kBucketPerThread * nt || N > kEscMaxFlops) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_esc_num<SR>, dim3(grid_for(nrows, 0)), dim3(nt), esc_lds_bytes<SR>(N, nt), s, op, rows,
                      nrows, N, c_ptr, c_idx, static_cast<typename SR::Out*>(c_val));
   return hipGetLastError();
