@@ -318,16 +318,16 @@ def dominant_kernel(H, phase, rownnz, p, s_in, s_out, sr):
     sym_dense_rows = fl > p.hash_max_flops()
     hmn = p.hash_max_nnz()
     ranked = phase.get("num_rank", 0.0) > 0
-    heavy = sym_dense_rows & (rownnz > hmn)
-    fixed_rows = heavy & (rownnz * p.rank_dense_div() >= H.ncols)
-    rank_rows = heavy & ~fixed_rows if ranked else np.zeros_like(sym_dense_rows)
     # pattern-only products expand the rows whose symbolic bitmap was kept
     # (at least one product per bitmap word; the budget is taken as enough)
     kept = sym_dense_rows & (fl >= -(-H.ncols // 32)) if sr == "or_and_bool" and not ranked \
         else np.zeros_like(sym_dense_rows)
-    num_dense_rows = (rownnz > hmn) & ~rank_rows & ~kept
     o = p.options()
     esc_rows = (rownnz > 0) & ~kept & (fl <= max(0, o.esc_max_flops)) & (16 * fl <= o.esc_ratio_x16 * rownnz)
+    heavy = sym_dense_rows & (rownnz > hmn) & ~esc_rows
+    fixed_rows = heavy & (rownnz * p.rank_dense_div() >= H.ncols)
+    rank_rows = heavy & ~fixed_rows if ranked else np.zeros_like(sym_dense_rows)
+    num_dense_rows = (rownnz > hmn) & ~rank_rows & ~kept & ~esc_rows
     hash_rows = (rownnz > 0) & (rownnz <= hmn) & ~kept & ~esc_rows
 
     def num_bytes(rows):

@@ -185,10 +185,11 @@ typedef struct spg_options {
                               columns), else through 8-byte (column, value)
                               pairs; -1 always through pairs */
   int32_t esc_max_flops;   /* numeric phase: rows of at most this many
-                              products (up to 4096; 0 = 4096, -1 = never)
-                              whose compression ratio flops / nnz is at most
-                              esc_ratio_x16 / 16 are expanded, sorted and
-                              compressed in LDS instead of hashed */
+                              products (up to 8192; 0 = 8192, -1 = never)
+                              whose compression ratio
+                              flops / nnz is at most esc_ratio_x16 / 16 are
+                              expanded, sorted and compressed in LDS instead
+                              of hashed or ranked */
   int32_t esc_ratio_x16;   /* 16 x that compression ratio (default 20: 1.25) */
 } spg_options;
 

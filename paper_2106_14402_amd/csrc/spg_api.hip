@@ -244,7 +244,7 @@ static spg_status plan_init(spg_plan* p, const spg_options* opt_in) {
   p->bp.split_heavy = p->split ? 1 : 0;
   // Expand-sort-compress for rows of at most esc_max_flops products whose
   // compression ratio flops/nnz is at most esc_ratio_x16 / 16.
-  p->bp.esc_max_flops = (p->split || p->opt.esc_max_flops < 0) ? 0 : p->opt.esc_max_flops;
+  p->bp.esc_max_flops = (p->split || p->opt.esc_max_flops < 0) ? 0 : std::min(p->opt.esc_max_flops, esc_class_limit(p->sr));
   p->bp.esc_ratio_x16 = p->opt.esc_ratio_x16;
 
   // Rank-compressed panels: chunks of 2^cw columns, with 2^cw value slots
@@ -1006,9 +1006,13 @@ static spg_status numeric_range(spg_plan* p, void* ws, int32_t rb, int32_t re, i
   const int64_t kcols = op.k;
   const int64_t fixed_lo = std::max<int64_t>(p->bp.hash_max_nnz + 1,
                                              (kcols + p->opt.rank_dense_div - 1) / p->opt.rank_dense_div);
+  RankShapes shapes = p->rank_shapes;
+  shapes.flops = reinterpret_cast<const int64_t*>(w + p->off_flops);
+  shapes.esc_max_flops = p->bp.esc_max_flops;
+  shapes.esc_ratio_x16 = p->bp.esc_ratio_x16;
   auto rank_launch = [&](bool fixed) {
     return launch_rank_num(p->sr, fixed, opr, rows_dense_sym, p->n_dense_sym, p->lists_rb, p->lists_re,
-                           p->rank_cw, p->rank_NC, p->rank_shapes, pchunk, rcnt,
+                           p->rank_cw, p->rank_NC, shapes, pchunk, rcnt,
                            fixed ? fixed_lo : p->bp.hash_max_nnz + 1, fixed ? INT64_MAX : fixed_lo, p->num_wlog2,
                            p->num_P, p->opt.dense_threads, p->opt.short_seg, kstore, kslot, p->keep_stride,
                            p->c_ptr, c_idx, c_val, s);

@@ -273,7 +273,8 @@ __global__ void k_count_num_bins(int32_t m, int32_t r0, int scanned, const int64
   if (i < m) {
     const int64_t nz = scanned ? c_ptr[i + 1] - c_ptr[i] : c_ptr[i + 1];
     const bool split = bp.split_heavy && flops[i] > bp.hash_max_flops;
-    const bool ranked = bp.rank_heavy && flops[i] > bp.hash_max_flops && nz > bp.hash_max_nnz;
+    const bool ranked = bp.rank_heavy && flops[i] > bp.hash_max_flops && nz > bp.hash_max_nnz &&
+                        !esc_row(nz, flops[i], bp.esc_max_flops, bp.esc_ratio_x16);
     const bool kept = bp.row_slot && flops[i] > bp.hash_max_flops && bp.row_slot[i] >= 0;
     atomicAdd(&lc[kept ? kExpandBin : ((split || ranked) ? 0 : num_bin(nz, flops[i], bp))], 1u);
   }
@@ -310,7 +311,8 @@ __global__ void k_scatter(int mode, int32_t m, int32_t r0, const int64_t* __rest
       bin = kExpandBin;
     else {
       const int64_t nz = c_ptr[i + 1] - c_ptr[i];
-      const bool ranked = bp.rank_heavy && flops[i] > bp.hash_max_flops && nz > bp.hash_max_nnz;
+      const bool ranked = bp.rank_heavy && flops[i] > bp.hash_max_flops && nz > bp.hash_max_nnz &&
+                          !esc_row(nz, flops[i], bp.esc_max_flops, bp.esc_ratio_x16);
       bin = ((bp.split_heavy && flops[i] > bp.hash_max_flops) || ranked) ? 0 : num_bin(nz, flops[i], bp);
     }
     if (bin > 0) local = atomicAdd(&lc[bin], 1u);
@@ -1491,7 +1493,7 @@ __global__ __launch_bounds__(1024) void k_hash_num(Operands op, const int32_t* _
   }
 }
 
-// Sort of n <= kBucketPerThread * blockDim.x (key, value) pairs in LDS by key
+// Sort of n <= R * blockDim.x (key, value) pairs in LDS by key
 // (keys >= 0), by buckets of the row's own key range: every pair goes to one
 // of blockDim.x buckets by a monotone function of its key (so the buckets
 // are in key order), the buckets are laid out by a scan of their counts, and
@@ -1501,11 +1503,8 @@ __global__ __launch_bounds__(1024) void k_hash_num(Operands op, const int32_t* _
 // bucket's size.  cnt: blockDim.x + 1 ints of LDS; red: 32 ints of LDS (scan
 // scratch).  keys/vals hold the pairs on entry (after a barrier) and, sorted,
 // on exit (after a barrier).
-constexpr int kBucketPerThread = 4;
-
-template <class S, bool kVals>
+template <class S, bool kVals, int R>
 __device__ void bucket_sort(int32_t* keys, S* vals, int n, int* cnt, int* red) {
-  constexpr int R = kBucketPerThread;
   const int nt = blockDim.x, tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid >> 6;
   const int e0 = R * tid;
   int32_t k[R];
@@ -1600,17 +1599,22 @@ __device__ void bucket_sort(int32_t* keys, S* vals, int n, int* cnt, int* red) {
 // binary search over the block's prefix of B-row lengths.
 // ---------------------------------------------------------------------------
 constexpr int kEscUnroll = 4;      // products per thread per batch of loads
-constexpr int kEscMaxPerThread = kBucketPerThread;  // positions per thread in the compress step
 
+// Threads of a class of N products: N / 4 (at most 1024), so each thread
+// holds R = N / threads of them, 4 or 8.
 inline int esc_threads(int N) { return std::max(64, std::min(1024, N / 4)); }
+inline int esc_per_thread(int N) { return std::max(4, N / esc_threads(N)); }
 
 template <class SR>
 __host__ __device__ inline size_t esc_lds_bytes(int N, int nt) {
   return RowQueue<typename SR::In>::bytes(nt) + static_cast<size_t>(N) * (4 + sizeof(typename SR::S));
 }
 
-template <class SR>
-__global__ __launch_bounds__(1024, sizeof(typename SR::S) > 4 ? 6 : 8) void k_esc_num(Operands op, const int32_t* __restrict__ rows, int64_t nrows,
+// R: products per thread (4 or 8); with 4 the kernel keeps its registers
+// within what two 1024-thread workgroups per compute unit allow (4-byte
+// values); the 8192-product class takes most of the LDS anyway.
+template <class SR, int R>
+__global__ __launch_bounds__(1024, R > 4 ? 4 : (sizeof(typename SR::S) > 4 ? 6 : 8)) void k_esc_num(Operands op, const int32_t* __restrict__ rows, int64_t nrows,
                                                   int N, const int64_t* __restrict__ c_ptr,
                                                   int32_t* __restrict__ c_idx,
                                                   typename SR::Out* __restrict__ c_val) {
@@ -1681,19 +1685,19 @@ __global__ __launch_bounds__(1024, sizeof(typename SR::S) > 4 ? 6 : 8) void k_es
       __syncthreads();  // the queue arrays are rewritten by the next block of entries
     }
     __syncthreads();
-    // 2. sort by column (the class bound N is at most kBucketPerThread * nt)
-    bucket_sort<S, !SR::kPattern>(keys, vals, base, q.pfx, q.ctr + 2);
+    // 2. sort by column (the class bound N is at most R * nt)
+    bucket_sort<S, !SR::kPattern, R>(keys, vals, base, q.pfx, q.ctr + 2);
     // 3. compress: each thread a contiguous run of positions; the first
     //    entry of every column keeps its place in the output, the others are
     //    combined into it (few: the rows here have almost no repeats)
     const int ch = (base + nt - 1) / nt;
     const int e0 = min(base, tid * ch), e1 = min(base, e0 + ch);
-    int32_t kr[kEscMaxPerThread];
-    S vr[kEscMaxPerThread];
-    bool head[kEscMaxPerThread];
+    int32_t kr[R];
+    S vr[R];
+    bool head[R];
     int cnt = 0;
 #pragma unroll
-    for (int r = 0; r < kEscMaxPerThread; ++r) {
+    for (int r = 0; r < R; ++r) {
       const int e = e0 + r;
       head[r] = false;
       if (e < e1) {
@@ -1706,7 +1710,7 @@ __global__ __launch_bounds__(1024, sizeof(typename SR::S) > 4 ? 6 : 8) void k_es
     int nnz;
     int pos = block_exclusive_scan(cnt, q.ctr + 2, &nnz);  // ends with a barrier: keys may be rewritten
 #pragma unroll
-    for (int r = 0; r < kEscMaxPerThread; ++r) {
+    for (int r = 0; r < R; ++r) {
       if (e0 + r < e1 && head[r]) {
         keys[pos] = kr[r];
         if constexpr (!SR::kPattern) vals[pos] = vr[r];
@@ -1717,7 +1721,7 @@ __global__ __launch_bounds__(1024, sizeof(typename SR::S) > 4 ? 6 : 8) void k_es
     if constexpr (!SR::kPattern) {
       pos = block_exclusive_scan(cnt, q.ctr + 2, &nnz);  // first head position of this thread's run
 #pragma unroll
-      for (int r = 0; r < kEscMaxPerThread; ++r) {
+      for (int r = 0; r < R; ++r) {
         if (e0 + r < e1) {
           if (head[r])
             ++pos;
@@ -1961,6 +1965,8 @@ __global__ __launch_bounds__(1024) void k_rank_num(Operands op, const int32_t* _
     const int64_t out = uniform64(c_ptr[row]), out_end = uniform64(c_ptr[row + 1]);
     const int64_t nnz = out_end - out;
     if (nnz < nnz_lo || nnz >= nnz_hi) continue;  // another launch takes this row
+    if (sh.esc_max_flops > 0 && esc_row(nnz, sh.flops[row], sh.esc_max_flops, sh.esc_ratio_x16))
+      continue;  // expanded, sorted and compressed instead
     const int64_t a_lo = op.a_ptr[row], a_hi = op.a_ptr[row + 1];
     if constexpr (kFixed) {
       // fixed panels of 2^wlog2 columns = 2^(wlog2-cw) chunks
@@ -2317,10 +2323,27 @@ static hipError_t esc_num_t(const Operands& op, const int32_t* rows, int64_t nro
                             int32_t* c_idx, void* c_val, hipStream_t s) {
   if (nrows <= 0) return hipSuccess;
   const int nt = esc_threads(N);
-  if (N > kBucketPerThread * nt || N > kEscMaxFlops) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_esc_num<SR>, dim3(grid_for(nrows, 0)), dim3(nt), esc_lds_bytes<SR>(N, nt), s, op, rows,
-                     nrows, N, c_ptr, c_idx, static_cast<typename SR::Out*>(c_val));
+  const int R = esc_per_thread(N);
+  const size_t lds = esc_lds_bytes<SR>(N, nt);
+  if (N > R * nt || N > kEscMaxFlops || lds > static_cast<size_t>(max_lds_bytes())) return hipErrorInvalidValue;
+  auto* cv = static_cast<typename SR::Out*>(c_val);
+  if (R == 4)
+    hipLaunchKernelGGL((k_esc_num<SR, 4>), dim3(grid_for(nrows, 0)), dim3(nt), lds, s, op, rows, nrows, N, c_ptr,
+                       c_idx, cv);
+  else if (R == 8)
+    hipLaunchKernelGGL((k_esc_num<SR, 8>), dim3(grid_for(nrows, 0)), dim3(nt), lds, s, op, rows, nrows, N, c_ptr,
+                       c_idx, cv);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
+}
+
+// The largest expand-sort-compress class whose LDS fits the device.
+template <class SR>
+static int esc_class_limit_t() {
+  int N = kEscMaxFlops;
+  while (N > 32 && esc_lds_bytes<SR>(N, esc_threads(N)) > static_cast<size_t>(max_lds_bytes())) N >>= 1;
+  return N;
 }
 
 template <class SR>
@@ -2520,6 +2543,7 @@ hipError_t launch_esc_num(int sr, const Operands& op, const int32_t* rows, int64
                           const int64_t* c_ptr, int32_t* c_idx, void* c_val, hipStream_t s) {
   SPG_DISPATCH(sr, esc_num_t, op, rows, nrows, N, c_ptr, c_idx, c_val, s)
 }
+int esc_class_limit(int sr) { SPG_DISPATCH(sr, esc_class_limit_t) }
 
 hipError_t launch_dense_num(int sr, const Operands& op, const int32_t* rows, int64_t nrows,
                             int wlog2, int P, const int32_t* pidx, int nt, int short_seg,

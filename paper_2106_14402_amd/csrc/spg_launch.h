@@ -32,9 +32,10 @@ struct BinParams {
 };
 constexpr int kExpandBin = 15;  // numeric bin of rows whose bitmap was kept
 // Numeric bins kEscBinBase.. hold the expand-sort-compress classes of
-// 32 << (bin - kEscBinBase) products (up to 4096); dense bins stay below.
-constexpr int kEscBinBase = 56;
+// 32 << (bin - kEscBinBase) products (up to 8192); dense bins stay below.
+constexpr int kEscBinBase = 55;
 constexpr int kEscMaxFlops = 32 << (kNumBins - 1 - kEscBinBase);
+static_assert(kDenseBinBase + 47 - 9 < kEscBinBase, "dense_bin stays below the expand-sort-compress bins");
 
 // Pass shapes of the rank kernel: value slots and chunks per pass.
 constexpr int kRankShapes = 6;
@@ -42,7 +43,15 @@ struct RankShapes {
   int n;
   int slots[kRankShapes];
   int maxc[kRankShapes];
+  // rows the expand-sort-compress kernel takes (esc_max_flops > 0: flops per
+  // row and the bounds of num_bin) are left out of the rank launches
+  const int64_t* flops;
+  int64_t esc_max_flops, esc_ratio_x16;
 };
+// A row the expand-sort-compress kernel takes.
+__host__ __device__ inline bool esc_row(int64_t nnz, int64_t flops, int64_t esc_max_flops, int64_t esc_ratio_x16) {
+  return esc_max_flops > 0 && nnz > 0 && flops <= esc_max_flops && 16 * flops <= esc_ratio_x16 * nnz;
+}
 
 // Symbolic bitmaps kept for the numeric phase of pattern-only products.
 struct KeepBitmaps {
@@ -76,7 +85,7 @@ __host__ __device__ inline int ceil_log2_u64(uint64_t x) {
 __host__ __device__ inline int dense_bin(int64_t flops) {
   int fl = floor_log2_u64(static_cast<uint64_t>(flops));
   fl = fl > 47 ? 47 : fl;
-  fl = fl < 8 ? 8 : fl;  // below the expand-sort-compress bins
+  fl = fl < 9 ? 9 : fl;  // below the expand-sort-compress bins
   return kDenseBinBase + (47 - fl);
 }
 __host__ __device__ inline int esc_bin(int64_t flops) {
@@ -94,8 +103,7 @@ __host__ __device__ inline int sym_bin(int64_t flops, const BinParams& bp) {
 }
 __host__ __device__ inline int num_bin(int64_t nnz, int64_t flops, const BinParams& bp) {
   if (nnz <= 0) return 0;
-  if (bp.esc_max_flops > 0 && flops <= bp.esc_max_flops && 16 * flops <= bp.esc_ratio_x16 * nnz)
-    return esc_bin(flops);
+  if (esc_row(nnz, flops, bp.esc_max_flops, bp.esc_ratio_x16)) return esc_bin(flops);
   if (nnz <= bp.hash_max_nnz) return hash_class(nnz);
   return dense_bin(flops);
 }
@@ -200,6 +208,9 @@ hipError_t launch_dense_num_sub(int sr, const Operands& op, const int32_t* rows,
 // Expand-sort-compress rows of one class (N = 32 << class products at most):
 // every product at its own LDS position, a bitonic sort by column, equal
 // columns combined.  sr as for launch_hash_num.
+// The largest class (products per row) the expand-sort-compress kernel holds
+// in LDS for semiring code sr.
+int esc_class_limit(int sr);
 hipError_t launch_esc_num(int sr, const Operands& op, const int32_t* rows, int64_t nrows, int N,
                           const int64_t* c_ptr, int32_t* c_idx, void* c_val, hipStream_t s);
 // sr: semiring code 0..6, or 7 for the pattern-only boolean product.

@@ -56,3 +56,25 @@ def test_esc_long_a_rows_and_small_classes():
     _ = rows
     got = run_gpu(A, A, "plus_times_f64", opts(esc_ratio_x16=1024))
     assert_parity(A, A, "plus_times_f64", got)
+
+
+@pytest.mark.parametrize("sr", ["plus_times_f64", "min_plus_i32", "max_times_f32", "or_and_bool"])
+def test_esc_largest_class_among_heavy_rows(sr):
+    """Rows of 4097 to 8192 products with almost no repeats (heavy rows of
+    the dense symbolic list, over 2^20 columns) take the 8192-product class
+    instead of the rank passes; lighter and heavier rows keep their paths."""
+    rng = np.random.default_rng(12)
+    kmid = 20000
+    degs = np.concatenate([rng.integers(60, 110, 1500), rng.integers(1, 40, 300), rng.integers(150, 260, 60)])
+    major, minor = spgen.distinct_minor(degs.size, kmid, degs, rng)
+    A = spgen.from_pairs(degs.size, kmid, major, minor, None, presorted=True)
+    B = spgen.erdos_renyi(kmid, 70, rng, values=None, ncols=1 << 20)
+    if sr != "or_and_bool":
+        A = with_semiring_values(A, sr, np.random.default_rng(13))
+        B = with_semiring_values(B, sr, np.random.default_rng(14))
+    got = run_gpu(A, B, sr)
+    assert_parity(A, B, sr, got)
+    off = run_gpu(A, B, sr, opts(esc_max_flops=4096))
+    if sr in ("min_plus_i32", "or_and_bool"):
+        for x, y in zip(got, off):
+            assert x is None and y is None or np.array_equal(x, y)
