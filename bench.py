@@ -678,22 +678,25 @@ def batched_dominant(items, bp, phase_ms, knobs):
     (symbolic)."""
     hmn = int(knobs.get("hash_max_nnz", 2048))
     hmf = int(knobs.get("hash_max_flops", 8192))
+    esc_max = int(knobs.get("esc_max_flops", 8192))  # the batch's semirings all hold the 8192 class
+    esc_ratio = int(knobs.get("esc_ratio_x16", 20))
     byts = {k: 0 for k in phase_ms}
     for b, it in enumerate(items):
         s_io = 8 if it.semiring == "plus_times_f64" else 4
         fl, deg = row_flops(it.A)
         rownnz = np.diff(bp.c_ptr[bp.pool_off[b]:bp.pool_off[b + 1]].cpu().numpy())
-        dense = rownnz > hmn
-        hashed = (rownnz > 0) & ~dense
+        esc = (rownnz > 0) & (fl <= esc_max) & (16 * fl <= esc_ratio * rownnz)
+        dense = (rownnz > hmn) & ~esc
+        hashed = (rownnz > 0) & ~dense & ~esc
         heavy = fl > hmf
         light = (fl > 0) & ~heavy
-        for name, rows, sym in (("num_dense", dense, False), ("num_hash", hashed, False),
+        for name, rows, sym in (("num_dense", dense, False), ("num_hash", hashed, False), ("num_esc", esc, False),
                                 ("sym_dense", heavy, True), ("sym_hash", light, True)):
             if rows.any():
                 byts[name] += alg_bytes_dense(it.A, int(deg[rows].sum()), int(rows.sum()),
                                               int(rownnz[rows].sum()), s_io, s_io, sym)
-    kern = {"num_dense": "k_dense_num_b", "num_hash": "k_hash_num_b", "sym_dense": "k_dense_sym_b",
-            "sym_hash": "k_hash_sym_b"}
+    kern = {"num_dense": "k_dense_num_b", "num_hash": "k_hash_num_b", "num_esc": "k_esc_num_b",
+            "sym_dense": "k_dense_sym_b", "sym_hash": "k_hash_sym_b"}
     name = max(phase_ms, key=lambda k: phase_ms[k])
     return {"kernel": kern[name], "semiring": "plus_times_f64+min_plus_i32", "ms": phase_ms[name],
             "bytes": byts[name]}

@@ -479,7 +479,8 @@ spg_status spg_batch_stats(const spg_batch_plan* plan, int64_t* flops, int64_t* 
 #define SPG_BATCH_PHASE_SYM_DENSE 1
 #define SPG_BATCH_PHASE_NUM_HASH 2
 #define SPG_BATCH_PHASE_NUM_DENSE 3
-#define SPG_BATCH_NUM_PHASES 4
+#define SPG_BATCH_PHASE_NUM_ESC 4  /* expand-sort-compress rows */
+#define SPG_BATCH_NUM_PHASES 5
 
 /* Device time of each phase of the last eager spg_batch_symbolic /
  * spg_batch_numeric call (graph replays are not timed) into

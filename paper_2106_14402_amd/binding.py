@@ -416,7 +416,7 @@ def spg_batch_stats(plan):
     return int(f.value), int(r.value)
 
 
-BATCH_PHASES = ["sym_hash", "sym_dense", "num_hash", "num_dense"]
+BATCH_PHASES = ["sym_hash", "sym_dense", "num_hash", "num_dense", "num_esc"]
 
 
 def spg_batch_timings(plan) -> dict:

@@ -337,11 +337,25 @@ spg_status enqueue_numeric(spg_batch_plan* p, unsigned char* w) {
     }
   }
   {
+    BatchPhaseTimer t(p, SPG_BATCH_PHASE_NUM_ESC);
+    for (int sl = 0; sl < nslots; ++sl) {
+      const int sr = p->slot_sr[sl];
+      for (int c = kEscBinBase; c < kNumBins; ++c) {
+        const int bin = c + kNumBins * sl;
+        if (!p->num_counts[bin]) continue;
+        const int N = 32 << (c - kEscBinBase);
+        SPG_TRY_HIP(launch_esc_num_b(sr, d, row_off, p->nprod, items + no[bin],
+                                     static_cast<int64_t>(p->num_counts[bin]), N, grid_cap(p, esc_threads(N)),
+                                     s));
+      }
+    }
+  }
+  {
     BatchPhaseTimer t(p, SPG_BATCH_PHASE_NUM_DENSE);
     for (int sl = 0; sl < nslots; ++sl) {
       const int sr = p->slot_sr[sl];
       int64_t nd = 0;
-      for (int c = kDenseBinBase; c < kNumBins; ++c) nd += static_cast<int64_t>(p->num_counts[c + kNumBins * sl]);
+      for (int c = kDenseBinBase; c < kEscBinBase; ++c) nd += static_cast<int64_t>(p->num_counts[c + kNumBins * sl]);
       if (nd > 0) {
         const int nt = p->opt.dense_threads;
         SPG_TRY_HIP(launch_dense_num_b(sr, d, row_off, p->nprod, items + no[kDenseBinBase + kNumBins * sl], nd,
@@ -374,8 +388,10 @@ spg_status spg_batch_plan_create(int nprod, const spg_matrix* A, const spg_matri
   if (p->opt.dense_threads <= 0) p->opt.dense_threads = 512;
   if (p->opt.sym_panel_log2 <= 0) p->opt.sym_panel_log2 = 20;
   if (p->opt.lds_budget <= 0) p->opt.lds_budget = 65536;
+  if (p->opt.esc_max_flops == 0) p->opt.esc_max_flops = kEscMaxFlops;
+  if (p->opt.esc_ratio_x16 <= 0) p->opt.esc_ratio_x16 = 20;
   if (p->opt.hash_max_flops > 16384 || p->opt.hash_max_flops < 32 || p->opt.hash_max_nnz < 32 ||
-      p->opt.hash_max_nnz > 4096 ||
+      p->opt.hash_max_nnz > 4096 || p->opt.esc_max_flops > kEscMaxFlops ||
       p->opt.dense_threads % kWave || p->opt.dense_threads > 1024 || p->opt.sym_panel_log2 < 7 ||
       p->opt.sym_panel_log2 > 20) {
     delete p;
@@ -384,8 +400,9 @@ spg_status spg_batch_plan_create(int nprod, const spg_matrix* A, const spg_matri
   p->bp.hash_max_flops = p->opt.hash_max_flops;
   p->bp.hash_max_nnz = p->opt.hash_max_nnz;
   p->bp.split_heavy = 0;
-  p->bp.esc_max_flops = 0;  // no expand-sort-compress classes in the batched kernels
-  p->bp.esc_ratio_x16 = 0;
+  // expand-sort-compress classes: set once the batch's semirings are known
+  p->bp.esc_max_flops = 0;
+  p->bp.esc_ratio_x16 = p->opt.esc_ratio_x16;
   p->desc.resize(nprod);
   p->slot_of.resize(nprod);
   p->row_off.assign(nprod + 1, 0);
@@ -478,6 +495,13 @@ spg_status spg_batch_plan_create(int nprod, const spg_matrix* A, const spg_matri
     p->pool_off[b + 1] = p->pool_off[b] + d.op.m + 1;
     p->psym_off[b + 1] = p->psym_off[b] + (d.sym_P > 1 ? static_cast<int64_t>(d.op.n) * (d.sym_P + 1) : 0);
     p->pnum_off[b + 1] = p->pnum_off[b] + (d.num_P > 1 ? static_cast<int64_t>(d.op.n) * (d.num_P + 1) : 0);
+  }
+  // rows of low compression ratio (as in the single-product plan) up to the
+  // largest class every semiring of the batch holds in LDS
+  if (p->opt.esc_max_flops > 0) {
+    int64_t lim = p->opt.esc_max_flops;
+    for (int sr : p->slot_sr) lim = std::min<int64_t>(lim, esc_class_limit(sr));
+    p->bp.esc_max_flops = lim;
   }
   p->mtot = p->row_off[nprod];
   p->ntot = p->brow_off[nprod];

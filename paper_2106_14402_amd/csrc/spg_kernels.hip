@@ -1600,10 +1600,7 @@ __device__ void bucket_sort(int32_t* keys, S* vals, int n, int* cnt, int* red) {
 // ---------------------------------------------------------------------------
 constexpr int kEscUnroll = 4;      // products per thread per batch of loads
 
-// Threads of a class of N products: N / 4 (at most 1024), so each thread
-// holds R = N / threads of them, 4 or 8.
-inline int esc_threads(int N) { return std::max(64, std::min(1024, N / 4)); }
-inline int esc_per_thread(int N) { return std::max(4, N / esc_threads(N)); }
+
 
 template <class SR>
 __host__ __device__ inline size_t esc_lds_bytes(int N, int nt) {
@@ -1613,131 +1610,153 @@ __host__ __device__ inline size_t esc_lds_bytes(int N, int nt) {
 // R: products per thread (4 or 8); with 4 the kernel keeps its registers
 // within what two 1024-thread workgroups per compute unit allow (4-byte
 // values); the 8192-product class takes most of the LDS anyway.
+// One row of at most N products into C's entries [out, out_end).
 template <class SR, int R>
-__global__ __launch_bounds__(1024, R > 4 ? 4 : (sizeof(typename SR::S) > 4 ? 6 : 8)) void k_esc_num(Operands op, const int32_t* __restrict__ rows, int64_t nrows,
-                                                  int N, const int64_t* __restrict__ c_ptr,
-                                                  int32_t* __restrict__ c_idx,
-                                                  typename SR::Out* __restrict__ c_val) {
+__device__ void esc_num_row(const Operands& op, int32_t row, int N, int64_t out, int64_t out_end,
+                            int32_t* __restrict__ c_idx, typename SR::Out* __restrict__ c_val,
+                            unsigned char* smem) {
   using S = typename SR::S;
   using In = typename SR::In;
-  extern __shared__ __align__(16) unsigned char smem[];
   const int nt = blockDim.x, tid = threadIdx.x;
   auto q = RowQueue<In>::carve(smem, nt);
   int32_t* keys = reinterpret_cast<int32_t*>(smem + RowQueue<In>::bytes(nt));
   S* vals = reinterpret_cast<S*>(keys + N);
+  const int64_t a_lo = op.a_ptr[row], a_hi = op.a_ptr[row + 1];
+  // 1. expand
+  int base = 0;
+  for (int64_t r0 = a_lo; r0 < a_hi; r0 += nt) {
+    int64_t lo = 0;
+    int32_t len = 0;
+    In a = In(1);
+    if (r0 + tid < a_hi) {
+      const int32_t kk = op.a_idx[r0 + tid];
+      a = load_val<SR>(op.a_val, r0 + tid);
+      lo = op.b_ptr[kk];
+      len = static_cast<int32_t>(op.b_ptr[kk + 1] - lo);
+    }
+    int E;
+    const int off = block_exclusive_scan(len, q.ctr + 2, &E);
+    q.lo[tid] = lo;
+    q.a[tid] = a;
+    q.pfx[tid] = off;  // threads past the row's entries have len 0
+    if (tid == 0) q.pfx[nt] = E;
+    __syncthreads();
+    E = min(E, N - base);  // the class bound holds the row's products; never write past it
+    for (int j0 = 0; j0 < E; j0 += kEscUnroll * nt) {
+      int es[kEscUnroll];
+#pragma unroll
+      for (int u = 0; u < kEscUnroll; ++u) {
+        const int j = j0 + u * nt + tid;
+        int e_lo = -1;
+        if (j < E) {
+          e_lo = 0;
+          int e_hi = nt;
+          while (e_hi - e_lo > 1) {
+            const int mid = (e_lo + e_hi) >> 1;
+            if (q.pfx[mid] <= j)
+              e_lo = mid;
+            else
+              e_hi = mid;
+          }
+        }
+        es[u] = e_lo;
+      }
+      int32_t cols[kEscUnroll];
+      In bv[kEscUnroll];
+#pragma unroll
+      for (int u = 0; u < kEscUnroll; ++u)
+        if (es[u] >= 0) load_b<SR>(op, q.lo[es[u]] + (j0 + u * nt + tid - q.pfx[es[u]]), cols[u], bv[u]);
+#pragma unroll
+      for (int u = 0; u < kEscUnroll; ++u)
+        if (es[u] >= 0) {
+          const int j = base + j0 + u * nt + tid;
+          keys[j] = cols[u];
+          if constexpr (!SR::kPattern) vals[j] = SR::mul(q.a[es[u]], bv[u]);
+        }
+    }
+    base += E;
+    __syncthreads();  // the queue arrays are rewritten by the next block of entries
+  }
+  __syncthreads();
+  // 2. sort by column (the class bound N is at most R * nt)
+  bucket_sort<S, !SR::kPattern, R>(keys, vals, base, q.pfx, q.ctr + 2);
+  // 3. compress: each thread a contiguous run of positions; the first
+  //    entry of every column keeps its place in the output, the others are
+  //    combined into it (few: the rows here have almost no repeats)
+  const int ch = (base + nt - 1) / nt;
+  const int e0 = min(base, tid * ch), e1 = min(base, e0 + ch);
+  int32_t kr[R];
+  S vr[R];
+  bool head[R];
+  int cnt = 0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int e = e0 + r;
+    head[r] = false;
+    if (e < e1) {
+      kr[r] = keys[e];
+      if constexpr (!SR::kPattern) vr[r] = vals[e];
+      head[r] = e == 0 || keys[e - 1] != kr[r];
+      cnt += head[r] ? 1 : 0;
+    }
+  }
+  int nnz;
+  int pos = block_exclusive_scan(cnt, q.ctr + 2, &nnz);  // ends with a barrier: keys may be rewritten
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    if (e0 + r < e1 && head[r]) {
+      keys[pos] = kr[r];
+      if constexpr (!SR::kPattern) vals[pos] = vr[r];
+      ++pos;
+    }
+  }
+  __syncthreads();
+  if constexpr (!SR::kPattern) {
+    pos = block_exclusive_scan(cnt, q.ctr + 2, &nnz);  // first head position of this thread's run
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (e0 + r < e1) {
+        if (head[r])
+          ++pos;
+        else
+          SR::combine(&vals[pos - 1], vr[r]);  // the column's first entry is at pos - 1
+      }
+    }
+    __syncthreads();
+  }
+  // the symbolic count and this one agree; the clamp keeps writes inside the row
+  const int lim = static_cast<int>(min(static_cast<int64_t>(nnz), out_end - out));
+  for (int e = tid; e < lim; e += nt) {
+    c_idx[out + e] = keys[e];
+    if constexpr (!SR::kPattern) c_val[out + e] = SR::out(vals[e]);
+  }
+  __syncthreads();
+}
+
+template <class SR, int R>
+__global__ __launch_bounds__(1024, R > 4 ? 4 : (sizeof(typename SR::S) > 4 ? 6 : 8)) void k_esc_num(
+    Operands op, const int32_t* __restrict__ rows, int64_t nrows, int N, const int64_t* __restrict__ c_ptr,
+    int32_t* __restrict__ c_idx, typename SR::Out* __restrict__ c_val) {
+  extern __shared__ __align__(16) unsigned char smem[];
   for (int64_t it = blockIdx.x; it < nrows; it += gridDim.x) {
     const int32_t row = uniform(rows[it]);
-    const int64_t a_lo = op.a_ptr[row], a_hi = op.a_ptr[row + 1];
-    const int64_t out = c_ptr[row], out_end = c_ptr[row + 1];
-    // 1. expand
-    int base = 0;
-    for (int64_t r0 = a_lo; r0 < a_hi; r0 += nt) {
-      int64_t lo = 0;
-      int32_t len = 0;
-      In a = In(1);
-      if (r0 + tid < a_hi) {
-        const int32_t kk = op.a_idx[r0 + tid];
-        a = load_val<SR>(op.a_val, r0 + tid);
-        lo = op.b_ptr[kk];
-        len = static_cast<int32_t>(op.b_ptr[kk + 1] - lo);
-      }
-      int E;
-      const int off = block_exclusive_scan(len, q.ctr + 2, &E);
-      q.lo[tid] = lo;
-      q.a[tid] = a;
-      q.pfx[tid] = off;  // threads past the row's entries have len 0
-      if (tid == 0) q.pfx[nt] = E;
-      __syncthreads();
-      E = min(E, N - base);  // the class bound holds the row's products; never write past it
-      for (int j0 = 0; j0 < E; j0 += kEscUnroll * nt) {
-        int es[kEscUnroll];
-#pragma unroll
-        for (int u = 0; u < kEscUnroll; ++u) {
-          const int j = j0 + u * nt + tid;
-          int e_lo = -1;
-          if (j < E) {
-            e_lo = 0;
-            int e_hi = nt;
-            while (e_hi - e_lo > 1) {
-              const int mid = (e_lo + e_hi) >> 1;
-              if (q.pfx[mid] <= j)
-                e_lo = mid;
-              else
-                e_hi = mid;
-            }
-          }
-          es[u] = e_lo;
-        }
-        int32_t cols[kEscUnroll];
-        In bv[kEscUnroll];
-#pragma unroll
-        for (int u = 0; u < kEscUnroll; ++u)
-          if (es[u] >= 0) load_b<SR>(op, q.lo[es[u]] + (j0 + u * nt + tid - q.pfx[es[u]]), cols[u], bv[u]);
-#pragma unroll
-        for (int u = 0; u < kEscUnroll; ++u)
-          if (es[u] >= 0) {
-            const int j = base + j0 + u * nt + tid;
-            keys[j] = cols[u];
-            if constexpr (!SR::kPattern) vals[j] = SR::mul(q.a[es[u]], bv[u]);
-          }
-      }
-      base += E;
-      __syncthreads();  // the queue arrays are rewritten by the next block of entries
-    }
-    __syncthreads();
-    // 2. sort by column (the class bound N is at most R * nt)
-    bucket_sort<S, !SR::kPattern, R>(keys, vals, base, q.pfx, q.ctr + 2);
-    // 3. compress: each thread a contiguous run of positions; the first
-    //    entry of every column keeps its place in the output, the others are
-    //    combined into it (few: the rows here have almost no repeats)
-    const int ch = (base + nt - 1) / nt;
-    const int e0 = min(base, tid * ch), e1 = min(base, e0 + ch);
-    int32_t kr[R];
-    S vr[R];
-    bool head[R];
-    int cnt = 0;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int e = e0 + r;
-      head[r] = false;
-      if (e < e1) {
-        kr[r] = keys[e];
-        if constexpr (!SR::kPattern) vr[r] = vals[e];
-        head[r] = e == 0 || keys[e - 1] != kr[r];
-        cnt += head[r] ? 1 : 0;
-      }
-    }
-    int nnz;
-    int pos = block_exclusive_scan(cnt, q.ctr + 2, &nnz);  // ends with a barrier: keys may be rewritten
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      if (e0 + r < e1 && head[r]) {
-        keys[pos] = kr[r];
-        if constexpr (!SR::kPattern) vals[pos] = vr[r];
-        ++pos;
-      }
-    }
-    __syncthreads();
-    if constexpr (!SR::kPattern) {
-      pos = block_exclusive_scan(cnt, q.ctr + 2, &nnz);  // first head position of this thread's run
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        if (e0 + r < e1) {
-          if (head[r])
-            ++pos;
-          else
-            SR::combine(&vals[pos - 1], vr[r]);  // the column's first entry is at pos - 1
-        }
-      }
-      __syncthreads();
-    }
-    // the symbolic count and this one agree; the clamp keeps writes inside the row
-    const int lim = static_cast<int>(min(static_cast<int64_t>(nnz), out_end - out));
-    for (int e = tid; e < lim; e += nt) {
-      c_idx[out + e] = keys[e];
-      if constexpr (!SR::kPattern) c_val[out + e] = SR::out(vals[e]);
-    }
-    __syncthreads();
+    esc_num_row<SR, R>(op, row, N, c_ptr[row], c_ptr[row + 1], c_idx, c_val, smem);
+  }
+}
+
+// The same over the rows of many products (global row ids in items).
+template <class SR, int R>
+__global__ __launch_bounds__(1024, R > 4 ? 4 : (sizeof(typename SR::S) > 4 ? 6 : 8)) void k_esc_num_b(
+    const BatchDesc* __restrict__ descs, const int64_t* __restrict__ row_off, int nprod,
+    const int32_t* __restrict__ items, int64_t nitems, int N) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const int64_t r = uniform(items[it]);
+    const int b = uniform(batch_product(row_off, nprod, r));
+    const BatchDesc d = descs[b];  // uniform: held in scalar registers
+    const int32_t row = uniform(static_cast<int32_t>(r - row_off[b]));
+    esc_num_row<SR, R>(d.op, row, N, d.c_ptr[row], d.c_ptr[row + 1], d.c_idx,
+                       static_cast<typename SR::Out*>(d.c_val), smem);
   }
 }
 
@@ -2444,6 +2463,24 @@ static hipError_t hash_num_b_t(const BatchDesc* descs, const int64_t* row_off, i
 }
 
 template <class SR>
+static hipError_t esc_num_b_t(const BatchDesc* descs, const int64_t* row_off, int nprod, const int32_t* items,
+                              int64_t nitems, int N, int64_t grid_cap, hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+  const int nt = esc_threads(N);
+  const int R = esc_per_thread(N);
+  const size_t lds = esc_lds_bytes<SR>(N, nt);
+  if (N > R * nt || N > kEscMaxFlops || lds > static_cast<size_t>(max_lds_bytes())) return hipErrorInvalidValue;
+  const dim3 grid(grid_for(nitems, grid_cap));
+  if (R == 4)
+    hipLaunchKernelGGL((k_esc_num_b<SR, 4>), grid, dim3(nt), lds, s, descs, row_off, nprod, items, nitems, N);
+  else if (R == 8)
+    hipLaunchKernelGGL((k_esc_num_b<SR, 8>), grid, dim3(nt), lds, s, descs, row_off, nprod, items, nitems, N);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+template <class SR>
 static hipError_t dense_num_b_t(const BatchDesc* descs, const int64_t* row_off, int nprod,
                                 const int32_t* items, int64_t nitems, int wlog2_max, int nt,
                                 int short_seg, int64_t grid_cap, hipStream_t s) {
@@ -2562,6 +2599,10 @@ hipError_t launch_rank_num(int sr, bool fixed, const Operands& op, const int32_t
                wlog2, P, nt, short_seg, keep_store, keep_slot, keep_nwords, c_ptr, c_idx, c_val, s)
 }
 
+hipError_t launch_esc_num_b(int sr, const BatchDesc* descs, const int64_t* row_off, int nprod, const int32_t* items,
+                            int64_t nitems, int N, int64_t grid_cap, hipStream_t s) {
+  SPG_DISPATCH(sr, esc_num_b_t, descs, row_off, nprod, items, nitems, N, grid_cap, s)
+}
 hipError_t launch_hash_num_b(int sr, const BatchDesc* descs, const int64_t* row_off, int nprod,
                              const int32_t* items, int64_t nitems, int T, int nt, int short_seg,
                              int64_t grid_cap, hipStream_t s) {

@@ -208,6 +208,10 @@ hipError_t launch_dense_num_sub(int sr, const Operands& op, const int32_t* rows,
 // Expand-sort-compress rows of one class (N = 32 << class products at most):
 // every product at its own LDS position, a bitonic sort by column, equal
 // columns combined.  sr as for launch_hash_num.
+// Threads of an expand-sort-compress class of N products: N / 4 (at most
+// 1024), so each thread holds R = N / threads of them, 4 or 8.
+inline int esc_threads(int N) { return N / 4 < 64 ? 64 : (N / 4 > 1024 ? 1024 : N / 4); }
+inline int esc_per_thread(int N) { return N / esc_threads(N) > 4 ? N / esc_threads(N) : 4; }
 // The largest class (products per row) the expand-sort-compress kernel holds
 // in LDS for semiring code sr.
 int esc_class_limit(int sr);
@@ -242,6 +246,9 @@ hipError_t launch_hash_sym_b(const BatchDesc* descs, const int64_t* row_off, int
 hipError_t launch_dense_sym_b(const BatchDesc* descs, const int64_t* row_off, int nprod,
                               const int32_t* items, int64_t nitems, int wlog2_max, int nt,
                               int short_seg, int64_t grid_cap, hipStream_t s);
+// Expand-sort-compress over the batch's rows of one class of N products.
+hipError_t launch_esc_num_b(int sr, const BatchDesc* descs, const int64_t* row_off, int nprod, const int32_t* items,
+                            int64_t nitems, int N, int64_t grid_cap, hipStream_t s);
 hipError_t launch_hash_num_b(int sr, const BatchDesc* descs, const int64_t* row_off, int nprod,
                              const int32_t* items, int64_t nitems, int T, int nt, int short_seg,
                              int64_t grid_cap, hipStream_t s);

@@ -78,6 +78,26 @@ def test_forced_dense_and_panels_in_batch():
     bp.close()
 
 
+def test_batched_esc_rows_on_and_off():
+    """Rows of low compression ratio take the batched expand-sort-compress
+    classes (up to 8192 products); with them off the same rows take the
+    hash and dense kernels: both match the oracle, and the exact semirings
+    agree entry for entry."""
+    from paper_2106_14402_amd import binding
+    items = _batch(16, n_lo=2000, n_hi=12000, d_lo=20, d_hi=60)
+    on = _run_batch(items)
+    off = _run_batch(items, options=binding.make_options(esc_max_flops=-1))
+    t_items = [(b, it) for b, it in enumerate(items)]
+    for b, it in t_items:
+        got = _host(on.result(b))
+        assert_parity(it.A, it.A, it.semiring, got)
+        if it.semiring == "min_plus_i32":
+            for x, y in zip(got, _host(off.result(b))):
+                assert np.array_equal(x, y)
+    on.close()
+    off.close()
+
+
 def test_graph_replay_matches_eager():
     import torch
     items = _batch(20)
@@ -115,7 +135,7 @@ def test_batch_phase_timings_and_capture():
     o = binding.make_options(hash_max_flops=64, hash_max_nnz=64, timing=1)
     bp = _run_batch(items, options=o)
     t = bp.timings()
-    assert set(t) == {"sym_hash", "sym_dense", "num_hash", "num_dense"}
+    assert set(t) == {"sym_hash", "sym_dense", "num_hash", "num_dense", "num_esc"}
     assert all(v >= 0 for v in t.values()) and t["num_dense"] > 0 and t["sym_dense"] > 0
     eager_idx = bp.c_idx.clone()
     bp.capture()
