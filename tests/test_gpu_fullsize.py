@@ -153,6 +153,7 @@ def test_rmat20_bool_and_min_plus(rmat20):
     _check_sorted_in_range(C, A.ncols)
     full_b = _check_every_row(C, Hpat, "or_and_bool", A.nrows)
     print(f"[fullsize] (OR,AND) every slice against the oracle's digests: {full_b}", flush=True)
+    assert full_b, "the stored digests of the (OR,AND) square are missing"
     p.close()
     del C, p
     torch.cuda.empty_cache()
@@ -173,6 +174,7 @@ def test_rmat20_bool_and_min_plus(rmat20):
     _check_sorted_in_range(C, A.ncols)
     full_m = _check_every_row(C, A, "min_plus_i32", A.nrows)
     print(f"[fullsize] (min,+) every slice against the oracle's digests: {full_m}", flush=True)
+    assert full_m, "the stored digests of the (min,+) square are missing"
     p.close()
     del C, p
     torch.cuda.empty_cache()
