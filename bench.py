@@ -82,10 +82,13 @@ def kernel_sources_digest():
     return h.hexdigest()
 
 
-def measured_traffic(kernel, workload):
-    """HBM bytes per launch of ``kernel`` from the committed rocprofv3 counter
-    summary (request counts by size, see run_counters), or None when there is
-    no summary for it or the kernel sources changed since it was taken."""
+def measured_traffic(kernel, workload, launches=1):
+    """HBM bytes of one phase of ``kernel`` from the committed rocprofv3
+    counter summary (request counts by size, see run_counters): its mean
+    bytes per dispatch times the phase's launches (one per accumulator class;
+    a name with several semirings, ``k<a+b>``, sums one launch of each), or
+    None when there is no summary for it or the kernel sources changed since
+    it was taken."""
     path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.json")
     try:
         with open(path) as f:
@@ -95,10 +98,15 @@ def measured_traffic(kernel, workload):
     if rec.get("sources_sha256") != kernel_sources_digest():
         return None
     ks = rec.get("kernels", {})
-    k = ks.get(kernel) or ks.get(kernel.split("<")[0])
-    if not k:
-        return None
-    return int(round(k["read_bytes"] + k["write_bytes"]))
+    base, _, srs = kernel.partition("<")
+    names = [f"{base}<{sr}>" for sr in srs.rstrip(">").split("+")] if srs else [base]
+    total = 0.0
+    for nm in names:
+        k = ks.get(nm) or (ks.get(base) if len(names) == 1 else None)
+        if not k:
+            return None
+        total += k["read_bytes"] + k["write_bytes"]
+    return int(round(total * launches))
 
 
 # Counters of the L2-to-memory requests (TCC_EA0_*), one rocprofv3 pass for
@@ -301,6 +309,13 @@ def base_record(args, value, unit, ms_per_step, dtype, config, higher=True):
             "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config}
 
 
+# Numeric bins of the library's row classes (spg_launch.h): hash classes
+# 1..14 (15 holds the rows whose kept bitmap is expanded), expand-sort-compress
+# classes from 55 on.
+HASH_BINS_END = 15
+ESC_BIN_BASE = 55
+
+
 def row_flops(H):
     """Products per output slice of H*H (oriented CSR arrays), from the host
     copy of the operand (bookkeeping for the algorithmic bytes only)."""
@@ -344,19 +359,28 @@ def dominant_kernel(H, phase, rownnz, p, s_in, s_out, sr):
         "k_hash_sym": (phase.get("sym_hash", 0.0), alg_bytes_dense(
             H, int(deg[~sym_dense_rows].sum()), int((~sym_dense_rows).sum()), 0, s_in, 0, True)),
     }
+    # launches per phase: one per non-empty class of the hash and ESC kernels
+    sym_bins, num_bins = p.bins()
+    launches = {"k_hash_num": sum(1 for c in range(1, HASH_BINS_END) if num_bins[c]),
+                "k_esc_num": sum(1 for c in range(ESC_BIN_BASE, len(num_bins)) if num_bins[c]),
+                "k_hash_sym": sum(1 for c in range(1, HASH_BINS_END + 1) if sym_bins[c])}
     dom = None
     for name, (ms, by) in cands.items():
         if ms > 0 and (dom is None or ms > dom["ms"]):
-            dom = {"kernel": name, "semiring": sr, "ms": ms, "bytes": by}
+            dom = {"kernel": name, "semiring": sr, "ms": ms, "bytes": by, "launches": max(1, launches.get(name, 1))}
     return dom
 
 
 def roofline_record(dom, workload):
     achieved = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9
     name = f"{dom['kernel']}<{dom['semiring']}>"
-    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(name, workload),
-            "kernel": name, "kernel_ms": round(dom["ms"], 3), "alg_bytes": int(dom["bytes"])}
+    rec = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4),
+           "traffic": measured_traffic(name, workload, dom.get("launches", 1)),
+           "kernel": name, "kernel_ms": round(dom["ms"], 3), "alg_bytes": int(dom["bytes"])}
+    if dom.get("launches", 1) > 1:
+        rec["launches"] = dom["launches"]  # one per accumulator class, timed together
+    return rec
 
 
 def run_rmat(args):
