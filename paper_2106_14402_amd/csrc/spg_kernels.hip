@@ -2683,26 +2683,38 @@ int max_lds_bytes() { return 160 * 1024; }
 // ---------------------------------------------------------------------------
 // Prune (Markov-clustering step after expansion): keep value >= thresh.
 // ---------------------------------------------------------------------------
+// One wave per slice, kPruneUnroll loads per lane in flight.
+constexpr int kPruneUnroll = 8;
+
 __global__ void k_prune_count(const int64_t* __restrict__ ptr, const float* __restrict__ val,
                               int64_t nmajor, float thresh, int64_t* __restrict__ cnt) {
+  constexpr int U = kPruneUnroll;
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t waves = static_cast<int64_t>(gridDim.x) * (blockDim.x / kWave);
   for (int64_t s = static_cast<int64_t>(blockIdx.x) * (blockDim.x / kWave) + (threadIdx.x >> 6); s < nmajor;
        s += waves) {
-    int64_t c = 0;
-    for (int64_t p = ptr[s] + lane; p < ptr[s + 1]; p += kWave) c += val[p] >= thresh;
-    c = wave_sum(c);
-    if (lane == 0) cnt[s] = c;
+    const int64_t hi = ptr[s + 1];
+    int c = 0;
+    for (int64_t b = ptr[s] + lane; b < hi; b += U * kWave) {
+      float v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (b + u * kWave < hi) v[u] = val[b + u * kWave];
+#pragma unroll
+      for (int u = 0; u < U; ++u) c += (b + u * kWave < hi && v[u] >= thresh) ? 1 : 0;
+    }
+    const int64_t t = wave_sum(static_cast<int64_t>(c));
+    if (lane == 0) cnt[s] = t;
   }
 }
 
-// Kept entries of a slice in order: four groups of 64 entries are loaded
-// before their keep masks place them, so a wave has four loads in flight.
+// Kept entries of a slice in order: kPruneUnroll groups of 64 entries are
+// loaded before their keep masks place them.
 __global__ void k_prune_apply(const int64_t* __restrict__ ptr, const int32_t* __restrict__ idx,
                               const float* __restrict__ val, int64_t nmajor, float thresh,
                               const int64_t* __restrict__ new_ptr, int32_t* __restrict__ new_idx,
                               float* __restrict__ new_val) {
-  constexpr int U = 4;
+  constexpr int U = kPruneUnroll;
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t waves = static_cast<int64_t>(gridDim.x) * (blockDim.x / kWave);
   for (int64_t s = static_cast<int64_t>(blockIdx.x) * (blockDim.x / kWave) + (threadIdx.x >> 6); s < nmajor;
@@ -2746,17 +2758,30 @@ __global__ void k_inflate(const int64_t* __restrict__ ptr, const float* val, int
   const int64_t waves = static_cast<int64_t>(gridDim.x) * (blockDim.x / kWave);
   for (int64_t s = static_cast<int64_t>(blockIdx.x) * (blockDim.x / kWave) + (threadIdx.x >> 6); s < nmajor;
        s += waves) {
+    constexpr int U = kPruneUnroll;
     const int64_t lo = ptr[s], hi = ptr[s + 1];
     double sum = 0.0;
-    for (int64_t p = lo + lane; p < hi; p += kWave) sum += static_cast<double>(powf(val[p], r));
-    sum = wave_sum(sum);
-    if (sum == 0.0) {  // the slice is left as it is
-      for (int64_t p = lo + lane; p < hi; p += kWave) val_out[p] = val[p];
-      continue;
+    for (int64_t b = lo + lane; b < hi; b += U * kWave) {
+      float v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (b + u * kWave < hi) v[u] = val[b + u * kWave];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (b + u * kWave < hi) sum += static_cast<double>(powf(v[u], r));
     }
-    const double inv = 1.0 / sum;
-    for (int64_t p = lo + lane; p < hi; p += kWave)
-      val_out[p] = static_cast<float>(static_cast<double>(powf(val[p], r)) * inv);
+    sum = wave_sum(sum);
+    const double inv = sum == 0.0 ? 1.0 : 1.0 / sum;
+    for (int64_t b = lo + lane; b < hi; b += U * kWave) {
+      float v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (b + u * kWave < hi) v[u] = val[b + u * kWave];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (b + u * kWave < hi)  // a slice whose powers sum to 0 is left as it is
+          val_out[b + u * kWave] = sum == 0.0 ? v[u] : static_cast<float>(static_cast<double>(powf(v[u], r)) * inv);
+    }
   }
 }
 
