@@ -798,7 +798,9 @@ def run_merge(args):
     torch.cuda.synchronize()
     P = S.stack(parts)
     in_nnz = int(P.nnz)
-    p = S.SumPlan(P, k, "min_plus_i32")
+    from paper_2106_14402_amd import binding as B
+    extra = {kk: int(v) for kk, v in (o.split("=") for o in args.opt)}
+    p = S.SumPlan(P, k, "min_plus_i32", B.make_options(timing=1, **extra))
     nnz = p.symbolic()
     c_idx = torch.empty(nnz, dtype=torch.int32, device="cuda")
     c_val = torch.empty(nnz, dtype=torch.int32, device="cuda")
@@ -815,6 +817,7 @@ def run_merge(args):
     out["roofline"] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "whole merge step",
                        "alg_bytes": alg}
+    out["phase_ms"] = {kk: round(v, 3) for kk, v in p.timings().items() if v > 0}
     if args.cpu_seconds > 0:
         import oracle
         nthreads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()

@@ -62,6 +62,8 @@ static int64_t prep_blocks() {
 // range, a descending pair of adjacent ids (the slice is not sorted), an equal
 // pair of adjacent ids (a duplicate, or a possible one in an unsorted slice).
 // One wave per slice; never reads outside [0, nnz).
+constexpr int kValidateUnroll = 8;
+
 __global__ void k_validate(const int64_t* __restrict__ ptr, const int32_t* __restrict__ idx,
                            int64_t nmajor, int64_t nnz, int32_t nminor, int* err) {
   const int lane = threadIdx.x & (kWave - 1);
@@ -77,13 +79,29 @@ __global__ void k_validate(const int64_t* __restrict__ ptr, const int32_t* __res
     if (lo < 0 || hi > nnz || hi < lo) {
       e |= kCheckOffsets;
     } else {
-      for (int64_t q = lo + lane; q < hi; q += kWave) {
-        const int32_t c = idx[q];
-        if (c < 0 || c >= nminor) e |= kCheckRange;
-        if (q > lo) {
-          const int32_t b = idx[q - 1];
-          if (b > c) e |= kCheckUnsorted;
-          if (b == c) e |= kCheckDuplicate;
+      // kValidateUnroll groups of 64 ids loaded at once; an id's predecessor
+      // comes from the lane below (lane 0: one more load)
+      constexpr int U = kValidateUnroll;
+      for (int64_t b0 = lo; b0 < hi; b0 += U * kWave) {
+        int32_t c[U], pv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int64_t q = b0 + u * kWave + lane;
+          c[u] = q < hi ? idx[q] : 0;
+          pv[u] = (lane == 0 && q > lo && q < hi) ? idx[q - 1] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int64_t q = b0 + u * kWave + lane;
+          const int32_t below = __shfl_up(c[u], 1, kWave);
+          const int32_t b = lane == 0 ? pv[u] : below;
+          if (q < hi) {
+            if (c[u] < 0 || c[u] >= nminor) e |= kCheckRange;
+            if (q > lo) {
+              if (b > c[u]) e |= kCheckUnsorted;
+              if (b == c[u]) e |= kCheckDuplicate;
+            }
+          }
         }
       }
     }

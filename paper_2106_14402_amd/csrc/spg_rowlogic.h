@@ -22,12 +22,26 @@ __host__ __device__ inline void panel_index_fill(int32_t* out, int P, int32_t le
 // the one after its predecessor's panel up to its own.  For sorted ids every
 // slot up to the last id's panel is written exactly once; for any order every
 // value written lies in [0, len).
+// Ids are read in groups of kOpenUnroll per lane, all loads of a group
+// before any use.
+constexpr int kOpenUnroll = 8;
+
 __host__ __device__ inline void panel_index_open(const int32_t* ids, int64_t len, int wlog2, int P, int32_t* out,
                                                  int lane, int nlanes) {
-  for (int64_t q = lane; q < len; q += nlanes) {
-    const int cp = imin_rl(ids[q] >> wlog2, P);
-    const int pp = q == 0 ? -1 : imin_rl(ids[q - 1] >> wlog2, P);
-    for (int p = pp + 1; p <= cp; ++p) out[p] = static_cast<int32_t>(q);
+  for (int64_t b0 = 0; b0 < len; b0 += static_cast<int64_t>(kOpenUnroll) * nlanes) {
+    int32_t cur[kOpenUnroll], prev[kOpenUnroll];
+    for (int u = 0; u < kOpenUnroll; ++u) {
+      const int64_t q = b0 + static_cast<int64_t>(u) * nlanes + lane;
+      cur[u] = q < len ? ids[q] : 0;
+      prev[u] = (q > 0 && q < len) ? ids[q - 1] : 0;
+    }
+    for (int u = 0; u < kOpenUnroll; ++u) {
+      const int64_t q = b0 + static_cast<int64_t>(u) * nlanes + lane;
+      if (q >= len) continue;
+      const int cp = imin_rl(cur[u] >> wlog2, P);
+      const int pp = q == 0 ? -1 : imin_rl(prev[u] >> wlog2, P);
+      for (int p = pp + 1; p <= cp; ++p) out[p] = static_cast<int32_t>(q);
+    }
   }
 }
 
