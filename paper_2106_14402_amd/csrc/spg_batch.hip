@@ -72,10 +72,27 @@ __global__ void kb_validate(const BatchDesc* __restrict__ d, const int64_t* __re
     if (lo < 0 || hi > nnz || hi < lo) {
       e |= kCheckOffsets;
     } else {
-      for (int64_t q = lo + lane; q < hi; q += kWave) {
-        const int32_t c = idx[q];
-        if (c < 0 || c >= nminor) e |= kCheckRange;
-        if (q > lo && idx[q - 1] >= c) e |= idx[q - 1] > c ? kCheckUnsorted : kCheckDuplicate;
+      // eight groups of 64 ids loaded at once; an id's predecessor comes from
+      // the lane below (lane 0: one more load)
+      constexpr int U = 8;
+      for (int64_t b0 = lo; b0 < hi; b0 += U * kWave) {
+        int32_t c[U], pv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int64_t q = b0 + u * kWave + lane;
+          c[u] = q < hi ? idx[q] : 0;
+          pv[u] = (lane == 0 && q > lo && q < hi) ? idx[q - 1] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int64_t q = b0 + u * kWave + lane;
+          const int32_t below = __shfl_up(c[u], 1, kWave);
+          const int32_t b = lane == 0 ? pv[u] : below;
+          if (q < hi) {
+            if (c[u] < 0 || c[u] >= nminor) e |= kCheckRange;
+            if (q > lo && b >= c[u]) e |= b > c[u] ? kCheckUnsorted : kCheckDuplicate;
+          }
+        }
       }
     }
   }
