@@ -492,6 +492,8 @@ __device__ void enumerate_src(const Operands& op, const Src& src, int32_t c0, in
         q.pfx[tid] = off;  // threads past the row's entries have len 0: off == E
         if (tid == 0) q.pfx[nt] = E;
         __syncthreads();
+        // entries past the round's last one have pfx == E: the search stops there
+        const int nents = static_cast<int>(min(static_cast<int64_t>(nt), total - base));
         for (int j0 = 0; j0 < E; j0 += kFU * nt) {
           int es[kFU];  // segment of each product of this batch, or -1
 #pragma unroll
@@ -500,7 +502,7 @@ __device__ void enumerate_src(const Operands& op, const Src& src, int32_t c0, in
             int e_lo = -1;
             if (j < E) {
               e_lo = 0;
-              int e_hi = nt;  // the last entry with pfx <= j has len > 0
+              int e_hi = nents;  // the last entry with pfx <= j has len > 0
               while (e_hi - e_lo > 1) {
                 const int mid = (e_lo + e_hi) >> 1;
                 if (q.pfx[mid] <= j)

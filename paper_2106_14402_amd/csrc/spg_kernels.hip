@@ -1660,6 +1660,8 @@ __device__ void esc_num_row(const Operands& op, int32_t row, int N, int64_t out,
     if (tid == 0) q.pfx[nt] = E;
     __syncthreads();
     E = min(E, N - base);  // the class bound holds the row's products; never write past it
+    // entries past the block's last one have pfx == E: the search stops there
+    const int nents = static_cast<int>(min(static_cast<int64_t>(nt), a_hi - r0));
     for (int j0 = 0; j0 < E; j0 += kEscUnroll * nt) {
       int es[kEscUnroll];
 #pragma unroll
@@ -1668,7 +1670,7 @@ __device__ void esc_num_row(const Operands& op, int32_t row, int N, int64_t out,
         int e_lo = -1;
         if (j < E) {
           e_lo = 0;
-          int e_hi = nt;
+          int e_hi = nents;
           while (e_hi - e_lo > 1) {
             const int mid = (e_lo + e_hi) >> 1;
             if (q.pfx[mid] <= j)
