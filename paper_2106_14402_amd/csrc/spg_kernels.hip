@@ -2249,16 +2249,34 @@ __global__ __launch_bounds__(1024) void k_hash_num_b(const BatchDesc* __restrict
   }
 }
 
-// One rank pass over all k columns of a row (k small enough for the whole
-// bitmap, the row's entries few enough for the value slots): the pattern by
-// a walk over B's column ids, a prefix count per 64-bit word, the values
-// combined at their columns' ranks, then written in column order.  The
-// batched heavy rows of small products take it instead of one fixed panel
-// after another.
+// Rank passes over all k columns of a row (k small enough for the whole
+// bitmap in LDS): the pattern by a walk over B's column ids and a prefix
+// count per 64-bit word, once; then passes over runs of words whose entries
+// fit the value slots (one pass when the row's entries do), each combining
+// the values of its columns at their ranks and writing them in column order.
+// A pass reads only the B panels that overlap its columns (the numeric panel
+// index, when the product has more than one panel).  The batched heavy rows
+// of small products take it instead of one fixed panel after another.
+template <class SR>
+struct RankRangeSink {
+  using S = typename SR::S;
+  const uint64_t* bits;
+  const uint16_t* pre;
+  S* vals;
+  int w_lo, w_hi, r_lo;
+  __device__ void add(int32_t c, S v) {
+    const int w = c >> 6;
+    if (w < w_lo || w >= w_hi) return;  // a column of a boundary panel outside the pass
+    const uint64_t below = bits[w] & ((1ull << (c & 63)) - 1ull);
+    SR::combine(&vals[pre[w] + __popcll(below) - r_lo], v);
+  }
+};
+
 template <class SR>
 __device__ void rank_row_whole(const Operands& op, int64_t a_lo, int64_t a_hi, int slots, int short_seg,
-                               int64_t out, int64_t out_end, int32_t* __restrict__ c_idx,
-                               typename SR::Out* __restrict__ c_val, unsigned char* smem) {
+                               int wlog2, int P, const int32_t* __restrict__ pidx, int64_t out, int64_t out_end,
+                               int32_t* __restrict__ c_idx, typename SR::Out* __restrict__ c_val,
+                               unsigned char* smem) {
   using S = typename SR::S;
   const int nt = blockDim.x;
   const int tid = threadIdx.x;
@@ -2271,8 +2289,6 @@ __device__ void rank_row_whole(const Operands& op, int64_t a_lo, int64_t a_hi, i
   const int nw64 = (nwords + 1) >> 1;
   uint16_t* pre = reinterpret_cast<uint16_t*>(bits + 2 * nw64);
   const uint64_t* bits64 = reinterpret_cast<const uint64_t*>(bits);
-  const int total = static_cast<int>(out_end - out);  // <= slots (the caller checked)
-  for (int t = tid; t < total; t += nt) vals[t] = SR::identity();
   for (int t = tid; t < 2 * nw64; t += nt) bits[t] = 0u;
   __syncthreads();
   BitmapSink bs{bits};
@@ -2289,29 +2305,61 @@ __device__ void rank_row_whole(const Operands& op, int64_t a_lo, int64_t a_hi, i
     run += __popcll(bits64[w]);
   }
   __syncthreads();
-  RankSink<SR> rs{bits64, pre, vals};
-  RowSource<SR> vs{&op, a_lo, a_hi, false, nullptr, 1, 0, 1};
-  enumerate_src<SR, 2>(op, vs, 0, short_seg, q, rs);
-  const int lim = min(total, ptotal);
-  for (int r = tid; r < lim; r += nt) c_val[out + r] = SR::out(vals[r]);
-  __syncthreads();
-  int32_t* ids = reinterpret_cast<int32_t*>(vals);
-  static_assert(sizeof(S) >= sizeof(int32_t), "ids are staged over the value slots");
-  for (int w = tid; w < nw64; w += nt) {
-    uint64_t x = bits64[w];
-    int qi = pre[w];
-    while (x) {
-      ids[qi++] = (w << 6) + __ffsll(static_cast<unsigned long long>(x)) - 1;
-      x &= x - 1;
+  const int total = static_cast<int>(min(static_cast<int64_t>(ptotal), out_end - out));
+  for (int w_lo = 0; w_lo < nw64;) {
+    // the pass: words [w_lo, w_hi), the most whose entries fit the slots
+    // (a word holds at most 64 <= slots); every thread finds the same bound
+    const int r_lo = pre[w_lo];
+    // all the rest, or w_hi in [w_lo + 1, nw64 - 1] (more than one word's
+    // entries remain, so at least two words)
+    int lo = w_lo + 1, hi = nw64 - 1;
+    if (ptotal - r_lo <= slots) {
+      lo = nw64;
+    } else {
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] - r_lo <= slots)
+          lo = mid;
+        else
+          hi = mid - 1;
+      }
     }
+    const int w_hi = lo;
+    const int r_hi = w_hi < nw64 ? static_cast<int>(pre[w_hi]) : ptotal;
+    const int cnt = r_hi - r_lo;
+    for (int t = tid; t < cnt; t += nt) vals[t] = SR::identity();
+    __syncthreads();
+    RankRangeSink<SR> rs{bits64, pre, vals, w_lo, w_hi, r_lo};
+    if (P > 1) {
+      const int p_lo = (w_lo << 6) >> wlog2, p_hi = (((w_hi << 6) - 1) >> wlog2) + 1;
+      RowSource<SR> vs{&op, a_lo, a_hi, true, pidx, P, p_lo, min(p_hi, P)};
+      enumerate_src<SR, 2>(op, vs, 0, short_seg, q, rs);
+    } else {
+      RowSource<SR> vs{&op, a_lo, a_hi, false, nullptr, 1, 0, 1};
+      enumerate_src<SR, 2>(op, vs, 0, short_seg, q, rs);
+    }
+    const int lim = max(0, min(cnt, total - r_lo));
+    for (int r = tid; r < lim; r += nt) c_val[out + r_lo + r] = SR::out(vals[r]);
+    __syncthreads();
+    int32_t* ids = reinterpret_cast<int32_t*>(vals);
+    static_assert(sizeof(S) >= sizeof(int32_t), "ids are staged over the value slots");
+    for (int w = w_lo + tid; w < w_hi; w += nt) {
+      uint64_t x = bits64[w];
+      int qi = pre[w] - r_lo;
+      while (x) {
+        ids[qi++] = (w << 6) + __ffsll(static_cast<unsigned long long>(x)) - 1;
+        x &= x - 1;
+      }
+    }
+    __syncthreads();
+    for (int r = tid; r < lim; r += nt) c_idx[out + r_lo + r] = ids[r];
+    __syncthreads();
+    w_lo = w_hi;
   }
-  __syncthreads();
-  for (int r = tid; r < lim; r += nt) c_idx[out + r] = ids[r];
-  __syncthreads();
 }
 
-// Heavy rows of a batch: one whole-row rank pass when the product has at
-// most kcap columns and the row at most slots entries, else fixed panels.
+// Heavy rows of a batch: rank passes over the whole row's bitmap when the
+// product has at most kcap columns, else fixed panels.
 template <class SR>
 __global__ __launch_bounds__(1024) void k_dense_num_b(const BatchDesc* __restrict__ descs,
                                                       const int64_t* __restrict__ row_off, int nprod,
@@ -2325,9 +2373,9 @@ __global__ __launch_bounds__(1024) void k_dense_num_b(const BatchDesc* __restric
     const int32_t row = uniform(static_cast<int32_t>(r - row_off[b]));
     const int64_t out = uniform64(d.c_ptr[row]), out_end = uniform64(d.c_ptr[row + 1]);
     if constexpr (!SR::kPattern) {
-      if (d.op.k <= kcap && out_end - out <= slots) {
-        rank_row_whole<SR>(d.op, d.op.a_ptr[row], d.op.a_ptr[row + 1], slots, short_seg, out, out_end, d.c_idx,
-                           static_cast<typename SR::Out*>(d.c_val), smem);
+      if (d.op.k <= kcap) {
+        rank_row_whole<SR>(d.op, d.op.a_ptr[row], d.op.a_ptr[row + 1], slots, short_seg, d.num_wlog2, d.num_P,
+                           d.pnum, out, out_end, d.c_idx, static_cast<typename SR::Out*>(d.c_val), smem);
         continue;
       }
     }
