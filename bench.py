@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--batches", type=int, default=4, help="outbatch: output budget = nnz(C) / batches")
     ap.add_argument("--nprod", type=int, default=512, help="batched: number of products")
     ap.add_argument("--requests", type=int, default=2000, help="served: requests per arrival rate")
+    ap.add_argument("--batch-knobs", default="",
+                    help="batched: knob values k=v,... instead of the autotuner's")
     ap.add_argument("--autotune-cache", default=None,
                     help="batched: autotuner cache file (default gpurun_out/autotune.json under the repo)")
     ap.add_argument("--opt", action="append", default=[],
@@ -638,7 +640,13 @@ def run_batched(args):
     log(f"[bench] {len(items)} products generated in {time.time() - t0:.1f}s")
     from paper_2106_14402_amd import autotune as AT
     cache = os.path.join(ROOT, "gpurun_out", "autotune.json") if args.autotune_cache is None else args.autotune_cache
-    tuning = AT.tune_batch(mats, mats, srs, cache, log=log)
+    if args.batch_knobs:
+        # knob values given on the command line (e.g. a profiled run that must
+        # not include the tuner's trials)
+        knobs = {k: int(v) for k, v in (kv.split("=") for kv in args.batch_knobs.split(","))}
+        tuning = {"knobs": knobs, "ms": None, "default_ms": None, "from_cache": False, "given": True}
+    else:
+        tuning = AT.tune_batch(mats, mats, srs, cache, log=log)
     log(f"[bench] autotuned {tuning}")
     bopt = AT.make_options(tuning["knobs"])
     bopt.timing = 1
@@ -687,7 +695,7 @@ def run_batched(args):
     out["one_call_per_product"] = {"full_step_ms": round(ms_s, 3), "numeric_ms": round(ms_sn, 3)}
     out["speedup"] = {"full_step": round(ms_s / ms_b, 3), "numeric": round(ms_sn / ms_br, 3)}
     out["autotune"] = {"knobs": tuning["knobs"], "tuned_ms": tuning["ms"], "default_ms": tuning["default_ms"],
-                       "from_cache": tuning["from_cache"]}
+                       "from_cache": tuning["from_cache"], "given": bool(tuning.get("given"))}
     out["roofline"] = roofline
     out["phase_ms"] = {k: round(v, 3) for k, v in phase_ms.items()}
     bp.close()
