@@ -711,7 +711,7 @@ def batched_dominant(items, bp, phase_ms, knobs):
     hmn = int(knobs.get("hash_max_nnz", 2048))
     hmf = int(knobs.get("hash_max_flops", 8192))
     esc_max = int(knobs.get("esc_max_flops", 8192))  # the batch's semirings all hold the 8192 class
-    esc_ratio = int(knobs.get("esc_ratio_x16", 20))
+    esc_ratio = int(knobs.get("esc_ratio_x16", 20))  # the batched plan's default
     byts = {k: 0 for k in phase_ms}
     for b, it in enumerate(items):
         s_io = 8 if it.semiring == "plus_times_f64" else 4

@@ -190,7 +190,8 @@ typedef struct spg_options {
                               flops / nnz is at most esc_ratio_x16 / 16 are
                               expanded, sorted and compressed in LDS instead
                               of hashed or ranked */
-  int32_t esc_ratio_x16;   /* 16 x that compression ratio (default 20: 1.25) */
+  int32_t esc_ratio_x16;   /* 16 x that compression ratio (default 32: 2;
+                              20: 1.25 in batched plans) */
 } spg_options;
 
 /* Phases reported by spg_plan_timings, in milliseconds. */

@@ -159,7 +159,7 @@ void resolve_options(const spg_options* in, spg_options* o, int sr) {
   if (o->win_threads <= 0) o->win_threads = 256;
   if (o->win_wgs <= 0) o->win_wgs = 8;
   if (o->esc_max_flops == 0) o->esc_max_flops = kEscMaxFlops;
-  if (o->esc_ratio_x16 <= 0) o->esc_ratio_x16 = 20;
+  if (o->esc_ratio_x16 <= 0) o->esc_ratio_x16 = 32;
 }
 
 spg_status check_options(const spg_options& o, int sr) {

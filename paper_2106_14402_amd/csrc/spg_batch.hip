@@ -100,11 +100,13 @@ __global__ void kb_validate(const BatchDesc* __restrict__ d, const int64_t* __re
   if (lane == 0 && e) atomicOr(err, e);
 }
 
-// flops per global row, symbolic bin counts, zero nnz for empty rows; a
-// wave per row, rows strided over a grid of a few workgroups per compute unit.
+// flops and product per global row, symbolic bin counts, zero nnz for empty
+// rows; a wave per row, rows strided over a grid of a few workgroups per
+// compute unit.
 __global__ void kb_flops_bin(const BatchDesc* __restrict__ d, const int64_t* __restrict__ row_off,
                              int nprod, int64_t mtot, BinParams bp, int64_t* __restrict__ flops,
-                             unsigned long long* counts, unsigned long long* total) {
+                             int32_t* __restrict__ prod_of, unsigned long long* counts,
+                             unsigned long long* total) {
   __shared__ unsigned int lc[kNumBins];
   __shared__ unsigned long long ltot;
   const int tid = threadIdx.x;
@@ -125,6 +127,7 @@ __global__ void kb_flops_bin(const BatchDesc* __restrict__ d, const int64_t* __r
     f = wave_sum(f);
     if (lane == 0) {
       flops[r] = f;
+      prod_of[r] = b;  // the row kernels' product lookup
       if (f == 0) d[b].c_ptr[i + 1] = 0;
       atomicAdd(&lc[sym_bin(f, bp)], 1u);
       atomicAdd(&ltot, static_cast<unsigned long long>(f));
@@ -251,7 +254,7 @@ struct spg_batch_plan {
   int64_t mtot, ntot, pool_len;
   int sym_wlog2_max, num_wlog2_max[kMaxSlots];
   int64_t grid_cap_per_thread;  // resident threads of the device
-  size_t off_desc, off_rowoff, off_browoff, off_pooloff, off_slot, off_ctr, off_flops, off_items_sym,
+  size_t off_desc, off_rowoff, off_browoff, off_pooloff, off_slot, off_ctr, off_flops, off_prod, off_items_sym,
       off_items_num, off_scan, off_bases, off_offs, off_psym, off_pnum, ws_bytes;
   int state;
   int64_t flops_total;
@@ -330,6 +333,7 @@ spg_status enqueue_numeric(spg_batch_plan* p, unsigned char* w) {
   auto* row_off = reinterpret_cast<const int64_t*>(w + p->off_rowoff);
   auto* brow_off = reinterpret_cast<const int64_t*>(w + p->off_browoff);
   auto* items = reinterpret_cast<const int32_t*>(w + p->off_items_num);
+  auto* prod_of = reinterpret_cast<const int32_t*>(w + p->off_prod);
   bool any_panels = false;
   for (const auto& x : p->desc) any_panels = any_panels || x.num_P > 1;
   if (any_panels && p->ntot > 0)
@@ -347,7 +351,7 @@ spg_status enqueue_numeric(spg_batch_plan* p, unsigned char* w) {
         const int bin = c + kNumBins * sl;
         if (!p->num_counts[bin]) continue;
         const int nt = hash_threads_num(c, sr);
-        SPG_TRY_HIP(launch_hash_num_b(sr, d, row_off, p->nprod, items + no[bin],
+        SPG_TRY_HIP(launch_hash_num_b(sr, d, row_off, prod_of, p->nprod, items + no[bin],
                                       static_cast<int64_t>(p->num_counts[bin]), hash_table_size(c), nt,
                                       p->opt.short_seg, grid_cap(p, nt), s));
       }
@@ -361,7 +365,7 @@ spg_status enqueue_numeric(spg_batch_plan* p, unsigned char* w) {
         const int bin = c + kNumBins * sl;
         if (!p->num_counts[bin]) continue;
         const int N = 32 << (c - kEscBinBase);
-        SPG_TRY_HIP(launch_esc_num_b(sr, d, row_off, p->nprod, items + no[bin],
+        SPG_TRY_HIP(launch_esc_num_b(sr, d, row_off, prod_of, p->nprod, items + no[bin],
                                      static_cast<int64_t>(p->num_counts[bin]), N, grid_cap(p, esc_threads(N)),
                                      s));
       }
@@ -375,7 +379,7 @@ spg_status enqueue_numeric(spg_batch_plan* p, unsigned char* w) {
       for (int c = kDenseBinBase; c < kEscBinBase; ++c) nd += static_cast<int64_t>(p->num_counts[c + kNumBins * sl]);
       if (nd > 0) {
         const int nt = p->opt.dense_threads;
-        SPG_TRY_HIP(launch_dense_num_b(sr, d, row_off, p->nprod, items + no[kDenseBinBase + kNumBins * sl], nd,
+        SPG_TRY_HIP(launch_dense_num_b(sr, d, row_off, prod_of, p->nprod, items + no[kDenseBinBase + kNumBins * sl], nd,
                                        p->num_wlog2_max[sl], nt, p->opt.short_seg, grid_cap(p, nt), s));
       }
     }
@@ -406,7 +410,7 @@ spg_status spg_batch_plan_create(int nprod, const spg_matrix* A, const spg_matri
   if (p->opt.sym_panel_log2 <= 0) p->opt.sym_panel_log2 = 20;
   if (p->opt.lds_budget <= 0) p->opt.lds_budget = 65536;
   if (p->opt.esc_max_flops == 0) p->opt.esc_max_flops = kEscMaxFlops;
-  if (p->opt.esc_ratio_x16 <= 0) p->opt.esc_ratio_x16 = 20;
+  if (p->opt.esc_ratio_x16 <= 0) p->opt.esc_ratio_x16 = 20;  // measured: 2 is slower in batches
   if (p->opt.hash_max_flops > 16384 || p->opt.hash_max_flops < 32 || p->opt.hash_max_nnz < 32 ||
       p->opt.hash_max_nnz > 4096 || p->opt.esc_max_flops > kEscMaxFlops ||
       p->opt.dense_threads % kWave || p->opt.dense_threads > 1024 || p->opt.sym_panel_log2 < 7 ||
@@ -546,6 +550,7 @@ spg_status spg_batch_plan_create(int nprod, const spg_matrix* A, const spg_matri
   p->off_slot = take(sizeof(int32_t) * std::max(1, nprod));
   p->off_ctr = take(sizeof(uint64_t) * kCtrWords);
   p->off_flops = take(sizeof(int64_t) * p->mtot);
+  p->off_prod = take(sizeof(int32_t) * p->mtot);
   p->off_items_sym = take(sizeof(int32_t) * p->mtot);
   p->off_items_num = take(sizeof(int32_t) * p->mtot);
   p->off_scan = take(sizeof(int64_t) * ((p->pool_len + kScanTile - 1) / kScanTile + 1));
@@ -593,6 +598,7 @@ spg_status spg_batch_symbolic(spg_batch_plan* p, void* ws, int64_t* c_ptr_pool, 
   auto* slot_of = reinterpret_cast<int32_t*>(w + p->off_slot);
   auto* ctr = reinterpret_cast<unsigned long long*>(w + p->off_ctr);
   auto* flops = reinterpret_cast<int64_t*>(w + p->off_flops);
+  auto* prod_of = reinterpret_cast<int32_t*>(w + p->off_prod);
   auto* items_sym = reinterpret_cast<int32_t*>(w + p->off_items_sym);
   auto* items_num = reinterpret_cast<int32_t*>(w + p->off_items_num);
   auto* scan = reinterpret_cast<int64_t*>(w + p->off_scan);
@@ -633,7 +639,7 @@ spg_status spg_batch_symbolic(spg_batch_plan* p, void* ws, int64_t* c_ptr_pool, 
   }
   if (p->mtot > 0)
     hipLaunchKernelGGL(kb_flops_bin, dim3(std::min<int64_t>(blocks(p->mtot, 4), prep_grid(p))), dim3(256), 0, s,
-                       d, row_off, nprod, p->mtot, p->bp, flops, ctr + kCtrSym, ctr + kCtrMisc);
+                       d, row_off, nprod, p->mtot, p->bp, flops, prod_of, ctr + kCtrSym, ctr + kCtrMisc);
   unsigned long long h[kNumBins + 1];
   SPG_TRY_HIP(hipMemcpyAsync(h, ctr + kCtrSym, sizeof(uint64_t) * kNumBins, hipMemcpyDeviceToHost, s));
   SPG_TRY_HIP(hipMemcpyAsync(&h[kNumBins], ctr + kCtrMisc, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
@@ -658,7 +664,7 @@ spg_status spg_batch_symbolic(spg_batch_plan* p, void* ws, int64_t* c_ptr_pool, 
       for (int c = 1; c < kDenseBinBase; ++c) {
         if (!p->sym_counts[c]) continue;
         const int nt = hash_threads(c);
-        SPG_TRY_HIP(launch_hash_sym_b(d, row_off, nprod, items_sym + so[c],
+        SPG_TRY_HIP(launch_hash_sym_b(d, row_off, prod_of, nprod, items_sym + so[c],
                                       static_cast<int64_t>(p->sym_counts[c]), hash_table_size(c), nt,
                                       p->opt.short_seg, grid_cap(p, nt), s));
       }
@@ -668,7 +674,7 @@ spg_status spg_batch_symbolic(spg_batch_plan* p, void* ws, int64_t* c_ptr_pool, 
     if (nd > 0) {
       BatchPhaseTimer t(p, SPG_BATCH_PHASE_SYM_DENSE);
       const int nt = p->opt.dense_threads;
-      SPG_TRY_HIP(launch_dense_sym_b(d, row_off, nprod, items_sym + so[kDenseBinBase], nd, p->sym_wlog2_max,
+      SPG_TRY_HIP(launch_dense_sym_b(d, row_off, prod_of, nprod, items_sym + so[kDenseBinBase], nd, p->sym_wlog2_max,
                                      nt, p->opt.short_seg, grid_cap(p, nt), s));
     }
   }

@@ -695,19 +695,6 @@ __device__ int64_t dense_sym_row(const Operands& op, int32_t row, int wlog2, int
   return total;
 }
 
-// Product of global row r in a batch: the last b with row_off[b] <= r.
-__device__ __forceinline__ int batch_product(const int64_t* __restrict__ row_off, int nprod, int64_t r) {
-  int lo = 0, hi = nprod;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (row_off[mid] <= r)
-      lo = mid;
-    else
-      hi = mid;
-  }
-  return lo;
-}
-
 __global__ __launch_bounds__(1024) void k_hash_sym(Operands op, const int32_t* __restrict__ rows,
                                                    int64_t nrows, int T, int short_seg,
                                                    int64_t* __restrict__ c_ptr) {
@@ -751,13 +738,14 @@ __global__ __launch_bounds__(1024) void k_dense_sym(Operands op, const int32_t* 
 }
 
 __global__ __launch_bounds__(1024) void k_hash_sym_b(const BatchDesc* __restrict__ descs,
-                                                     const int64_t* __restrict__ row_off, int nprod,
+                                                     const int64_t* __restrict__ row_off,
+    const int32_t* __restrict__ prod_of, int nprod,
                                                      const int32_t* __restrict__ items, int64_t nitems,
                                                      int T, int short_seg) {
   extern __shared__ __align__(16) unsigned char smem[];
   for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
     const int64_t r = uniform(items[it]);
-    const int b = uniform(batch_product(row_off, nprod, r));
+    const int b = uniform(prod_of[r]);
     const BatchDesc d = descs[b];  // uniform: held in scalar registers
     const int32_t row = uniform(static_cast<int32_t>(r - row_off[b]));
     const int64_t nz = hash_sym_row<false>(d.op, row, T, short_seg, smem);
@@ -766,13 +754,14 @@ __global__ __launch_bounds__(1024) void k_hash_sym_b(const BatchDesc* __restrict
 }
 
 __global__ __launch_bounds__(1024) void k_dense_sym_b(const BatchDesc* __restrict__ descs,
-                                                      const int64_t* __restrict__ row_off, int nprod,
+                                                      const int64_t* __restrict__ row_off,
+    const int32_t* __restrict__ prod_of, int nprod,
                                                       const int32_t* __restrict__ items, int64_t nitems,
                                                       int short_seg) {
   extern __shared__ __align__(16) unsigned char smem[];
   for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
     const int64_t r = uniform(items[it]);
-    const int b = uniform(batch_product(row_off, nprod, r));
+    const int b = uniform(prod_of[r]);
     const BatchDesc d = descs[b];  // uniform: held in scalar registers
     const int32_t row = uniform(static_cast<int32_t>(r - row_off[b]));
     const int64_t nz = dense_sym_row(d.op, row, d.sym_wlog2, d.sym_P, d.psym, short_seg, smem);
@@ -1254,21 +1243,21 @@ hipError_t launch_sub_scatter(int64_t nslots, int subP, const int32_t* cnt, BinP
   return hipGetLastError();
 }
 
-hipError_t launch_hash_sym_b(const BatchDesc* descs, const int64_t* row_off, int nprod,
+hipError_t launch_hash_sym_b(const BatchDesc* descs, const int64_t* row_off, const int32_t* prod_of, int nprod,
                              const int32_t* items, int64_t nitems, int T, int nt, int short_seg,
                              int64_t grid_cap, hipStream_t s) {
   if (nitems <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_hash_sym_b, dim3(grid_for(nitems, grid_cap)), dim3(nt), hash_sym_lds(T, nt), s,
-                     descs, row_off, nprod, items, nitems, T, short_seg);
+                     descs, row_off, prod_of, nprod, items, nitems, T, short_seg);
   return hipGetLastError();
 }
 
-hipError_t launch_dense_sym_b(const BatchDesc* descs, const int64_t* row_off, int nprod,
+hipError_t launch_dense_sym_b(const BatchDesc* descs, const int64_t* row_off, const int32_t* prod_of, int nprod,
                               const int32_t* items, int64_t nitems, int wlog2_max, int nt,
                               int short_seg, int64_t grid_cap, hipStream_t s) {
   if (nitems <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_dense_sym_b, dim3(grid_for(nitems, grid_cap)), dim3(nt),
-                     dense_sym_lds(wlog2_max, nt), s, descs, row_off, nprod, items, nitems, short_seg);
+                     dense_sym_lds(wlog2_max, nt), s, descs, row_off, prod_of, nprod, items, nitems, short_seg);
   return hipGetLastError();
 }
 
@@ -1767,12 +1756,13 @@ __global__ __launch_bounds__(1024, R > 4 ? 4 : (sizeof(typename SR::S) > 4 ? 6 :
 // The same over the rows of many products (global row ids in items).
 template <class SR, int R>
 __global__ __launch_bounds__(1024, R > 4 ? 4 : (sizeof(typename SR::S) > 4 ? 6 : 8)) void k_esc_num_b(
-    const BatchDesc* __restrict__ descs, const int64_t* __restrict__ row_off, int nprod,
+    const BatchDesc* __restrict__ descs, const int64_t* __restrict__ row_off,
+    const int32_t* __restrict__ prod_of, int nprod,
     const int32_t* __restrict__ items, int64_t nitems, int N) {
   extern __shared__ __align__(16) unsigned char smem[];
   for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
     const int64_t r = uniform(items[it]);
-    const int b = uniform(batch_product(row_off, nprod, r));
+    const int b = uniform(prod_of[r]);
     const BatchDesc d = descs[b];  // uniform: held in scalar registers
     const int32_t row = uniform(static_cast<int32_t>(r - row_off[b]));
     esc_num_row<SR, R>(d.op, row, N, d.c_ptr[row], d.c_ptr[row + 1], d.c_idx,
@@ -2235,13 +2225,14 @@ __global__ __launch_bounds__(1024) void k_dense_num_seg(Operands op, const int32
 
 template <class SR>
 __global__ __launch_bounds__(1024) void k_hash_num_b(const BatchDesc* __restrict__ descs,
-                                                     const int64_t* __restrict__ row_off, int nprod,
+                                                     const int64_t* __restrict__ row_off,
+    const int32_t* __restrict__ prod_of, int nprod,
                                                      const int32_t* __restrict__ items, int64_t nitems,
                                                      int T, int short_seg) {
   extern __shared__ __align__(16) unsigned char smem[];
   for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
     const int64_t r = uniform(items[it]);
-    const int b = uniform(batch_product(row_off, nprod, r));
+    const int b = uniform(prod_of[r]);
     const BatchDesc d = descs[b];  // uniform: held in scalar registers
     const int32_t row = uniform(static_cast<int32_t>(r - row_off[b]));
     hash_num_row<SR>(d.op, row, T, short_seg, d.c_ptr[row], d.c_ptr[row + 1], d.c_idx,
@@ -2362,13 +2353,14 @@ __device__ void rank_row_whole(const Operands& op, int64_t a_lo, int64_t a_hi, i
 // product has at most kcap columns, else fixed panels.
 template <class SR>
 __global__ __launch_bounds__(1024) void k_dense_num_b(const BatchDesc* __restrict__ descs,
-                                                      const int64_t* __restrict__ row_off, int nprod,
+                                                      const int64_t* __restrict__ row_off,
+    const int32_t* __restrict__ prod_of, int nprod,
                                                       const int32_t* __restrict__ items, int64_t nitems,
                                                       int short_seg, int kcap, int slots) {
   extern __shared__ __align__(16) unsigned char smem[];
   for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
     const int64_t r = uniform(items[it]);
-    const int b = uniform(batch_product(row_off, nprod, r));
+    const int b = uniform(prod_of[r]);
     const BatchDesc d = descs[b];  // uniform: held in scalar registers
     const int32_t row = uniform(static_cast<int32_t>(r - row_off[b]));
     const int64_t out = uniform64(d.c_ptr[row]), out_end = uniform64(d.c_ptr[row + 1]);
@@ -2521,17 +2513,17 @@ static hipError_t rank_num_t(bool fixed, const Operands& op, const int32_t* rows
 }
 
 template <class SR>
-static hipError_t hash_num_b_t(const BatchDesc* descs, const int64_t* row_off, int nprod,
+static hipError_t hash_num_b_t(const BatchDesc* descs, const int64_t* row_off, const int32_t* prod_of, int nprod,
                                const int32_t* items, int64_t nitems, int T, int nt, int short_seg,
                                int64_t grid_cap, hipStream_t s) {
   if (nitems <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_hash_num_b<SR>, dim3(grid_for(nitems, grid_cap)), dim3(nt),
-                     hash_num_lds_t<SR>(T, nt), s, descs, row_off, nprod, items, nitems, T, short_seg);
+                     hash_num_lds_t<SR>(T, nt), s, descs, row_off, prod_of, nprod, items, nitems, T, short_seg);
   return hipGetLastError();
 }
 
 template <class SR>
-static hipError_t esc_num_b_t(const BatchDesc* descs, const int64_t* row_off, int nprod, const int32_t* items,
+static hipError_t esc_num_b_t(const BatchDesc* descs, const int64_t* row_off, const int32_t* prod_of, int nprod, const int32_t* items,
                               int64_t nitems, int N, int64_t grid_cap, hipStream_t s) {
   if (nitems <= 0) return hipSuccess;
   const int nt = esc_threads(N);
@@ -2540,16 +2532,16 @@ static hipError_t esc_num_b_t(const BatchDesc* descs, const int64_t* row_off, in
   if (N > R * nt || N > kEscMaxFlops || lds > static_cast<size_t>(max_lds_bytes())) return hipErrorInvalidValue;
   const dim3 grid(grid_for(nitems, grid_cap));
   if (R == 4)
-    hipLaunchKernelGGL((k_esc_num_b<SR, 4>), grid, dim3(nt), lds, s, descs, row_off, nprod, items, nitems, N);
+    hipLaunchKernelGGL((k_esc_num_b<SR, 4>), grid, dim3(nt), lds, s, descs, row_off, prod_of, nprod, items, nitems, N);
   else if (R == 8)
-    hipLaunchKernelGGL((k_esc_num_b<SR, 8>), grid, dim3(nt), lds, s, descs, row_off, nprod, items, nitems, N);
+    hipLaunchKernelGGL((k_esc_num_b<SR, 8>), grid, dim3(nt), lds, s, descs, row_off, prod_of, nprod, items, nitems, N);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
 template <class SR>
-static hipError_t dense_num_b_t(const BatchDesc* descs, const int64_t* row_off, int nprod,
+static hipError_t dense_num_b_t(const BatchDesc* descs, const int64_t* row_off, const int32_t* prod_of, int nprod,
                                 const int32_t* items, int64_t nitems, int wlog2_max, int nt,
                                 int short_seg, int64_t grid_cap, hipStream_t s) {
   if (nitems <= 0) return hipSuccess;
@@ -2568,7 +2560,7 @@ static hipError_t dense_num_b_t(const BatchDesc* descs, const int64_t* row_off, 
       }
     }
   }
-  hipLaunchKernelGGL(k_dense_num_b<SR>, dim3(grid_for(nitems, grid_cap)), dim3(nt), lds, s, descs, row_off, nprod,
+  hipLaunchKernelGGL(k_dense_num_b<SR>, dim3(grid_for(nitems, grid_cap)), dim3(nt), lds, s, descs, row_off, prod_of, nprod,
                      items, nitems, short_seg, kcap, slots);
   return hipGetLastError();
 }
@@ -2667,20 +2659,20 @@ hipError_t launch_rank_num(int sr, bool fixed, const Operands& op, const int32_t
                wlog2, P, nt, short_seg, keep_store, keep_slot, keep_nwords, c_ptr, c_idx, c_val, s)
 }
 
-hipError_t launch_esc_num_b(int sr, const BatchDesc* descs, const int64_t* row_off, int nprod, const int32_t* items,
+hipError_t launch_esc_num_b(int sr, const BatchDesc* descs, const int64_t* row_off, const int32_t* prod_of, int nprod, const int32_t* items,
                             int64_t nitems, int N, int64_t grid_cap, hipStream_t s) {
-  SPG_DISPATCH(sr, esc_num_b_t, descs, row_off, nprod, items, nitems, N, grid_cap, s)
+  SPG_DISPATCH(sr, esc_num_b_t, descs, row_off, prod_of, nprod, items, nitems, N, grid_cap, s)
 }
-hipError_t launch_hash_num_b(int sr, const BatchDesc* descs, const int64_t* row_off, int nprod,
+hipError_t launch_hash_num_b(int sr, const BatchDesc* descs, const int64_t* row_off, const int32_t* prod_of, int nprod,
                              const int32_t* items, int64_t nitems, int T, int nt, int short_seg,
                              int64_t grid_cap, hipStream_t s) {
-  SPG_DISPATCH(sr, hash_num_b_t, descs, row_off, nprod, items, nitems, T, nt, short_seg, grid_cap, s)
+  SPG_DISPATCH(sr, hash_num_b_t, descs, row_off, prod_of, nprod, items, nitems, T, nt, short_seg, grid_cap, s)
 }
 
-hipError_t launch_dense_num_b(int sr, const BatchDesc* descs, const int64_t* row_off, int nprod,
+hipError_t launch_dense_num_b(int sr, const BatchDesc* descs, const int64_t* row_off, const int32_t* prod_of, int nprod,
                               const int32_t* items, int64_t nitems, int wlog2_max, int nt,
                               int short_seg, int64_t grid_cap, hipStream_t s) {
-  SPG_DISPATCH(sr, dense_num_b_t, descs, row_off, nprod, items, nitems, wlog2_max, nt, short_seg,
+  SPG_DISPATCH(sr, dense_num_b_t, descs, row_off, prod_of, nprod, items, nitems, wlog2_max, nt, short_seg,
                grid_cap, s)
 }
 

@@ -240,19 +240,19 @@ hipError_t launch_rank_num(int sr, bool fixed, const Operands& op, const int32_t
                            int32_t* c_idx, void* c_val, hipStream_t s);
 size_t rank_num_lds(int sr, int cw, int slots, int max_chunks, int wlog2, int nt);
 size_t rank_pass_lds(int sr, int cw, int slots, int max_chunks, int nt);  // the rank passes alone
-hipError_t launch_hash_sym_b(const BatchDesc* descs, const int64_t* row_off, int nprod,
+hipError_t launch_hash_sym_b(const BatchDesc* descs, const int64_t* row_off, const int32_t* prod_of, int nprod,
                              const int32_t* items, int64_t nitems, int T, int nt, int short_seg,
                              int64_t grid_cap, hipStream_t s);
-hipError_t launch_dense_sym_b(const BatchDesc* descs, const int64_t* row_off, int nprod,
+hipError_t launch_dense_sym_b(const BatchDesc* descs, const int64_t* row_off, const int32_t* prod_of, int nprod,
                               const int32_t* items, int64_t nitems, int wlog2_max, int nt,
                               int short_seg, int64_t grid_cap, hipStream_t s);
 // Expand-sort-compress over the batch's rows of one class of N products.
-hipError_t launch_esc_num_b(int sr, const BatchDesc* descs, const int64_t* row_off, int nprod, const int32_t* items,
+hipError_t launch_esc_num_b(int sr, const BatchDesc* descs, const int64_t* row_off, const int32_t* prod_of, int nprod, const int32_t* items,
                             int64_t nitems, int N, int64_t grid_cap, hipStream_t s);
-hipError_t launch_hash_num_b(int sr, const BatchDesc* descs, const int64_t* row_off, int nprod,
+hipError_t launch_hash_num_b(int sr, const BatchDesc* descs, const int64_t* row_off, const int32_t* prod_of, int nprod,
                              const int32_t* items, int64_t nitems, int T, int nt, int short_seg,
                              int64_t grid_cap, hipStream_t s);
-hipError_t launch_dense_num_b(int sr, const BatchDesc* descs, const int64_t* row_off, int nprod,
+hipError_t launch_dense_num_b(int sr, const BatchDesc* descs, const int64_t* row_off, const int32_t* prod_of, int nprod,
                               const int32_t* items, int64_t nitems, int wlog2_max, int nt,
                               int short_seg, int64_t grid_cap, hipStream_t s);
 // Segment lists of (row, panel) pieces.
