@@ -31,15 +31,16 @@ from . import binding as B_
 
 # Library defaults of the batched plan, and the candidates tried per knob.
 BATCH_DEFAULTS: Dict[str, int] = {"hash_max_flops": 8192, "hash_max_nnz": 2048, "short_seg": 16,
-                                  "dense_threads": 512, "lds_budget": 65536}
+                                  "dense_threads": 512, "lds_budget": 65536, "esc_ratio_x16": 20}
 CANDIDATES: Dict[str, List[int]] = {
     "hash_max_nnz": [512, 1024, 2048, 4096],
     "hash_max_flops": [2048, 4096, 8192, 16384],
     "short_seg": [8, 16, 32, 64],
     "dense_threads": [256, 512, 1024],
     "lds_budget": [32768, 65536, 131072],
+    "esc_ratio_x16": [16, 20, 32],
 }
-ORDER = ["hash_max_nnz", "hash_max_flops", "short_seg", "dense_threads", "lds_budget"]
+ORDER = ["hash_max_nnz", "hash_max_flops", "short_seg", "dense_threads", "lds_budget", "esc_ratio_x16"]
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "spg_autotune.json")
 
