@@ -587,7 +587,8 @@ def run_mcl(args):
     A = spgen.config_mcl()
     log(f"[bench] MCL matrix n={A.ncols} nnz={A.nnz} in {time.time() - t0:.1f}s")
     dA = S.to_device(A)
-    p = S.Product(dA, dA, "plus_times_f32", B.make_options(timing=1))
+    extra = {k: int(v) for k, v in (o.split("=") for o in args.opt)}
+    p = S.Product(dA, dA, "plus_times_f32", B.make_options(timing=1, **extra))
     nnz = p.symbolic()
     flops = p.stats()[0]
     c_idx = torch.empty(nnz, dtype=torch.int32, device="cuda")
