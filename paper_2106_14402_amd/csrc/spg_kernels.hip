@@ -2820,6 +2820,30 @@ __global__ void k_inflate(const int64_t* __restrict__ ptr, const float* val, int
        s += waves) {
     constexpr int U = kPruneUnroll;
     const int64_t lo = ptr[s], hi = ptr[s + 1];
+    if (hi - lo <= 2 * U * kWave) {
+      // the slice in registers: one load and one power per entry
+      float w[2 * U];
+#pragma unroll
+      for (int u = 0; u < 2 * U; ++u)
+        if (lo + lane + u * kWave < hi) w[u] = val[lo + lane + u * kWave];
+      double t = 0.0;
+#pragma unroll
+      for (int u = 0; u < 2 * U; ++u)
+        if (lo + lane + u * kWave < hi) {
+          w[u] = powf(w[u], r);
+          t += static_cast<double>(w[u]);
+        }
+      t = wave_sum(t);
+      if (t == 0.0) {  // a slice whose powers sum to 0 is left as it is
+        for (int64_t q = lo + lane; q < hi; q += kWave) val_out[q] = val[q];
+        continue;
+      }
+      const double inv = 1.0 / t;
+#pragma unroll
+      for (int u = 0; u < 2 * U; ++u)
+        if (lo + lane + u * kWave < hi) val_out[lo + lane + u * kWave] = static_cast<float>(static_cast<double>(w[u]) * inv);
+      continue;
+    }
     double sum = 0.0;
     for (int64_t b = lo + lane; b < hi; b += U * kWave) {
       float v[U];

@@ -11,11 +11,16 @@ pytestmark = pytest.mark.gpu
 
 @pytest.mark.parametrize("r", [2.0, 1.5])
 @pytest.mark.parametrize("layout", ["csc", "csr"])
-def test_inflation_matches_oracle(r, layout):
+@pytest.mark.parametrize("n,mean_deg", [(5000, 40.0), (20000, 150.0)])
+def test_inflation_matches_oracle(r, layout, n, mean_deg):
+    """Slices of a few dozen entries (held in registers) and of several
+    thousand (two passes over the slice)."""
     import torch
 
     from paper_2106_14402_amd import spgemm as S
-    M = spgen.mcl_matrix(5000, 40.0, 1.0, np.random.default_rng(11))
+    M = spgen.mcl_matrix(n, mean_deg, 1.0, np.random.default_rng(11))
+    if mean_deg > 100:
+        assert np.diff(M.ptr).max() > 1024
     if layout == "csr":  # the same arrays read as the transpose's rows
         M = spgen.SparseMatrix(M.ncols, M.nrows, "csr", M.ptr, M.idx, M.val)
     d = S.to_device(M)
