@@ -30,6 +30,10 @@ from . import binding as B_
 from .spgemm import DeviceMatrix, Product
 
 SPG_OK, SPG_E_INVALID, SPG_E_NOMEM, SPG_E_DEVICE = 0, 1, 5, 7
+# Statuses of the server itself (not the library's): a request withdrawn by
+# cancel() before a worker took it, and one whose deadline passed while it
+# waited.
+CANCELLED, EXPIRED = -1, -2
 
 
 @dataclasses.dataclass
@@ -141,6 +145,7 @@ class FrontierServer:
         self.options.b_checked = 1
         self._cv = threading.Condition()
         self._pending = collections.deque()   # (arrival, rid, Ft, bound)
+        self._deadline = {}                   # rid -> time after which it is not started
         self._in_flight = 0
         self._results: List[Result] = []
         self._stop = False
@@ -159,6 +164,7 @@ class FrontierServer:
         product."""
         with self._cv:
             while True:
+                self._expire_locked(time.perf_counter())
                 if self._pending:
                     batch, rows, ents, need = [], 0, 0, 0
                     while self._pending and len(batch) < self.max_reqs:
@@ -169,6 +175,7 @@ class FrontierServer:
                         if self._in_flight + need + bound + ws > self.budget:
                             break
                         self._pending.popleft()
+                        self._deadline.pop(rid, None)  # taken: it runs to completion
                         batch.append((arr, rid, Ft, bound))
                         rows += Ft.nrows
                         ents += Ft.nnz
@@ -181,13 +188,46 @@ class FrontierServer:
                     return None, 0
                 self._cv.wait(timeout=0.05)
 
+    def _expire_locked(self, now: float) -> None:
+        """Drop the waiting requests whose deadline has passed (caller holds
+        the lock); each gets an EXPIRED result."""
+        if not self._deadline:
+            return
+        keep = collections.deque()
+        for item in self._pending:
+            arr, rid, _, _ = item
+            dl = self._deadline.get(rid)
+            if dl is not None and now > dl:
+                self._results.append(Result(rid, EXPIRED, arr, now, now))
+                del self._deadline[rid]
+            else:
+                keep.append(item)
+        self._pending = keep
+
+    def cancel(self, rid: int) -> bool:
+        """Withdraw a request that no worker has taken yet; it completes with
+        status CANCELLED.  False if it is not waiting (already taken,
+        finished or unknown): a product under way is not interrupted."""
+        with self._cv:
+            for item in self._pending:
+                if item[1] == rid:
+                    self._pending.remove(item)
+                    self._deadline.pop(rid, None)
+                    now = time.perf_counter()
+                    self._results.append(Result(rid, CANCELLED, item[0], now, now))
+                    self._cv.notify_all()
+                    return True
+        return False
+
     def _release(self, need):
         with self._cv:
             self._in_flight -= need
             self._cv.notify_all()
 
-    def submit(self, rid: int, Ft, arrival: float) -> Optional[Result]:
-        """Queue a request; returns a Result right away when it is rejected."""
+    def submit(self, rid: int, Ft, arrival: float, deadline: Optional[float] = None) -> Optional[Result]:
+        """Queue a request; returns a Result right away when it is rejected.
+        deadline: a time.perf_counter() value after which the request is not
+        started any more (it then completes with status EXPIRED)."""
         if not check_frontier(self.g, Ft):
             return Result(rid, SPG_E_INVALID, arrival, arrival, time.perf_counter())
         bound = request_bound_bytes(self.g, Ft)
@@ -195,6 +235,8 @@ class FrontierServer:
             return Result(rid, SPG_E_NOMEM, arrival, arrival, time.perf_counter())
         with self._cv:
             self._pending.append((arrival, rid, Ft, bound))
+            if deadline is not None:
+                self._deadline[rid] = deadline
             self._cv.notify_all()
         return None
 
@@ -262,9 +304,10 @@ class FrontierServer:
             with self._cv:
                 self._results.extend(res)
 
-    def serve(self, requests, rate_scale: float = 1.0) -> List[Result]:
+    def serve(self, requests, rate_scale: float = 1.0, timeout_s: Optional[float] = None) -> List[Result]:
         """Replay ``requests`` (each with .rid, .arrival seconds, .Ft) in real
-        time and return every result (completed or rejected)."""
+        time and return every result (completed, rejected or, with
+        timeout_s, expired after waiting that long)."""
         self._results = []
         self._stop = False
         self._feeding = True
@@ -278,7 +321,7 @@ class FrontierServer:
             delay = target - time.perf_counter()
             if delay > 0:
                 time.sleep(delay)
-            rej = self.submit(r.rid, r.Ft, target)
+            rej = self.submit(r.rid, r.Ft, target, None if timeout_s is None else target + timeout_s)
             if rej is not None:
                 rejected.append(rej)
         with self._cv:

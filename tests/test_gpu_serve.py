@@ -87,3 +87,25 @@ def test_tight_budget_queues_and_rejects():
             assert r.status == SV.SPG_E_NOMEM
         else:
             _check(r, A, q.Ft, SV.expand_alone(g, q.Ft))
+
+
+def test_deadlines_under_overload():
+    """Requests offered far above the service rate with a short wait limit:
+    every request has exactly one result, each either completed (and equal
+    to its product alone) or expired while waiting; with no limit all
+    complete."""
+    from paper_2106_14402_amd import serve as SV
+    A = _graph()
+    g = SV.ResidentGraph(A)
+    reqs = spgen.request_stream(A.nrows, 120, rate=1e6, rng=np.random.default_rng(8), k_max=64)
+    srv = SV.FrontierServer(g, workers=1, max_batch_requests=4)
+    results = srv.serve(reqs, timeout_s=0.002)
+    assert sorted(r.rid for r in results) == sorted(q.rid for q in reqs)
+    by = {r.rid: r for r in results}
+    done = [q for q in reqs if by[q.rid].status == SV.SPG_OK]
+    assert all(by[q.rid].status in (SV.SPG_OK, SV.EXPIRED) for q in reqs)
+    assert done
+    for q in done[:20]:
+        _check(by[q.rid], A, q.Ft, SV.expand_alone(g, q.Ft))
+    again = SV.FrontierServer(g, workers=1, max_batch_requests=4).serve(reqs)
+    assert all(r.status == SV.SPG_OK for r in again)

@@ -164,3 +164,52 @@ def test_batch_caps():
     srv.max_rows = 1000
     batch, need = srv._take_batch()
     assert len(batch) == 3                  # request cap
+
+
+def test_cancel_withdraws_a_waiting_request():
+    """cancel() removes a request no worker has taken: it completes with
+    status CANCELLED and is never admitted; the others are taken as before."""
+    g, _ = fake_graph()
+    rng = np.random.default_rng(4)
+    reqs = [spgen.frontier(g.n, 3, rng) for _ in range(4)]
+    srv = SV.FrontierServer(g, workers=1)
+    for i, F in enumerate(reqs):
+        assert srv.submit(i, F, 0.0) is None
+    assert srv.cancel(2)
+    assert not srv.cancel(2)      # no longer waiting
+    assert not srv.cancel(99)     # unknown
+    srv._feeding = False
+    taken = []
+    while srv._pending:
+        batch, need = srv._take_batch()
+        taken += [rid for _, rid, _, _ in batch]
+        srv._release(need)
+    assert sorted(taken) == [0, 1, 3]
+    assert [(r.rid, r.status) for r in srv._results] == [(2, SV.CANCELLED)]
+    assert srv._in_flight == 0
+
+
+def test_deadline_expires_waiting_requests_only():
+    """A request whose deadline passes while it waits completes with status
+    EXPIRED; one taken before its deadline is not touched; a request with
+    no deadline waits as long as it must."""
+    import time
+    g, _ = fake_graph()
+    rng = np.random.default_rng(5)
+    reqs = [spgen.frontier(g.n, 3, rng) for _ in range(3)]
+    srv = SV.FrontierServer(g, workers=1, max_batch_requests=1)
+    now = time.perf_counter()
+    assert srv.submit(0, reqs[0], now, deadline=now + 60.0) is None   # taken in time
+    assert srv.submit(1, reqs[1], now, deadline=now - 1.0) is None    # already past
+    assert srv.submit(2, reqs[2], now) is None                        # no deadline
+    srv._feeding = False
+    taken = []
+    while srv._pending:
+        batch, need = srv._take_batch()
+        if batch is None:
+            break
+        taken += [rid for _, rid, _, _ in batch]
+        srv._release(need)
+    assert taken == [0, 2]
+    assert [(r.rid, r.status) for r in srv._results] == [(1, SV.EXPIRED)]
+    assert not srv._deadline
