@@ -48,27 +48,16 @@ def _writes(disp, name, n64, ns):
 
 
 def test_counter_summary_and_calibration(tmp_path, monkeypatch):
-    """Exact request counts of a stream and of 4 KiB gathers give ratio 1 to
-    the known bytes; a library kernel's per-dispatch bytes are the mean over
-    its dispatches; the summary records the sources' digest."""
+    """Exact request counts of the calibration stream give ratio 1 to its
+    known bytes; a library kernel's per-dispatch bytes are the mean over its
+    dispatches; the summary records the sources' digest."""
     rank = "void spg::k_rank_num<spg::PackedB<spg::SrMinPlusI32>, false>(spg::Operands, int)"
     w_rd, w_wr = str(tmp_path / "w_rd"), str(tmp_path / "w_wr")
     _write_pass(w_rd, _reads(1, rank, 1000, 2_000_000) + _reads(2, rank, 3000, 4_000_000))
     _write_pass(w_wr, _writes(1, rank, 500, 2_000_000) + _writes(2, rank, 700, 4_000_000))
-    known = bench.calib_known()
-    cal_rd, cal_wr = [], []
-    n = (1 << 30) // 4
-    cal_rd += _reads(1, "void at::native::neg_kernel(float*)", 4 * n // 128, 1_000_000)
-    cal_wr += _writes(1, "void at::native::neg_kernel(float*)", 4 * n // 64, 1_000_000)
-    for j, wdt in enumerate(bench.CALIB_WIDTHS):
-        rows = bench.calib_rows(wdt)
-        if wdt < 128:
-            continue  # no exact 128-byte model of the short gathers: not written
-        r128 = known[f"calib_gather{wdt}"]["read_bytes"] // 128
-        w64 = known[f"calib_gather{wdt}"]["write_bytes"] // 64
-        cal_rd += _reads(10 + j, "void at::native::vectorized_gather_kernel(float*)", r128, 1_000_000)
-        cal_wr += _writes(10 + j, "void at::native::vectorized_gather_kernel(float*)", w64, 1_000_000)
-        assert rows > 0
+    n = (1 << 30) // 4  # the calibration stream: 1 GiB read, 1 GiB written
+    cal_rd = _reads(1, "void at::native::neg_kernel(float*)", 4 * n // 128, 1_000_000)
+    cal_wr = _writes(1, "void at::native::neg_kernel(float*)", 4 * n // 64, 1_000_000)
     _write_pass(str(tmp_path / "c_rd"), cal_rd)
     _write_pass(str(tmp_path / "c_wr"), cal_wr)
     out = str(tmp_path / "sum.json")
