@@ -1247,7 +1247,7 @@ hipError_t launch_hash_sym_b(const BatchDesc* descs, const int64_t* row_off, con
                              const int32_t* items, int64_t nitems, int T, int nt, int short_seg,
                              int64_t grid_cap, hipStream_t s) {
   if (nitems <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_hash_sym_b, dim3(grid_for(nitems, grid_cap)), dim3(nt), hash_sym_lds(T, nt), s,
+  hipLaunchKernelGGL(k_hash_sym_b, dim3(grid_for(nitems, 0)), dim3(nt), hash_sym_lds(T, nt), s,
                      descs, row_off, prod_of, nprod, items, nitems, T, short_seg);
   return hipGetLastError();
 }
@@ -1256,7 +1256,7 @@ hipError_t launch_dense_sym_b(const BatchDesc* descs, const int64_t* row_off, co
                               const int32_t* items, int64_t nitems, int wlog2_max, int nt,
                               int short_seg, int64_t grid_cap, hipStream_t s) {
   if (nitems <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_dense_sym_b, dim3(grid_for(nitems, grid_cap)), dim3(nt),
+  hipLaunchKernelGGL(k_dense_sym_b, dim3(grid_for(nitems, 0)), dim3(nt),
                      dense_sym_lds(wlog2_max, nt), s, descs, row_off, prod_of, nprod, items, nitems, short_seg);
   return hipGetLastError();
 }
@@ -2517,7 +2517,7 @@ static hipError_t hash_num_b_t(const BatchDesc* descs, const int64_t* row_off, c
                                const int32_t* items, int64_t nitems, int T, int nt, int short_seg,
                                int64_t grid_cap, hipStream_t s) {
   if (nitems <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_hash_num_b<SR>, dim3(grid_for(nitems, grid_cap)), dim3(nt),
+  hipLaunchKernelGGL(k_hash_num_b<SR>, dim3(grid_for(nitems, 0)), dim3(nt),
                      hash_num_lds_t<SR>(T, nt), s, descs, row_off, prod_of, nprod, items, nitems, T, short_seg);
   return hipGetLastError();
 }
@@ -2530,7 +2530,7 @@ static hipError_t esc_num_b_t(const BatchDesc* descs, const int64_t* row_off, co
   const int R = esc_per_thread(N);
   const size_t lds = esc_lds_bytes<SR>(N, nt);
   if (N > R * nt || N > kEscMaxFlops || lds > static_cast<size_t>(max_lds_bytes())) return hipErrorInvalidValue;
-  const dim3 grid(grid_for(nitems, grid_cap));
+  const dim3 grid(grid_for(nitems, 0));
   if (R == 4)
     hipLaunchKernelGGL((k_esc_num_b<SR, 4>), grid, dim3(nt), lds, s, descs, row_off, prod_of, nprod, items, nitems, N);
   else if (R == 8)
@@ -2560,7 +2560,7 @@ static hipError_t dense_num_b_t(const BatchDesc* descs, const int64_t* row_off, 
       }
     }
   }
-  hipLaunchKernelGGL(k_dense_num_b<SR>, dim3(grid_for(nitems, grid_cap)), dim3(nt), lds, s, descs, row_off, prod_of, nprod,
+  hipLaunchKernelGGL(k_dense_num_b<SR>, dim3(grid_for(nitems, 0)), dim3(nt), lds, s, descs, row_off, prod_of, nprod,
                      items, nitems, short_seg, kcap, slots);
   return hipGetLastError();
 }
