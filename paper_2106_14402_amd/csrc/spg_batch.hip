@@ -322,11 +322,6 @@ std::vector<int64_t> offsets_of(const unsigned long long* counts, int n) {
 // unit, each wave striding over rows.
 int64_t prep_grid(const spg_batch_plan* p) { return std::max<int64_t>(1, p->grid_cap_per_thread / 256); }
 
-int64_t grid_cap(const spg_batch_plan* p, int nt) {
-  const int64_t c = p->grid_cap_per_thread / nt;
-  return c < 1 ? 1 : c;
-}
-
 spg_status enqueue_numeric(spg_batch_plan* p, unsigned char* w) {
   hipStream_t s = p->stream;
   auto* d = reinterpret_cast<const BatchDesc*>(w + p->off_desc);
@@ -353,7 +348,7 @@ spg_status enqueue_numeric(spg_batch_plan* p, unsigned char* w) {
         const int nt = hash_threads_num(c, sr);
         SPG_TRY_HIP(launch_hash_num_b(sr, d, row_off, prod_of, p->nprod, items + no[bin],
                                       static_cast<int64_t>(p->num_counts[bin]), hash_table_size(c), nt,
-                                      p->opt.short_seg, grid_cap(p, nt), s));
+                                      p->opt.short_seg, s));
       }
     }
   }
@@ -366,8 +361,7 @@ spg_status enqueue_numeric(spg_batch_plan* p, unsigned char* w) {
         if (!p->num_counts[bin]) continue;
         const int N = 32 << (c - kEscBinBase);
         SPG_TRY_HIP(launch_esc_num_b(sr, d, row_off, prod_of, p->nprod, items + no[bin],
-                                     static_cast<int64_t>(p->num_counts[bin]), N, grid_cap(p, esc_threads(N)),
-                                     s));
+                                     static_cast<int64_t>(p->num_counts[bin]), N, s));
       }
     }
   }
@@ -380,7 +374,7 @@ spg_status enqueue_numeric(spg_batch_plan* p, unsigned char* w) {
       if (nd > 0) {
         const int nt = p->opt.dense_threads;
         SPG_TRY_HIP(launch_dense_num_b(sr, d, row_off, prod_of, p->nprod, items + no[kDenseBinBase + kNumBins * sl], nd,
-                                       p->num_wlog2_max[sl], nt, p->opt.short_seg, grid_cap(p, nt), s));
+                                       p->num_wlog2_max[sl], nt, p->opt.short_seg, s));
       }
     }
   }
@@ -666,7 +660,7 @@ spg_status spg_batch_symbolic(spg_batch_plan* p, void* ws, int64_t* c_ptr_pool, 
         const int nt = hash_threads(c);
         SPG_TRY_HIP(launch_hash_sym_b(d, row_off, prod_of, nprod, items_sym + so[c],
                                       static_cast<int64_t>(p->sym_counts[c]), hash_table_size(c), nt,
-                                      p->opt.short_seg, grid_cap(p, nt), s));
+                                      p->opt.short_seg, s));
       }
     }
     int64_t nd = 0;
@@ -675,7 +669,7 @@ spg_status spg_batch_symbolic(spg_batch_plan* p, void* ws, int64_t* c_ptr_pool, 
       BatchPhaseTimer t(p, SPG_BATCH_PHASE_SYM_DENSE);
       const int nt = p->opt.dense_threads;
       SPG_TRY_HIP(launch_dense_sym_b(d, row_off, prod_of, nprod, items_sym + so[kDenseBinBase], nd, p->sym_wlog2_max,
-                                     nt, p->opt.short_seg, grid_cap(p, nt), s));
+                                     nt, p->opt.short_seg, s));
     }
   }
   // offsets: zero each product's leading slot, scan the whole pool, rebase

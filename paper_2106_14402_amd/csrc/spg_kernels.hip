@@ -1245,7 +1245,7 @@ hipError_t launch_sub_scatter(int64_t nslots, int subP, const int32_t* cnt, BinP
 
 hipError_t launch_hash_sym_b(const BatchDesc* descs, const int64_t* row_off, const int32_t* prod_of, int nprod,
                              const int32_t* items, int64_t nitems, int T, int nt, int short_seg,
-                             int64_t grid_cap, hipStream_t s) {
+                             hipStream_t s) {
   if (nitems <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_hash_sym_b, dim3(grid_for(nitems, 0)), dim3(nt), hash_sym_lds(T, nt), s,
                      descs, row_off, prod_of, nprod, items, nitems, T, short_seg);
@@ -1254,7 +1254,7 @@ hipError_t launch_hash_sym_b(const BatchDesc* descs, const int64_t* row_off, con
 
 hipError_t launch_dense_sym_b(const BatchDesc* descs, const int64_t* row_off, const int32_t* prod_of, int nprod,
                               const int32_t* items, int64_t nitems, int wlog2_max, int nt,
-                              int short_seg, int64_t grid_cap, hipStream_t s) {
+                              int short_seg, hipStream_t s) {
   if (nitems <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_dense_sym_b, dim3(grid_for(nitems, 0)), dim3(nt),
                      dense_sym_lds(wlog2_max, nt), s, descs, row_off, prod_of, nprod, items, nitems, short_seg);
@@ -2515,7 +2515,7 @@ static hipError_t rank_num_t(bool fixed, const Operands& op, const int32_t* rows
 template <class SR>
 static hipError_t hash_num_b_t(const BatchDesc* descs, const int64_t* row_off, const int32_t* prod_of, int nprod,
                                const int32_t* items, int64_t nitems, int T, int nt, int short_seg,
-                               int64_t grid_cap, hipStream_t s) {
+                               hipStream_t s) {
   if (nitems <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_hash_num_b<SR>, dim3(grid_for(nitems, 0)), dim3(nt),
                      hash_num_lds_t<SR>(T, nt), s, descs, row_off, prod_of, nprod, items, nitems, T, short_seg);
@@ -2524,7 +2524,7 @@ static hipError_t hash_num_b_t(const BatchDesc* descs, const int64_t* row_off, c
 
 template <class SR>
 static hipError_t esc_num_b_t(const BatchDesc* descs, const int64_t* row_off, const int32_t* prod_of, int nprod, const int32_t* items,
-                              int64_t nitems, int N, int64_t grid_cap, hipStream_t s) {
+                              int64_t nitems, int N, hipStream_t s) {
   if (nitems <= 0) return hipSuccess;
   const int nt = esc_threads(N);
   const int R = esc_per_thread(N);
@@ -2543,7 +2543,7 @@ static hipError_t esc_num_b_t(const BatchDesc* descs, const int64_t* row_off, co
 template <class SR>
 static hipError_t dense_num_b_t(const BatchDesc* descs, const int64_t* row_off, const int32_t* prod_of, int nprod,
                                 const int32_t* items, int64_t nitems, int wlog2_max, int nt,
-                                int short_seg, int64_t grid_cap, hipStream_t s) {
+                                int short_seg, hipStream_t s) {
   if (nitems <= 0) return hipSuccess;
   // whole-row rank passes in the same LDS: up to 2^16 columns (bitmap and
   // word ranks), the rest of it value slots
@@ -2660,20 +2660,20 @@ hipError_t launch_rank_num(int sr, bool fixed, const Operands& op, const int32_t
 }
 
 hipError_t launch_esc_num_b(int sr, const BatchDesc* descs, const int64_t* row_off, const int32_t* prod_of, int nprod, const int32_t* items,
-                            int64_t nitems, int N, int64_t grid_cap, hipStream_t s) {
-  SPG_DISPATCH(sr, esc_num_b_t, descs, row_off, prod_of, nprod, items, nitems, N, grid_cap, s)
+                            int64_t nitems, int N, hipStream_t s) {
+  SPG_DISPATCH(sr, esc_num_b_t, descs, row_off, prod_of, nprod, items, nitems, N, s)
 }
 hipError_t launch_hash_num_b(int sr, const BatchDesc* descs, const int64_t* row_off, const int32_t* prod_of, int nprod,
                              const int32_t* items, int64_t nitems, int T, int nt, int short_seg,
-                             int64_t grid_cap, hipStream_t s) {
-  SPG_DISPATCH(sr, hash_num_b_t, descs, row_off, prod_of, nprod, items, nitems, T, nt, short_seg, grid_cap, s)
+                             hipStream_t s) {
+  SPG_DISPATCH(sr, hash_num_b_t, descs, row_off, prod_of, nprod, items, nitems, T, nt, short_seg, s)
 }
 
 hipError_t launch_dense_num_b(int sr, const BatchDesc* descs, const int64_t* row_off, const int32_t* prod_of, int nprod,
                               const int32_t* items, int64_t nitems, int wlog2_max, int nt,
-                              int short_seg, int64_t grid_cap, hipStream_t s) {
+                              int short_seg, hipStream_t s) {
   SPG_DISPATCH(sr, dense_num_b_t, descs, row_off, prod_of, nprod, items, nitems, wlog2_max, nt, short_seg,
-               grid_cap, s)
+               s)
 }
 
 hipError_t launch_hash_num_sub(int sr, const Operands& op, const int32_t* rows, const int32_t* items,

@@ -242,19 +242,19 @@ size_t rank_num_lds(int sr, int cw, int slots, int max_chunks, int wlog2, int nt
 size_t rank_pass_lds(int sr, int cw, int slots, int max_chunks, int nt);  // the rank passes alone
 hipError_t launch_hash_sym_b(const BatchDesc* descs, const int64_t* row_off, const int32_t* prod_of, int nprod,
                              const int32_t* items, int64_t nitems, int T, int nt, int short_seg,
-                             int64_t grid_cap, hipStream_t s);
+                             hipStream_t s);
 hipError_t launch_dense_sym_b(const BatchDesc* descs, const int64_t* row_off, const int32_t* prod_of, int nprod,
                               const int32_t* items, int64_t nitems, int wlog2_max, int nt,
-                              int short_seg, int64_t grid_cap, hipStream_t s);
+                              int short_seg, hipStream_t s);
 // Expand-sort-compress over the batch's rows of one class of N products.
 hipError_t launch_esc_num_b(int sr, const BatchDesc* descs, const int64_t* row_off, const int32_t* prod_of, int nprod, const int32_t* items,
-                            int64_t nitems, int N, int64_t grid_cap, hipStream_t s);
+                            int64_t nitems, int N, hipStream_t s);
 hipError_t launch_hash_num_b(int sr, const BatchDesc* descs, const int64_t* row_off, const int32_t* prod_of, int nprod,
                              const int32_t* items, int64_t nitems, int T, int nt, int short_seg,
-                             int64_t grid_cap, hipStream_t s);
+                             hipStream_t s);
 hipError_t launch_dense_num_b(int sr, const BatchDesc* descs, const int64_t* row_off, const int32_t* prod_of, int nprod,
                               const int32_t* items, int64_t nitems, int wlog2_max, int nt,
-                              int short_seg, int64_t grid_cap, hipStream_t s);
+                              int short_seg, hipStream_t s);
 // Segment lists of (row, panel) pieces.
 hipError_t launch_seg_count(const Operands& op, const int32_t* rows, int64_t nslots, int P,
                             const int32_t* pidx, const int32_t* wend, int64_t* cnt_out, hipStream_t s);
