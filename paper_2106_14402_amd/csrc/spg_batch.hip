@@ -43,20 +43,27 @@ __device__ __forceinline__ int find_segment(const int64_t* __restrict__ off, int
   return lo;
 }
 
+// Product of every global row: block b writes b over its product's rows
+// [off[b], off[b + 1]) (the row kernels' lookup, instead of a search per row).
+__global__ void kb_fill_prod(const int64_t* __restrict__ off, int32_t* __restrict__ prod) {
+  const int b = blockIdx.x;
+  for (int64_t r = off[b] + threadIdx.x; r < off[b + 1]; r += blockDim.x) prod[r] = b;
+}
+
 // Operand check of every product (the checks of k_validate, error bits into
 // *err): global slices [0, mtot) are the A slices, [mtot, mtot + ntot) the
 // B slices; each wave takes slices g = its index, + all waves, ... (a grid
 // of a few workgroups per compute unit, not one per slice).
 __global__ void kb_validate(const BatchDesc* __restrict__ d, const int64_t* __restrict__ row_off,
-                            const int64_t* __restrict__ brow_off, int nprod, int64_t mtot, int64_t ntot,
-                            int* err) {
+                            const int64_t* __restrict__ brow_off, const int32_t* __restrict__ prod_of,
+                            const int32_t* __restrict__ bprod_of, int64_t mtot, int64_t ntot, int* err) {
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t waves = static_cast<int64_t>(gridDim.x) * (blockDim.x / kWave);
   int e = 0;
   for (int64_t g = static_cast<int64_t>(blockIdx.x) * (blockDim.x / kWave) + (threadIdx.x >> 6);
        g < mtot + ntot; g += waves) {
     const bool is_a = g < mtot;
-    const int b = is_a ? find_segment(row_off, nprod, g) : find_segment(brow_off, nprod, g - mtot);
+    const int b = is_a ? prod_of[g] : bprod_of[g - mtot];
     const Operands& op = d[b].op;
     const int64_t s = is_a ? g - row_off[b] : g - mtot - brow_off[b];
     const int64_t nmajor = is_a ? op.m : op.n;
@@ -100,12 +107,11 @@ __global__ void kb_validate(const BatchDesc* __restrict__ d, const int64_t* __re
   if (lane == 0 && e) atomicOr(err, e);
 }
 
-// flops and product per global row, symbolic bin counts, zero nnz for empty
-// rows; a wave per row, rows strided over a grid of a few workgroups per
-// compute unit.
+// flops per global row, symbolic bin counts, zero nnz for empty rows; a
+// wave per row, rows strided over a grid of a few workgroups per compute unit.
 __global__ void kb_flops_bin(const BatchDesc* __restrict__ d, const int64_t* __restrict__ row_off,
                              int nprod, int64_t mtot, BinParams bp, int64_t* __restrict__ flops,
-                             int32_t* __restrict__ prod_of, unsigned long long* counts,
+                             const int32_t* __restrict__ prod_of, unsigned long long* counts,
                              unsigned long long* total) {
   __shared__ unsigned int lc[kNumBins];
   __shared__ unsigned long long ltot;
@@ -116,7 +122,7 @@ __global__ void kb_flops_bin(const BatchDesc* __restrict__ d, const int64_t* __r
   __syncthreads();
   const int64_t waves = static_cast<int64_t>(gridDim.x) * (blockDim.x / kWave);
   for (int64_t r = static_cast<int64_t>(blockIdx.x) * (blockDim.x / kWave) + (tid >> 6); r < mtot; r += waves) {
-    const int b = find_segment(row_off, nprod, r);
+    const int b = prod_of[r];
     const Operands& op = d[b].op;
     const int64_t i = r - row_off[b];
     int64_t f = 0;
@@ -127,7 +133,6 @@ __global__ void kb_flops_bin(const BatchDesc* __restrict__ d, const int64_t* __r
     f = wave_sum(f);
     if (lane == 0) {
       flops[r] = f;
-      prod_of[r] = b;  // the row kernels' product lookup
       if (f == 0) d[b].c_ptr[i + 1] = 0;
       atomicAdd(&lc[sym_bin(f, bp)], 1u);
       atomicAdd(&ltot, static_cast<unsigned long long>(f));
@@ -141,11 +146,11 @@ __global__ void kb_flops_bin(const BatchDesc* __restrict__ d, const int64_t* __r
 // Bin of global row r: mode 0 symbolic (by flops), mode 1 numeric (by nnz,
 // per semiring slot; nnz read from the scanned product offsets).
 __device__ __forceinline__ int batch_bin(int mode, const BatchDesc* __restrict__ d,
-                                         const int64_t* __restrict__ row_off, int nprod,
+                                         const int64_t* __restrict__ row_off, const int32_t* __restrict__ prod_of,
                                          const int32_t* __restrict__ slot_of, int64_t r,
                                          const int64_t* __restrict__ flops, BinParams bp) {
   if (mode == 0) return sym_bin(flops[r], bp);
-  const int b = find_segment(row_off, nprod, r);
+  const int b = prod_of[r];
   const int64_t i = r - row_off[b];
   const int64_t nz = d[b].c_ptr[i + 1] - d[b].c_ptr[i];
   const int c = num_bin(nz, flops[r], bp);
@@ -153,20 +158,20 @@ __device__ __forceinline__ int batch_bin(int mode, const BatchDesc* __restrict__
 }
 
 __global__ void kb_count(int mode, const BatchDesc* __restrict__ d, const int64_t* __restrict__ row_off,
-                         int nprod, const int32_t* __restrict__ slot_of, int64_t mtot,
+                         const int32_t* __restrict__ prod_of, const int32_t* __restrict__ slot_of, int64_t mtot,
                          const int64_t* __restrict__ flops, BinParams bp, unsigned long long* counts) {
   __shared__ unsigned int lc[kBatchBins];
   for (int t = threadIdx.x; t < kBatchBins; t += blockDim.x) lc[t] = 0;
   __syncthreads();
   const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (r < mtot) atomicAdd(&lc[batch_bin(mode, d, row_off, nprod, slot_of, r, flops, bp)], 1u);
+  if (r < mtot) atomicAdd(&lc[batch_bin(mode, d, row_off, prod_of, slot_of, r, flops, bp)], 1u);
   __syncthreads();
   for (int t = threadIdx.x; t < kBatchBins; t += blockDim.x)
     if (lc[t]) atomicAdd(&counts[t], static_cast<unsigned long long>(lc[t]));
 }
 
 __global__ void kb_scatter(int mode, const BatchDesc* __restrict__ d, const int64_t* __restrict__ row_off,
-                           int nprod, const int32_t* __restrict__ slot_of, int64_t mtot,
+                           const int32_t* __restrict__ prod_of, const int32_t* __restrict__ slot_of, int64_t mtot,
                            const int64_t* __restrict__ flops, BinParams bp,
                            const int64_t* __restrict__ offs, unsigned long long* cursors,
                            int32_t* __restrict__ items) {
@@ -178,7 +183,7 @@ __global__ void kb_scatter(int mode, const BatchDesc* __restrict__ d, const int6
   int bin = 0;
   unsigned int local = 0;
   if (r < mtot) {
-    bin = batch_bin(mode, d, row_off, nprod, slot_of, r, flops, bp);
+    bin = batch_bin(mode, d, row_off, prod_of, slot_of, r, flops, bp);
     if (bin > 0) local = atomicAdd(&lc[bin], 1u);
   }
   __syncthreads();
@@ -191,11 +196,11 @@ __global__ void kb_scatter(int mode, const BatchDesc* __restrict__ d, const int6
 // Panel index for every product that needs one (which: 0 symbolic, 1 numeric),
 // one wave per global B row.
 __global__ void kb_panel_index(const BatchDesc* __restrict__ d, const int64_t* __restrict__ brow_off,
-                               int nprod, int64_t ntot, int which) {
+                               const int32_t* __restrict__ bprod_of, int64_t ntot, int which) {
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t g = static_cast<int64_t>(blockIdx.x) * (blockDim.x / kWave) + (threadIdx.x >> 6);
   if (g >= ntot) return;
-  const int b = find_segment(brow_off, nprod, g);
+  const int b = bprod_of[g];
   const BatchDesc& db = d[b];
   const int P = which == 0 ? db.sym_P : db.num_P;
   if (P <= 1) return;
@@ -254,7 +259,7 @@ struct spg_batch_plan {
   int64_t mtot, ntot, pool_len;
   int sym_wlog2_max, num_wlog2_max[kMaxSlots];
   int64_t grid_cap_per_thread;  // resident threads of the device
-  size_t off_desc, off_rowoff, off_browoff, off_pooloff, off_slot, off_ctr, off_flops, off_prod, off_items_sym,
+  size_t off_desc, off_rowoff, off_browoff, off_pooloff, off_slot, off_ctr, off_flops, off_prod, off_bprod, off_items_sym,
       off_items_num, off_scan, off_bases, off_offs, off_psym, off_pnum, ws_bytes;
   int state;
   int64_t flops_total;
@@ -329,10 +334,11 @@ spg_status enqueue_numeric(spg_batch_plan* p, unsigned char* w) {
   auto* brow_off = reinterpret_cast<const int64_t*>(w + p->off_browoff);
   auto* items = reinterpret_cast<const int32_t*>(w + p->off_items_num);
   auto* prod_of = reinterpret_cast<const int32_t*>(w + p->off_prod);
+  auto* bprod_of = reinterpret_cast<const int32_t*>(w + p->off_bprod);  // filled by the symbolic call
   bool any_panels = false;
   for (const auto& x : p->desc) any_panels = any_panels || x.num_P > 1;
   if (any_panels && p->ntot > 0)
-    hipLaunchKernelGGL(kb_panel_index, dim3(blocks(p->ntot, 4)), dim3(256), 0, s, d, brow_off, p->nprod,
+    hipLaunchKernelGGL(kb_panel_index, dim3(blocks(p->ntot, 4)), dim3(256), 0, s, d, brow_off, bprod_of,
                        p->ntot, 1);
   const std::vector<int64_t> no = offsets_of(p->num_counts, kBatchBins);
   const int nslots = static_cast<int>(p->slot_sr.size());
@@ -545,6 +551,7 @@ spg_status spg_batch_plan_create(int nprod, const spg_matrix* A, const spg_matri
   p->off_ctr = take(sizeof(uint64_t) * kCtrWords);
   p->off_flops = take(sizeof(int64_t) * p->mtot);
   p->off_prod = take(sizeof(int32_t) * p->mtot);
+  p->off_bprod = take(sizeof(int32_t) * p->ntot);
   p->off_items_sym = take(sizeof(int32_t) * p->mtot);
   p->off_items_num = take(sizeof(int32_t) * p->mtot);
   p->off_scan = take(sizeof(int64_t) * ((p->pool_len + kScanTile - 1) / kScanTile + 1));
@@ -621,11 +628,16 @@ spg_status spg_batch_symbolic(spg_batch_plan* p, void* ws, int64_t* c_ptr_pool, 
     SPG_TRY_HIP(hipMemcpyAsync(slot_of, p->h_slots.data(), sizeof(int32_t) * nprod, hipMemcpyHostToDevice, s));
   }
   SPG_TRY_HIP(launch_fill_u64(reinterpret_cast<uint64_t*>(ctr), kCtrWords, 0, s));
+  auto* bprod_of = reinterpret_cast<int32_t*>(w + p->off_bprod);
+  if (nprod > 0) {
+    hipLaunchKernelGGL(kb_fill_prod, dim3(nprod), dim3(256), 0, s, row_off, prod_of);
+    hipLaunchKernelGGL(kb_fill_prod, dim3(nprod), dim3(256), 0, s, brow_off, bprod_of);
+  }
   // Operand check of every product before any kernel indexes with their ids.
   if (p->mtot + p->ntot > 0) {
     int* err = reinterpret_cast<int*>(ctr + kCtrMisc + 1);
     hipLaunchKernelGGL(kb_validate, dim3(std::min<int64_t>(blocks(p->mtot + p->ntot, 4), prep_grid(p))), dim3(256),
-                       0, s, d, row_off, brow_off, nprod, p->mtot, p->ntot, err);
+                       0, s, d, row_off, brow_off, prod_of, bprod_of, p->mtot, p->ntot, err);
     int herr = 0;
     SPG_TRY_HIP(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, s));
     SPG_TRY_HIP(hipStreamSynchronize(s));
@@ -646,12 +658,12 @@ spg_status spg_batch_symbolic(spg_batch_plan* p, void* ws, int64_t* c_ptr_pool, 
     std::copy(so.begin(), so.end(), p->h_offs_sym.begin());
     SPG_TRY_HIP(hipMemcpyAsync(offs, p->h_offs_sym.data(), sizeof(int64_t) * kBatchBins, hipMemcpyHostToDevice, s));
     if (p->mtot > 0)
-      hipLaunchKernelGGL(kb_scatter, dim3(blocks(p->mtot, 256)), dim3(256), 0, s, 0, d, row_off, nprod,
+      hipLaunchKernelGGL(kb_scatter, dim3(blocks(p->mtot, 256)), dim3(256), 0, s, 0, d, row_off, prod_of,
                          slot_of, p->mtot, flops, p->bp, offs, ctr + kCtrCursor, items_sym);
     bool any_panels = false;
     for (const auto& x : p->desc) any_panels = any_panels || x.sym_P > 1;
     if (any_panels && p->ntot > 0)
-      hipLaunchKernelGGL(kb_panel_index, dim3(blocks(p->ntot, 4)), dim3(256), 0, s, d, brow_off, nprod,
+      hipLaunchKernelGGL(kb_panel_index, dim3(blocks(p->ntot, 4)), dim3(256), 0, s, d, brow_off, bprod_of,
                          p->ntot, 0);
     {
       BatchPhaseTimer t(p, SPG_BATCH_PHASE_SYM_HASH);
@@ -682,7 +694,7 @@ spg_status spg_batch_symbolic(spg_batch_plan* p, void* ws, int64_t* c_ptr_pool, 
                        p->pool_len, bases, c_ptr_pool);
   }
   if (p->mtot > 0)
-    hipLaunchKernelGGL(kb_count, dim3(blocks(p->mtot, 256)), dim3(256), 0, s, 1, d, row_off, nprod, slot_of,
+    hipLaunchKernelGGL(kb_count, dim3(blocks(p->mtot, 256)), dim3(256), 0, s, 1, d, row_off, prod_of, slot_of,
                        p->mtot, flops, p->bp, ctr + kCtrNum);
   p->bases.assign(nprod + 1, 0);
   if (nprod > 0)
@@ -694,7 +706,7 @@ spg_status spg_batch_symbolic(spg_batch_plan* p, void* ws, int64_t* c_ptr_pool, 
     SPG_TRY_HIP(hipMemcpyAsync(offs, p->h_offs_num.data(), sizeof(int64_t) * kBatchBins, hipMemcpyHostToDevice, s));
     SPG_TRY_HIP(launch_fill_u64(reinterpret_cast<uint64_t*>(ctr + kCtrCursor), kBatchBins, 0, s));
     if (p->mtot > 0)
-      hipLaunchKernelGGL(kb_scatter, dim3(blocks(p->mtot, 256)), dim3(256), 0, s, 1, d, row_off, nprod,
+      hipLaunchKernelGGL(kb_scatter, dim3(blocks(p->mtot, 256)), dim3(256), 0, s, 1, d, row_off, prod_of,
                          slot_of, p->mtot, flops, p->bp, offs, ctr + kCtrCursor, items_num);
     SPG_TRY_HIP(hipStreamSynchronize(s));
   }
