@@ -605,6 +605,11 @@ def run_mcl(args):
     phase = {k: v for k, v in p.timings().items()}
     rownnz = torch.diff(p.c_ptr).cpu().numpy()
 
+    def expansion():  # the product alone, without the prune
+        p.symbolic(p.c_ptr)
+        p.numeric(c_idx, c_val)
+    ms_exp = timed(expansion, args.steps, 1)
+
     def iteration():  # the whole Markov-clustering iteration: expansion, prune, selection, inflation (r = 2)
         step()
         state["Q"] = S.select_f32(state["P"], args.select)
@@ -617,6 +622,7 @@ def run_mcl(args):
                        "select": args.select, "nnz_selected": state["Q"].nnz})
     out["roofline"] = roofline_record(dominant_kernel(A, phase, rownnz, p, 4, 4, "plus_times_f32"), "mcl")
     out["phase_ms"] = {k: round(v, 3) for k, v in phase.items() if v > 0}
+    out["expansion_ms"] = round(ms_exp, 3)
     out["iteration_ms"] = round(ms_it, 3)
     if args.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline_generic(A, "plus_times_f32", args.cpu_seconds)
