@@ -1020,9 +1020,11 @@ __device__ __forceinline__ void wave_sync() {
 // words at a time, the lanes put the column ids of their words in order into
 // the wave's LDS staging area, at the same offset modulo 4 as their place in
 // c_idx, and the wave writes the staged ids out with consecutive lanes on
-// consecutive 16-byte groups (single ids at the unaligned ends).
+// consecutive 16-byte groups (single ids at the unaligned ends).  Two-wave
+// workgroups (17 KiB of LDS) keep many rows in flight on a CU, so that the
+// load, scan and store steps of different rows overlap.
 constexpr int kExpandWords = 16;
-constexpr int kExpandThreads = 1024;
+constexpr int kExpandThreads = 128;
 constexpr int kExpandStage = kWave * 32 + 4;  // ids of 64 words, plus the alignment offset
 
 __global__ __launch_bounds__(kExpandThreads) void k_expand_rows(const int32_t* __restrict__ rows, int64_t nrows,
