@@ -2889,10 +2889,11 @@ hipError_t launch_inflate(const int64_t* ptr, const float* val, int64_t nmajor, 
 // column, paper Sec. 7.5): a slice longer than S keeps the S entries with the
 // largest values, ties going to the smaller id, in id order.  The order is
 // that of the 64-bit key (total-order key of the float32 value, -0 < +0) << 32
-// | (2^32 - 1 - id), unique within a slice.  The S-th largest key is found by
-// a radix select (eight passes of 8 bits over the slice, a histogram in LDS,
-// one workgroup per slice); the entries whose key is at least that large are
-// exactly the S kept ones, placed in order by a block scan of keep flags.
+// | (2^32 - 1 - id), unique within a slice.  A radix select (at most eight
+// passes of 8 bits from the top over the slice, a histogram in LDS, one
+// workgroup per slice) finds a threshold that exactly S keys reach: the S-th
+// largest key, or its leading digits alone once every key sharing them is
+// kept; those S entries are placed in order by a block scan of keep flags.
 // ---------------------------------------------------------------------------
 __global__ void k_select_count(const int64_t* __restrict__ ptr, int64_t nmajor, int64_t S,
                                int64_t* __restrict__ cnt) {
@@ -2915,6 +2916,7 @@ __global__ __launch_bounds__(kSelectThreads) void k_select_apply(const int64_t* 
   __shared__ unsigned int hist[256];
   __shared__ uint64_t prefix_s;
   __shared__ int64_t need_s;
+  __shared__ int done_s;
   __shared__ int64_t tmp[16];
   const int tid = threadIdx.x, nt = blockDim.x, lane = tid & (kWave - 1);
   for (int64_t s = blockIdx.x; s < nmajor; s += gridDim.x) {
@@ -2961,12 +2963,17 @@ __global__ __launch_bounds__(kSelectThreads) void k_select_apply(const int64_t* 
           }
           prefix_s = prefix | (static_cast<uint64_t>(d) << shift);
           need_s = need - acc;
+          // every key of digit d is kept: the keys >= prefix_s (lower bits
+          // zero) are then exactly the S largest, and the search ends
+          done_s = hist[d] == need - acc ? 1 : 0;
         }
       }
       __syncthreads();
       prefix = prefix_s;
       need = need_s;
-      __syncthreads();  // prefix_s and hist are rewritten by the next pass
+      const bool done = done_s != 0;
+      __syncthreads();  // prefix_s, done_s and hist are rewritten by the next pass
+      if (done) break;
     }
     // the S keys >= prefix, in slice order
     int64_t base = out;
