@@ -423,8 +423,8 @@ spg_status spg_select_apply_f32(const spg_matrix* C, int64_t S, void* ws, void* 
  *   r        inflation exponent, > 0
  *   val_out  device float[nnz]: the new values in C's entry order; may be
  *            C->val itself (in place).  Slices whose powers sum to 0 are left
- *            as they are (copied to val_out).  Powers in float32, their sum
- *            in float64.
+ *            as they are (copied to val_out).  Powers in float32 (for
+ *            r = 2 the single product v * v), their sum in float64.
  * Enqueues one kernel on `stream` and returns.
  * Errors: SPG_E_INVALID for r <= 0 or missing values. */
 spg_status spg_inflate_f32(const spg_matrix* C, float r, float* val_out, void* stream);
