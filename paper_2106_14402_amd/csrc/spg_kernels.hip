@@ -3030,7 +3030,10 @@ hipError_t launch_prune_apply(const int64_t* ptr, const int32_t* idx, const floa
                               int32_t* new_idx, float* new_val, hipStream_t s) {
   if (nmajor <= 0) return hipSuccess;
   const int nt = 256;
-  const int64_t nb = std::min<int64_t>((nmajor + nt / kWave - 1) / (nt / kWave), prep_blocks());
+  // one wave per slice (up to 2^24 slices; the kernel strides beyond): the
+  // dispatcher balances the uneven slices better than a grid of a few
+  // workgroups per CU striding over them
+  const int64_t nb = std::min<int64_t>((nmajor + nt / kWave - 1) / (nt / kWave), int64_t(1) << 22);
   hipLaunchKernelGGL(k_prune_apply, dim3(static_cast<unsigned>(nb)), dim3(nt), 0, s, ptr, idx, val,
                      nmajor, thresh, new_ptr, new_idx, new_val);
   return hipGetLastError();
