@@ -56,6 +56,17 @@ static int64_t prep_blocks() {
   return static_cast<int64_t>(ncu) * 8;
 }
 
+// Workgroups for the prune and inflation kernels, one wave per slice: one
+// workgroup per group of slices, up to 2^22 (the kernels stride beyond).  The
+// dispatcher balances their uneven slices better than a grid of a few
+// workgroups per CU striding over them (prune placement 7.9 -> 6.8 ms, count
+// 2.0 -> 1.7, inflation 1.9 -> 1.5 on the MCL matrix).  The operand checks
+// measured slower that way, and the flop count reduces into global counters
+// per workgroup: both keep the small grid of prep_blocks().
+static int64_t wave_grid(int64_t slices, int nt) {
+  return std::min<int64_t>((slices + nt / kWave - 1) / (nt / kWave), int64_t(1) << 22);
+}
+
 // Operand check: ptr[0] == 0, ptr non-decreasing within [0, nnz],
 // ptr[nmajor] == nnz, ids in [0, nminor), and the order of the ids of each
 // slice.  Error bits (kCheck*): bad endpoints, bad offsets, an id out of
@@ -2879,7 +2890,7 @@ hipError_t launch_inflate(const int64_t* ptr, const float* val, int64_t nmajor, 
                           hipStream_t s) {
   if (nmajor <= 0) return hipSuccess;
   const int nt = 256;
-  const int64_t nb = std::min<int64_t>((nmajor + nt / kWave - 1) / (nt / kWave), prep_blocks());
+  const int64_t nb = wave_grid(nmajor, nt);
   hipLaunchKernelGGL(k_inflate, dim3(static_cast<unsigned>(nb)), dim3(nt), 0, s, ptr, val, nmajor, r, val_out);
   return hipGetLastError();
 }
@@ -3019,7 +3030,7 @@ hipError_t launch_prune_count(const int64_t* ptr, const float* val, int64_t nmaj
                               int64_t* new_ptr, hipStream_t s) {
   if (nmajor <= 0) return hipSuccess;
   const int nt = 256;
-  const int64_t nb = std::min<int64_t>((nmajor + nt / kWave - 1) / (nt / kWave), prep_blocks());
+  const int64_t nb = wave_grid(nmajor, nt);
   hipLaunchKernelGGL(k_prune_count, dim3(static_cast<unsigned>(nb)), dim3(nt), 0, s, ptr, val,
                      nmajor, thresh, new_ptr + 1);
   return hipGetLastError();
@@ -3030,10 +3041,7 @@ hipError_t launch_prune_apply(const int64_t* ptr, const int32_t* idx, const floa
                               int32_t* new_idx, float* new_val, hipStream_t s) {
   if (nmajor <= 0) return hipSuccess;
   const int nt = 256;
-  // one wave per slice (up to 2^24 slices; the kernel strides beyond): the
-  // dispatcher balances the uneven slices better than a grid of a few
-  // workgroups per CU striding over them
-  const int64_t nb = std::min<int64_t>((nmajor + nt / kWave - 1) / (nt / kWave), int64_t(1) << 22);
+  const int64_t nb = wave_grid(nmajor, nt);
   hipLaunchKernelGGL(k_prune_apply, dim3(static_cast<unsigned>(nb)), dim3(nt), 0, s, ptr, idx, val,
                      nmajor, thresh, new_ptr, new_idx, new_val);
   return hipGetLastError();
